@@ -1,0 +1,115 @@
+/*
+ * CPU oracle for event-based Monte Carlo transport -- TEST INFRASTRUCTURE.
+ *
+ * This is the plain, slow, history-based definition of what the transport
+ * hot path computes.  Thread-data remapping (paper Sec. 2) only reorders
+ * independent histories and the events inside them; it never changes what
+ * a history computes.  So the result of every scheduler (naive, stack-based,
+ * asynchronous, batched) must equal the loop
+ *
+ *     for each history h: run h to completion, add each fixed-point
+ *                         track-length contribution into an int64 tally
+ *
+ * which is what this file implements, one history at a time.
+ *
+ * Only the tests, the package smoke check and the benchmark's CPU baseline
+ * may load this library.  It shares no code, header, table or constant with
+ * the GPU library.
+ *
+ * "parity unpinned" against the paper itself: the paper prints no worked
+ * example or table of values for this workload; pins are closed forms,
+ * library routines and brute force (see tests/test_oracle_*.py).
+ */
+#ifndef MCX_ORACLE_H
+#define MCX_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    int32_t geometry;          /* 0 box of x-slabs, 1 pin lattice            */
+    double box_lo[3], box_hi[3];
+    int32_t bc[6];             /* x-,x+,y-,y+,z-,z+ : 0 vacuum, 1 reflective */
+    int32_t n_slabs;           /* box: slab planes [n_slabs+1], materials    */
+    const double *slab_planes;
+    const int32_t *slab_mat;
+    int32_t nx, ny;            /* lattice                                    */
+    const double *xplanes, *yplanes, *cx, *cy;
+    double radius;
+    const int32_t *pin_mat;
+    int32_t mod_mat;
+    int32_t energy_mode;       /* 0 multigroup, 1 continuous energy          */
+    int32_t n_mat, n_grp;
+    const double *sigma_t, *sigma_s, *cdf;   /* [M*G], [M*G], [M*G*G]        */
+    int32_t n_species, grid_len;
+    const double *e_grid, *sig_a, *sig_s;    /* [S*grid_len]                 */
+    const double *awr, *density;             /* [S], [M*S]                   */
+    double e_min, e_source;
+    int32_t src_kind;          /* 0 point, 1 box volume, 2 disc              */
+    int32_t src_isotropic;
+    int32_t src_group;
+    int32_t tally_kind;        /* 0 mesh, 1 energy bins                      */
+    double src_pos[3], src_lo[3], src_hi[3], src_dir[3];
+    double src_radius;
+    int32_t mesh_n[3];
+    const double *mesh_x, *mesh_y, *mesh_z;
+    int32_t n_ebins;
+    const double *e_edges;
+    int32_t tally_scale_log2;
+    uint32_t problem_id;
+    uint64_t seed;
+    int64_t max_steps;
+} orc_problem;
+
+/* what a history ended with */
+enum { ORC_FATE_LEAK = 0, ORC_FATE_ABSORB = 1, ORC_FATE_CUTOFF = 2, ORC_FATE_KILLED = 3 };
+
+typedef struct {              /* one record per history                    */
+    int64_t qsum;             /* sum of its fixed-point tally contributions */
+    uint32_t flights;
+    uint32_t collisions;
+    uint32_t fate;
+    uint32_t pad;
+} orc_digest;
+
+typedef struct {              /* totals over a run (scheduler invariant)   */
+    uint64_t sourced, flights, collisions, scatters, absorbs, crossings;
+    uint64_t leaks, reflections, cutoffs, killed, pieces, qsum;
+    uint64_t overflow;        /* 1 if the total of all q reached 2^63       */
+} orc_counts;
+
+/* primitives, exposed for tests */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+double orc_uniform(uint64_t seed, uint32_t problem_id, uint32_t particle, uint32_t step,
+                   uint32_t slot, uint32_t stream);
+double orc_nlog(double x);
+double orc_sqrt(double x);
+void orc_cos_sin_turn(double t, double *c, double *s);
+int64_t orc_fixed(double x, int32_t scale_log2);
+
+/* geometry hooks for tests: distance to the next surface from a located state */
+int32_t orc_locate(const orc_problem *p, const double pos[3], const double dir[3], int32_t cell[3]);
+double orc_distance(const orc_problem *p, const double pos[3], const double dir[3],
+                    const int32_t cell[3], int32_t *surface);
+int32_t orc_ce_index(const double *grid, int32_t n, double e);        /* linear scan  */
+int32_t orc_ce_index_fast(const double *grid, int32_t n, double e);   /* bisection    */
+int32_t orc_edge_index(const double *edges, int32_t n, double x, double dir, int32_t fast);
+
+double orc_elastic(double A, double e, double xi_mu, double xi_phi, double dir[3]);
+void orc_tally_segment(const orc_problem *p, const double pos[3], const double dir[3], double d,
+                       int32_t g, double *out);
+double orc_ce_xs_hook(const orc_problem *p, int32_t m, double e, double *sa, double *ss);
+
+/* forward: histories [h0, h1) added into tally; digest (optional) indexed h-h0 */
+int orc_run(const orc_problem *p, uint64_t h0, uint64_t h1, int64_t *tally,
+            orc_digest *digest, orc_counts *counts);
+
+/* score-function backward, pass A: G_h = sum over tally pieces of w[bin]*len,
+   with L_h (track length) and n_h (flights); U += ceil(|G_h| * (L_h + n_h)) */
+int orc_replay_a(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w,
+                 double *G, uint64_t *U);
+
+/* pass B at scale 2^s: SL[m*G+g] += q(G_h*len) per flight, SA per absorption,
+   SS per scatter, with q(x) = rint(x * 2^s) */
+int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *G, int32_t s,
+                 int64_t *SL, int64_t *SA, int64_t *SS);
+
+#endif
