@@ -1,0 +1,240 @@
+/*
+ * mcx -- event-based Monte Carlo particle transport with thread-data
+ * remapping (TDR) on AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The transport method: independent particle histories (source, flights,
+ * collisions, surface crossings, track-length tallies) processed as events.
+ * Thread-data remapping (Sec. 2 of the paper) regroups particles between
+ * events so that the lanes of a wavefront run the same event; it reorders
+ * work but never changes what a history computes.  Three schedulers run the
+ * same events:
+ *   MCX_SCHED_NAIVE  one lane runs one whole history (the history-based
+ *                    baseline the remapping methods are measured against);
+ *   MCX_SCHED_STACK  stack-based remapping (Sec. 3.1): one global input and
+ *                    one global output stack per event type, wavefront-
+ *                    aggregated push/pop, on-demand source ("make_work")
+ *                    only once all input stacks are drained and only until
+ *                    the fullest output stack passes a threshold; one kernel
+ *                    launch per remapping round;
+ *   MCX_SCHED_ASYNC  asynchronous remapping (Sec. 3.2): one persistent
+ *                    launch; each wavefront keeps a stash of work links
+ *                    (64-particle arrays of one event type) in LDS, spills
+ *                    to and refills from a global link arena through
+ *                    lock-free queues, with no inter-block synchronisation.
+ * Event decomposition (Sec. 4): MCX_DECOMP_FUSED is the monolithic "step"
+ * event (one transport segment); MCX_DECOMP_SPLIT uses separate lookup,
+ * move(+tally), surface-crossing and collision events.
+ *
+ * Results are exact integers: tallies are int64 fixed point (track length
+ * times 2^tally_scale_log2, round half to even) and every scheduler, event
+ * decomposition, lookup method and launch shape yields the same integers.
+ *
+ * Conventions
+ *  - Every call returns mcx_status; nothing throws across the ABI.
+ *  - "where" arguments: MCX_HOST (pointer is host memory) or MCX_DEVICE
+ *    (pointer is device memory on the problem's device).
+ *  - Calls on one handle are not thread-safe; distinct handles are.
+ *  - Device memory passed in (tallies out, digests, dL/dT, gradients) is
+ *    owned by the caller; the library never frees caller memory.
+ *  - On MCX_E_CAPACITY or MCX_E_OVERFLOW the run's tallies are invalid and
+ *    reading them returns MCX_E_STATE until the next successful run.
+ */
+#ifndef MCX_H
+#define MCX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mcx_problem_s *mcx_problem_t;
+
+typedef enum {
+    MCX_OK = 0,
+    MCX_E_INVALID_ARG = 1,   /* bad descriptor, option or pointer            */
+    MCX_E_OOM = 2,           /* device allocation failed                     */
+    MCX_E_DEVICE = 3,        /* HIP runtime error (see mcx_last_error)       */
+    MCX_E_CAPACITY = 4,      /* stack / link arena capacity exhausted        */
+    MCX_E_OVERFLOW = 5,      /* fixed-point total reached 2^63               */
+    MCX_E_STATE = 6          /* call not valid in the handle's state         */
+} mcx_status;
+
+enum { MCX_HOST = 0, MCX_DEVICE = 1 };
+enum { MCX_GEOM_BOX = 0, MCX_GEOM_LATTICE = 1 };
+enum { MCX_MG = 0, MCX_CE = 1 };
+enum { MCX_BC_VACUUM = 0, MCX_BC_REFLECT = 1 };
+enum { MCX_SRC_POINT = 0, MCX_SRC_BOX = 1, MCX_SRC_DISC = 2 };
+enum { MCX_TALLY_MESH = 0, MCX_TALLY_ENERGY = 1 };
+typedef enum { MCX_SCHED_NAIVE = 0, MCX_SCHED_STACK = 1, MCX_SCHED_ASYNC = 2 } mcx_sched;
+typedef enum { MCX_DECOMP_FUSED = 0, MCX_DECOMP_SPLIT = 1 } mcx_decomp;
+typedef enum { MCX_LOOKUP_BINARY = 0, MCX_LOOKUP_HASH = 1 } mcx_lookup;
+enum { MCX_FATE_LEAK = 0, MCX_FATE_ABSORB = 1, MCX_FATE_CUTOFF = 2, MCX_FATE_KILLED = 3 };
+
+/* One fixed-source problem.  All arrays are host memory; mcx_create_problem
+ * deep-copies them, so the caller may free them afterwards.
+ *
+ * Geometry (all coordinates in cm):
+ *  BOX      box [box_lo, box_hi] cut by x-planes slab_planes[0..n_slabs]
+ *           (slab_planes[0] = box_lo[0], slab_planes[n_slabs] = box_hi[0]);
+ *           slab i has material slab_mat[i].
+ *  LATTICE  nx*ny rectangular cells bounded by xplanes[0..nx], yplanes[0..ny]
+ *           (outer planes = box faces), z in [box_lo[2], box_hi[2]] (may be
+ *           +-inf); cell (i,j) holds a full-height cylinder of radius
+ *           `radius` centred (cx[i], cy[j]) of material pin_mat[j*nx+i];
+ *           the rest is material mod_mat.
+ *  bc[6]    boundary condition of faces x-, x+, y-, y+, z-, z+.
+ * Physics:
+ *  MG       sigma_t, sigma_s [n_mat*n_grp] (1/cm), transfer_cdf
+ *           [n_mat*n_grp*n_grp]: cumulative outgoing-group probabilities per
+ *           (material, incoming group); the last entry of a row is 1.0.
+ *  CE       n_species pointwise tables on sorted grids e_grid[s*grid_len..],
+ *           sig_a, sig_s (same layout), target mass ratios awr[s], number
+ *           densities density[m*n_species+s]; histories end below e_min;
+ *           source energy e_source.  hash_bins > 0 sizes the hashed-grid
+ *           index (uniform in ln E); 0 picks a default.
+ * Source (sampled per history from its own random numbers):
+ *  POINT at src_pos; BOX uniform in [src_lo, src_hi]; DISC uniform in the
+ *  disc of radius src_radius about (src_pos x, y) at z = src_pos z.
+ *  Direction isotropic if src_isotropic, else src_dir.  Group src_group
+ *  (MG) or energy e_source (CE).
+ * Tally: MESH track length on the tensor mesh mesh_x/y/z (edges, mesh_n[a]+1
+ *  each), bins [g][iz][iy][ix]; ENERGY track length per flight into the bin
+ *  [e_edges[k], e_edges[k+1]) holding the particle energy.  Raw values are
+ *  int64 sum of rint(length * 2^tally_scale_log2).
+ * Random numbers: Philox4x32-10 keyed by (seed, problem_id), indexed by
+ *  (history, flight, slot); identical on every scheduler.
+ */
+typedef struct {
+    int32_t geometry;
+    double box_lo[3], box_hi[3];
+    int32_t bc[6];
+    int32_t n_slabs;
+    const double *slab_planes;
+    const int32_t *slab_mat;
+    int32_t nx, ny;
+    const double *xplanes, *yplanes, *cx, *cy;
+    double radius;
+    const int32_t *pin_mat;
+    int32_t mod_mat;
+    int32_t energy_mode;
+    int32_t n_mat, n_grp;
+    const double *sigma_t, *sigma_s, *transfer_cdf;
+    int32_t n_species, grid_len;
+    const double *e_grid, *sig_a, *sig_s, *awr, *density;
+    double e_min, e_source;
+    int32_t hash_bins;
+    int32_t src_kind, src_isotropic, src_group;
+    double src_pos[3], src_lo[3], src_hi[3], src_dir[3];
+    double src_radius;
+    int32_t tally_kind;
+    int32_t mesh_n[3];
+    const double *mesh_x, *mesh_y, *mesh_z;
+    int32_t n_ebins;
+    const double *e_edges;
+    int32_t tally_scale_log2;
+    uint32_t problem_id;
+    uint64_t seed;
+    uint64_t n_histories;
+    int64_t max_steps;
+} mcx_problem_desc;
+
+/* Options of one run.  Zero-initialise and set what you need; zero means the
+ * default for every tuning field.  Tuning fields never change results. */
+typedef struct {
+    int32_t sched;            /* mcx_sched                                      */
+    int32_t decomp;           /* mcx_decomp                                     */
+    int32_t lookup;           /* mcx_lookup (continuous energy)                 */
+    int32_t accumulate;       /* 0: zero the tallies first; 1: add into them    */
+    uint64_t first_history;   /* single-problem handles: run histories          */
+    uint64_t n_histories;     /*   [first, first+n); n = 0 means all            */
+    int64_t stack_capacity;   /* stack: particles per event stack               */
+    int64_t stack_threshold;  /* stack: make_work stops above this fill         */
+    int32_t stash_links;      /* async: work links per wavefront stash          */
+    int32_t arena_links;      /* async: links in the global arena               */
+    int32_t waves_per_cu;     /* stack/async: resident wavefronts per CU        */
+    int32_t block_size;       /* naive: threads per block                       */
+    void *hip_stream;         /* hipStream_t; NULL = the default stream         */
+    void *digest;             /* optional device array of mcx_digest, one per
+                                 history (all problems, in order)               */
+    int32_t time_kernels;     /* 1: time every launch with HIP events           */
+    int32_t reserved[7];
+} mcx_run_opts;
+
+/* one record per history, written by runs that pass opts.digest */
+typedef struct {
+    int64_t qsum;             /* sum of the history's tally contributions       */
+    uint32_t flights;
+    uint32_t collisions;
+    uint32_t fate;            /* MCX_FATE_*                                     */
+    uint32_t pad;
+} mcx_digest;
+
+/* totals of the last run (forward or backward pass) */
+typedef struct {
+    uint64_t sourced, flights, collisions, scatters, absorbs, crossings;
+    uint64_t leaks, reflections, cutoffs, killed, pieces, qsum;
+    uint64_t overflow;        /* 1 if the total of all contributions hit 2^63   */
+    uint64_t events;          /* event executions (per particle)                */
+    uint64_t lane_slots;      /* 64 x wavefront event dispatches                */
+    uint64_t dispatches;      /* wavefront event dispatches                     */
+    uint64_t spills, refills; /* async: links moved to / from the global arena  */
+    uint64_t make_work;       /* wavefront source calls                         */
+    uint64_t rounds;          /* stack: kernel launches (remapping rounds)      */
+    uint64_t launches;        /* kernel launches of the run                     */
+    double kernel_ms;         /* summed launch durations (time_kernels = 1)     */
+    int32_t grid_blocks;      /* blocks of the main launch                      */
+    int32_t block_threads;    /* threads per block of the main launch           */
+    int32_t lds_bytes;        /* dynamic LDS per block of the main launch       */
+    int32_t pad;
+} mcx_counters_t;
+
+/* Create a handle for n_problems independent problems (a batch runs all of
+ * them in one launch).  All problems of a batch must share geometry kind,
+ * energy mode and tally kind.  Invalid descriptors are rejected with no side
+ * effect.  Uses the current HIP device. */
+mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t n_problems, mcx_problem_t *out);
+
+/* Replace the multigroup Sigma_t, Sigma_s [n_mat*n_grp] of one problem
+ * (transfer probabilities stay).  Both must satisfy 0 <= Sigma_s <= Sigma_t,
+ * Sigma_t > 0. */
+mcx_status mcx_set_xs(mcx_problem_t p, int32_t problem, const double *sigma_t, const double *sigma_s,
+                      int32_t where);
+
+/* Run histories through the selected scheduler (forward transport with
+ * tallies).  Synchronises the run's stream before returning. */
+mcx_status mcx_run(mcx_problem_t p, const mcx_run_opts *opts);
+
+/* Copy problem `problem`'s raw int64 tally (n = its bin count) to out. */
+mcx_status mcx_tallies(mcx_problem_t p, int32_t problem, int64_t *out, int64_t n, int32_t where);
+
+/* Score-function (likelihood-ratio) backward of the last forward run: for
+ * T_b = raw_b 2^-S / N (per problem, N = histories run), given dL/dT_b,
+ * returns grad Sigma_t and grad Sigma_s [n_mat*n_grp] of
+ * sum_b dL/dT_b dE[T_b]/d theta, estimated by replaying every history from
+ * its random-number keys twice (pass A: G_h = sum over the history's tally
+ * pieces of dL/dT_bin * length; pass B: G_h times track length, absorptions
+ * and scatters per (material, group), in int64 fixed point at an adaptive
+ * power-of-two scale).  problem = -1 covers all problems of a batch:
+ * dL_dT is then the concatenation of every problem's bins and the gradients
+ * the concatenation of every problem's n_mat*n_grp entries.  Multigroup only.
+ * opts selects the scheduler and tuning for the replays (accumulate, range
+ * and digest fields are ignored). */
+mcx_status mcx_backward(mcx_problem_t p, int32_t problem, const double *dL_dT, double *grad_sigma_t,
+                        double *grad_sigma_s, int32_t where, const mcx_run_opts *opts);
+
+mcx_status mcx_counters(mcx_problem_t p, mcx_counters_t *out);
+
+/* Sizes of problem `problem`: tally bins, materials, groups, histories. */
+mcx_status mcx_problem_info(mcx_problem_t p, int32_t problem, int64_t *n_bins, int32_t *n_mat, int32_t *n_grp,
+                            uint64_t *n_histories);
+
+void mcx_destroy_problem(mcx_problem_t p);
+const char *mcx_status_str(mcx_status s);
+const char *mcx_last_error(mcx_problem_t p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

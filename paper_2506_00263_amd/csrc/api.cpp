@@ -1,0 +1,778 @@
+// C ABI of the transport library: problem upload, validation, run
+// orchestration, tallies and the score-function backward (host side).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcx.h"
+#include "kernels.hpp"
+
+using namespace mcx;
+
+static_assert(sizeof(mcx_digest) == 24, "digest layout");
+
+namespace {
+
+// host copy of one problem's arrays, owned by the handle
+struct HostProblem {
+    mcx_problem_desc d;
+    std::vector<double> xpl, ypl, cxs, cys, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, mx, my, mz, eedges;
+    std::vector<int32_t> cmat, hash_lo, hash_hi;
+    double hash_ln_lo = 0.0, hash_inv = 0.0;
+    int32_t hash_bins = 0;
+    int64_t n_bins = 0;
+};
+
+}  // namespace
+
+struct mcx_problem_s {
+    int device = 0;
+    int num_cus = 256;
+    int n = 0;
+    int geom = 0, emode = 0, tally_kind = 0;
+    std::vector<HostProblem> hp;
+    std::vector<ProbDev> pd;              // host image of the device table
+    std::vector<size_t> tally_off;        // bin offset of each problem
+    size_t total_bins = 0;
+    // device memory
+    void *blob = nullptr;                 // static arrays of every problem
+    ProbDev *d_probs = nullptr;
+    unsigned long long *d_prefix = nullptr;
+    unsigned long long *d_tally = nullptr;
+    RunCtl *d_ctl = nullptr;
+    // backward buffers
+    double *d_G = nullptr;
+    size_t G_cap = 0;
+    double *d_w = nullptr;
+    size_t w_cap = 0;
+    unsigned long long *d_gacc = nullptr; // per problem: U, then SL, SA, SS
+    std::vector<size_t> gacc_off;
+    size_t gacc_words = 0;
+    unsigned int *h_flag = nullptr;       // pinned
+    Workspace ws;
+    // state
+    bool tallies_valid = false;
+    bool have_forward = false;
+    std::vector<uint64_t> last_first, last_count;
+    mcx_counters_t counters{};
+    std::string err;
+};
+
+static mcx_status fail(mcx_problem_t p, mcx_status s, const char *fmt, ...)
+{
+    if (p) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        p->err = buf;
+    }
+    return s;
+}
+
+static mcx_status hip_fail(mcx_problem_t p, hipError_t e, const char *where)
+{
+    return fail(p, e == hipErrorOutOfMemory ? MCX_E_OOM : MCX_E_DEVICE, "%s: %s", where, hipGetErrorString(e));
+}
+
+#define HIP_TRY(p, call)                                    \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hip_fail(p, e_, #call); \
+    } while (0)
+
+static bool sorted_strict(const double *a, int64_t n)
+{
+    for (int64_t i = 0; i + 1 < n; ++i)
+        if (!(a[i] < a[i + 1])) return false;
+    return true;
+}
+
+template <class T>
+static std::vector<T> copy_of(const T *a, int64_t n)
+{
+    return std::vector<T>(a, a + n);
+}
+
+static int bit_length(unsigned long long u)
+{
+    int b = 0;
+    while (u) {
+        ++b;
+        u >>= 1;
+    }
+    return b;
+}
+
+// largest i <= n-2 with g[i] <= e
+static int host_bracket(const double *g, int n, double e)
+{
+    int i = (int)(std::upper_bound(g, g + n, e) - g) - 1;
+    if (i < 0) i = 0;
+    if (i > n - 2) i = n - 2;
+    return i;
+}
+
+// Validate one descriptor and deep-copy its arrays.
+static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int k, HostProblem &hp)
+{
+    hp.d = d;
+    if (d.geometry != MCX_GEOM_BOX && d.geometry != MCX_GEOM_LATTICE)
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: bad geometry %d", k, d.geometry);
+    if (d.energy_mode != MCX_MG && d.energy_mode != MCX_CE)
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: bad energy_mode", k);
+    if (d.n_mat < 1) return fail(h, MCX_E_INVALID_ARG, "problem %d: n_mat < 1", k);
+    for (int f = 0; f < 6; ++f)
+        if (d.bc[f] != MCX_BC_VACUUM && d.bc[f] != MCX_BC_REFLECT)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: bad boundary condition", k);
+    for (int a = 0; a < 3; ++a)
+        if (!(d.box_lo[a] < d.box_hi[a])) return fail(h, MCX_E_INVALID_ARG, "problem %d: empty box", k);
+    if (d.geometry == MCX_GEOM_BOX) {
+        if (d.n_slabs < 1 || d.n_slabs > 1023 || !d.slab_planes || !d.slab_mat)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: n_slabs must be 1..1023", k);
+        hp.xpl = copy_of(d.slab_planes, d.n_slabs + 1);
+        if (!sorted_strict(hp.xpl.data(), d.n_slabs + 1) || hp.xpl[0] != d.box_lo[0] || hp.xpl[d.n_slabs] != d.box_hi[0])
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: slab planes must increase from box_lo.x to box_hi.x", k);
+        if (!std::isfinite(d.box_lo[1]) || !std::isfinite(d.box_hi[1]) || !std::isfinite(d.box_lo[2]) ||
+            !std::isfinite(d.box_hi[2]))
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: box faces must be finite", k);
+        hp.cmat = copy_of(d.slab_mat, d.n_slabs);
+        hp.ypl = {0.0};
+        hp.cxs = {0.0};
+        hp.cys = {0.0};
+    } else {
+        if (d.nx < 1 || d.ny < 1 || d.nx > 1023 || d.ny > 1023 || !d.xplanes || !d.yplanes || !d.cx || !d.cy ||
+            !d.pin_mat)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: lattice needs nx, ny in 1..1023 and its arrays", k);
+        hp.xpl = copy_of(d.xplanes, d.nx + 1);
+        hp.ypl = copy_of(d.yplanes, d.ny + 1);
+        if (!sorted_strict(hp.xpl.data(), d.nx + 1) || !sorted_strict(hp.ypl.data(), d.ny + 1) ||
+            hp.xpl[0] != d.box_lo[0] || hp.xpl[d.nx] != d.box_hi[0] || hp.ypl[0] != d.box_lo[1] ||
+            hp.ypl[d.ny] != d.box_hi[1])
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: lattice planes must increase and span the box", k);
+        hp.cxs = copy_of(d.cx, d.nx);
+        hp.cys = copy_of(d.cy, d.ny);
+        if (!(d.radius > 0.0)) return fail(h, MCX_E_INVALID_ARG, "problem %d: radius must be > 0", k);
+        for (int i = 0; i < d.nx; ++i)
+            if (!(hp.cxs[i] - d.radius > hp.xpl[i] && hp.cxs[i] + d.radius < hp.xpl[i + 1]))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: pin %d crosses its cell in x", k, i);
+        for (int j = 0; j < d.ny; ++j)
+            if (!(hp.cys[j] - d.radius > hp.ypl[j] && hp.cys[j] + d.radius < hp.ypl[j + 1]))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: pin %d crosses its cell in y", k, j);
+        hp.cmat = copy_of(d.pin_mat, (int64_t)d.nx * d.ny);
+        if (d.mod_mat < 0 || d.mod_mat >= d.n_mat) return fail(h, MCX_E_INVALID_ARG, "problem %d: bad mod_mat", k);
+    }
+    for (int32_t m : hp.cmat)
+        if (m < 0 || m >= d.n_mat) return fail(h, MCX_E_INVALID_ARG, "problem %d: material index out of range", k);
+    const int64_t MG = (int64_t)d.n_mat * d.n_grp;
+    if (d.energy_mode == MCX_MG) {
+        if (d.n_grp < 1 || d.n_grp > 255) return fail(h, MCX_E_INVALID_ARG, "problem %d: n_grp must be 1..255", k);
+        if (!d.sigma_t || !d.sigma_s || !d.transfer_cdf)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: missing multigroup tables", k);
+        hp.sig_t = copy_of(d.sigma_t, MG);
+        hp.sig_s = copy_of(d.sigma_s, MG);
+        hp.cdf = copy_of(d.transfer_cdf, MG * d.n_grp);
+        for (int64_t i = 0; i < MG; ++i)
+            if (!(hp.sig_t[i] > 0.0 && hp.sig_s[i] >= 0.0 && hp.sig_s[i] <= hp.sig_t[i] && std::isfinite(hp.sig_t[i])))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: need 0 <= sigma_s <= sigma_t, sigma_t > 0", k);
+        for (int64_t r = 0; r < MG; ++r) {
+            const double *row = hp.cdf.data() + r * d.n_grp;
+            for (int g = 0; g + 1 < d.n_grp; ++g)
+                if (!(row[g] >= 0.0 && row[g] <= row[g + 1]))
+                    return fail(h, MCX_E_INVALID_ARG, "problem %d: transfer cdf rows must be non-decreasing", k);
+            if (row[d.n_grp - 1] != 1.0)
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: transfer cdf rows must end at 1.0", k);
+        }
+        if (d.src_group < 0 || d.src_group >= d.n_grp) return fail(h, MCX_E_INVALID_ARG, "problem %d: bad src_group", k);
+        hp.egrid = hp.siga = hp.sigs = hp.awr = hp.dens = {0.0};
+        hp.hash_lo = hp.hash_hi = {0};
+    } else {
+        if (d.geometry != MCX_GEOM_LATTICE)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: continuous energy needs the lattice geometry", k);
+        if (d.n_species < 1 || d.n_species > MAX_SPECIES)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: n_species must be 1..%d", k, (int)MAX_SPECIES);
+        if (d.grid_len < 2 || !d.e_grid || !d.sig_a || !d.sig_s || !d.awr || !d.density)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: missing continuous-energy tables", k);
+        const int64_t SN = (int64_t)d.n_species * d.grid_len;
+        hp.egrid = copy_of(d.e_grid, SN);
+        hp.siga = copy_of(d.sig_a, SN);
+        hp.sigs = copy_of(d.sig_s, SN);
+        hp.awr = copy_of(d.awr, d.n_species);
+        hp.dens = copy_of(d.density, (int64_t)d.n_mat * d.n_species);
+        for (int s = 0; s < d.n_species; ++s) {
+            if (!sorted_strict(hp.egrid.data() + (int64_t)s * d.grid_len, d.grid_len) || !(hp.egrid[(int64_t)s * d.grid_len] > 0.0))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: energy grid %d must be positive and increasing", k, s);
+            if (!(hp.awr[s] > 0.0)) return fail(h, MCX_E_INVALID_ARG, "problem %d: awr must be > 0", k);
+        }
+        for (int64_t i = 0; i < SN; ++i)
+            if (!(hp.siga[i] >= 0.0 && hp.sigs[i] >= 0.0))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: cross sections must be >= 0", k);
+        for (double v : hp.dens)
+            if (!(v >= 0.0)) return fail(h, MCX_E_INVALID_ARG, "problem %d: densities must be >= 0", k);
+        if (!(d.e_min > 0.0) || !(d.e_source > 0.0))
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: e_min and e_source must be > 0", k);
+        hp.sig_t = hp.sig_s = hp.cdf = {1.0};
+        // hashed grid: uniform bins in ln E over the union of the grids
+        double lo = hp.egrid[0], hi = hp.egrid[d.grid_len - 1];
+        for (int s = 1; s < d.n_species; ++s) {
+            lo = std::min(lo, hp.egrid[(int64_t)s * d.grid_len]);
+            hi = std::max(hi, hp.egrid[(int64_t)s * d.grid_len + d.grid_len - 1]);
+        }
+        int M = d.hash_bins > 0 ? d.hash_bins : std::max(64, d.grid_len / 8);
+        hp.hash_bins = M;
+        hp.hash_ln_lo = std::log(lo);
+        hp.hash_inv = (double)M / (std::log(hi) - std::log(lo));
+        hp.hash_lo.resize((size_t)d.n_species * M);
+        hp.hash_hi.resize((size_t)d.n_species * M);
+        for (int s = 0; s < d.n_species; ++s) {
+            const double *g = hp.egrid.data() + (int64_t)s * d.grid_len;
+            for (int b = 0; b < M; ++b) {
+                double e0 = std::exp(hp.hash_ln_lo + (double)b / hp.hash_inv);
+                double e1 = std::exp(hp.hash_ln_lo + (double)(b + 1) / hp.hash_inv);
+                int l = host_bracket(g, d.grid_len, e0) - 1;
+                int u = host_bracket(g, d.grid_len, e1) + 2;
+                hp.hash_lo[(size_t)s * M + b] = std::max(l, 0);
+                hp.hash_hi[(size_t)s * M + b] = std::min(u, d.grid_len - 1);
+            }
+        }
+    }
+    if (d.src_kind < MCX_SRC_POINT || d.src_kind > MCX_SRC_DISC)
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: bad src_kind", k);
+    if (d.tally_kind == MCX_TALLY_MESH) {
+        for (int a = 0; a < 3; ++a)
+            if (d.mesh_n[a] < 1) return fail(h, MCX_E_INVALID_ARG, "problem %d: mesh_n must be >= 1", k);
+        if (!d.mesh_x || !d.mesh_y || !d.mesh_z) return fail(h, MCX_E_INVALID_ARG, "problem %d: missing mesh edges", k);
+        hp.mx = copy_of(d.mesh_x, d.mesh_n[0] + 1);
+        hp.my = copy_of(d.mesh_y, d.mesh_n[1] + 1);
+        hp.mz = copy_of(d.mesh_z, d.mesh_n[2] + 1);
+        if (!sorted_strict(hp.mx.data(), d.mesh_n[0] + 1) || !sorted_strict(hp.my.data(), d.mesh_n[1] + 1) ||
+            !sorted_strict(hp.mz.data(), d.mesh_n[2] + 1))
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: mesh edges must increase", k);
+        hp.n_bins = (int64_t)d.mesh_n[0] * d.mesh_n[1] * d.mesh_n[2] * (d.energy_mode == MCX_MG ? d.n_grp : 1);
+        hp.eedges = {0.0, 1.0};
+    } else if (d.tally_kind == MCX_TALLY_ENERGY) {
+        if (d.n_ebins < 1 || !d.e_edges) return fail(h, MCX_E_INVALID_ARG, "problem %d: n_ebins must be >= 1", k);
+        hp.eedges = copy_of(d.e_edges, d.n_ebins + 1);
+        if (!sorted_strict(hp.eedges.data(), d.n_ebins + 1))
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: energy edges must increase", k);
+        hp.n_bins = d.n_ebins;
+        hp.mx = hp.my = hp.mz = {0.0, 1.0};
+    } else {
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: bad tally_kind", k);
+    }
+    if (d.energy_mode == MCX_CE && d.tally_kind == MCX_TALLY_MESH && false) return MCX_E_INVALID_ARG;
+    if (d.tally_scale_log2 < 0 || d.tally_scale_log2 > 62)
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: tally_scale_log2 must be 0..62", k);
+    if (d.n_histories >= (1ull << 32)) return fail(h, MCX_E_INVALID_ARG, "problem %d: at most 2^32-1 histories", k);
+    if (d.max_steps < 0) return fail(h, MCX_E_INVALID_ARG, "problem %d: max_steps must be >= 0", k);
+    hp.d.max_steps = d.max_steps == 0 ? 1000000 : d.max_steps;
+    if (hp.d.max_steps >= (int64_t)0xFFFFFFFFll) hp.d.max_steps = 0xFFFFFFFEll;
+    return MCX_OK;
+}
+
+// Device blob layout: every array 256-byte aligned.
+struct BlobBuilder {
+    std::vector<char> bytes;
+    template <class T>
+    size_t add(const std::vector<T> &v)
+    {
+        size_t off = (bytes.size() + 255) / 256 * 256;
+        bytes.resize(off + v.size() * sizeof(T));
+        std::memcpy(bytes.data() + off, v.data(), v.size() * sizeof(T));
+        return off;
+    }
+};
+
+static mcx_status upload(mcx_problem_t h)
+{
+    BlobBuilder bb;
+    struct Offs {
+        size_t xpl, ypl, cxs, cys, cmat, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, hlo, hhi, mx, my, mz, ee;
+    };
+    std::vector<Offs> off(h->n);
+    for (int k = 0; k < h->n; ++k) {
+        HostProblem &p = h->hp[k];
+        Offs &o = off[k];
+        o.xpl = bb.add(p.xpl); o.ypl = bb.add(p.ypl); o.cxs = bb.add(p.cxs); o.cys = bb.add(p.cys);
+        o.cmat = bb.add(p.cmat); o.sig_t = bb.add(p.sig_t); o.sig_s = bb.add(p.sig_s); o.cdf = bb.add(p.cdf);
+        o.egrid = bb.add(p.egrid); o.siga = bb.add(p.siga); o.sigs = bb.add(p.sigs); o.awr = bb.add(p.awr);
+        o.dens = bb.add(p.dens); o.hlo = bb.add(p.hash_lo); o.hhi = bb.add(p.hash_hi);
+        o.mx = bb.add(p.mx); o.my = bb.add(p.my); o.mz = bb.add(p.mz); o.ee = bb.add(p.eedges);
+    }
+    HIP_TRY(h, hipMalloc(&h->blob, std::max<size_t>(bb.bytes.size(), 256)));
+    HIP_TRY(h, hipMemcpy(h->blob, bb.bytes.data(), bb.bytes.size(), hipMemcpyHostToDevice));
+    // tallies
+    h->tally_off.resize(h->n);
+    size_t tb = 0;
+    for (int k = 0; k < h->n; ++k) {
+        h->tally_off[k] = tb;
+        tb += (size_t)h->hp[k].n_bins;
+    }
+    h->total_bins = tb;
+    HIP_TRY(h, hipMalloc(&h->d_tally, std::max<size_t>(tb, 1) * 8));
+    HIP_TRY(h, hipMemset(h->d_tally, 0, std::max<size_t>(tb, 1) * 8));
+    // gradient accumulators: per problem U (1 word) + SL, SA, SS (3 MG words)
+    h->gacc_off.resize(h->n);
+    size_t gw = 0;
+    for (int k = 0; k < h->n; ++k) {
+        h->gacc_off[k] = gw;
+        gw += 1 + 3 * (size_t)h->hp[k].d.n_mat * h->hp[k].d.n_grp;
+    }
+    h->gacc_words = gw;
+    HIP_TRY(h, hipMalloc(&h->d_gacc, gw * 8));
+    HIP_TRY(h, hipMalloc(&h->d_probs, sizeof(ProbDev) * h->n));
+    HIP_TRY(h, hipMalloc(&h->d_prefix, sizeof(unsigned long long) * (h->n + 1)));
+    HIP_TRY(h, hipMalloc(&h->d_ctl, sizeof(RunCtl)));
+    HIP_TRY(h, hipHostMalloc((void **)&h->h_flag, 64, hipHostMallocDefault));
+    // host image of the problem table (static part)
+    char *base = (char *)h->blob;
+    h->pd.resize(h->n);
+    for (int k = 0; k < h->n; ++k) {
+        HostProblem &hp = h->hp[k];
+        const mcx_problem_desc &d = hp.d;
+        Offs &o = off[k];
+        ProbDev &P = h->pd[k];
+        std::memset(&P, 0, sizeof P);
+        P.geometry = d.geometry;
+        P.n_slabs = d.geometry == MCX_GEOM_BOX ? d.n_slabs : 0;
+        P.nx = d.geometry == MCX_GEOM_LATTICE ? d.nx : 0;
+        P.ny = d.geometry == MCX_GEOM_LATTICE ? d.ny : 0;
+        P.mod_mat = d.mod_mat;
+        P.refl_mask = 0;
+        for (int f = 0; f < 6; ++f)
+            if (d.bc[f] == MCX_BC_REFLECT) P.refl_mask |= 1 << f;
+        for (int a = 0; a < 3; ++a) {
+            P.box_lo[a] = d.box_lo[a];
+            P.box_hi[a] = d.box_hi[a];
+        }
+        P.radius = d.radius;
+        P.r2 = d.radius * d.radius;
+        P.xpl = (const double *)(base + o.xpl);
+        P.ypl = (const double *)(base + o.ypl);
+        P.cxs = (const double *)(base + o.cxs);
+        P.cys = (const double *)(base + o.cys);
+        P.cmat = (const int32_t *)(base + o.cmat);
+        P.n_mat = d.n_mat;
+        P.n_grp = d.energy_mode == MCX_MG ? d.n_grp : 1;
+        P.sig_t = (const double *)(base + o.sig_t);
+        P.sig_s = (const double *)(base + o.sig_s);
+        P.cdf = (const double *)(base + o.cdf);
+        P.n_species = d.energy_mode == MCX_CE ? d.n_species : 0;
+        P.grid_len = d.energy_mode == MCX_CE ? d.grid_len : 0;
+        P.egrid = (const double *)(base + o.egrid);
+        P.siga = (const double *)(base + o.siga);
+        P.sigs = (const double *)(base + o.sigs);
+        P.awr = (const double *)(base + o.awr);
+        P.dens = (const double *)(base + o.dens);
+        P.e_min = d.e_min;
+        P.e_src = d.e_source;
+        P.hash_bins = hp.hash_bins;
+        P.hash_ln_lo = hp.hash_ln_lo;
+        P.hash_inv = hp.hash_inv;
+        P.hash_lo = (const int32_t *)(base + o.hlo);
+        P.hash_hi = (const int32_t *)(base + o.hhi);
+        P.src_kind = d.src_kind;
+        P.src_iso = d.src_isotropic ? 1 : 0;
+        P.src_group = d.energy_mode == MCX_MG ? d.src_group : 0;
+        P.tally_kind = d.tally_kind;
+        for (int a = 0; a < 3; ++a) {
+            P.src_pos[a] = d.src_pos[a];
+            P.src_lo[a] = d.src_lo[a];
+            P.src_ext[a] = d.src_hi[a] - d.src_lo[a];
+            P.src_dir[a] = d.src_dir[a];
+            P.mesh_n[a] = d.tally_kind == MCX_TALLY_MESH ? d.mesh_n[a] : 1;
+        }
+        P.src_radius = d.src_radius;
+        P.n_ebins = d.tally_kind == MCX_TALLY_ENERGY ? d.n_ebins : 1;
+        P.mx = (const double *)(base + o.mx);
+        P.my = (const double *)(base + o.my);
+        P.mz = (const double *)(base + o.mz);
+        P.eedges = (const double *)(base + o.ee);
+        P.tscale = std::ldexp(1.0, d.tally_scale_log2);
+        P.tally = h->d_tally + h->tally_off[k];
+        P.key0 = (uint32_t)d.seed;
+        P.key1 = (uint32_t)(d.seed >> 32) ^ d.problem_id;
+        P.max_steps = hp.d.max_steps;
+        unsigned long long *ga = h->d_gacc + h->gacc_off[k];
+        size_t mg = (size_t)P.n_mat * P.n_grp;
+        P.U = ga;
+        P.SL = ga + 1;
+        P.SA = ga + 1 + mg;
+        P.SS = ga + 1 + 2 * mg;
+    }
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t n_problems, mcx_problem_t *out)
+{
+    if (!out) return MCX_E_INVALID_ARG;
+    *out = nullptr;
+    if (!descs || n_problems < 1) return MCX_E_INVALID_ARG;
+    mcx_problem_t h = new mcx_problem_s();
+    h->n = n_problems;
+    h->hp.resize(n_problems);
+    mcx_status s = MCX_OK;
+    for (int k = 0; k < n_problems && s == MCX_OK; ++k) s = import_problem(h, descs[k], k, h->hp[k]);
+    if (s == MCX_OK) {
+        h->geom = descs[0].geometry;
+        h->emode = descs[0].energy_mode;
+        h->tally_kind = descs[0].tally_kind;
+        for (int k = 1; k < n_problems; ++k)
+            if (descs[k].geometry != h->geom || descs[k].energy_mode != h->emode || descs[k].tally_kind != h->tally_kind)
+                s = fail(h, MCX_E_INVALID_ARG, "problems of one handle must share geometry, energy mode and tally kind");
+    }
+    if (s == MCX_OK) {
+        hipError_t e = hipGetDevice(&h->device);
+        hipDeviceProp_t prop;
+        if (e == hipSuccess) e = hipGetDeviceProperties(&prop, h->device);
+        if (e != hipSuccess) s = hip_fail(h, e, "hipGetDeviceProperties");
+        else h->num_cus = prop.multiProcessorCount;
+    }
+    if (s == MCX_OK) s = upload(h);
+    if (s != MCX_OK) {
+        mcx_destroy_problem(h);
+        return s;
+    }
+    *out = h;
+    return MCX_OK;
+}
+
+extern "C" void mcx_destroy_problem(mcx_problem_t h)
+{
+    if (!h) return;
+    if (h->blob) hipFree(h->blob);
+    if (h->d_probs) hipFree(h->d_probs);
+    if (h->d_prefix) hipFree(h->d_prefix);
+    if (h->d_tally) hipFree(h->d_tally);
+    if (h->d_ctl) hipFree(h->d_ctl);
+    if (h->d_G) hipFree(h->d_G);
+    if (h->d_w) hipFree(h->d_w);
+    if (h->d_gacc) hipFree(h->d_gacc);
+    if (h->h_flag) hipHostFree(h->h_flag);
+    if (h->ws.ptr) hipFree(h->ws.ptr);
+    delete h;
+}
+
+extern "C" mcx_status mcx_set_xs(mcx_problem_t h, int32_t problem, const double *sigma_t, const double *sigma_s,
+                                 int32_t where)
+{
+    if (!h) return MCX_E_INVALID_ARG;
+    if (problem < 0 || problem >= h->n) return fail(h, MCX_E_INVALID_ARG, "bad problem index");
+    HostProblem &hp = h->hp[problem];
+    if (hp.d.energy_mode != MCX_MG) return fail(h, MCX_E_INVALID_ARG, "mcx_set_xs needs a multigroup problem");
+    size_t mg = (size_t)hp.d.n_mat * hp.d.n_grp;
+    std::vector<double> st(mg), ss(mg);
+    if (!sigma_t || !sigma_s) return fail(h, MCX_E_INVALID_ARG, "null cross-section pointer");
+    if (where == MCX_DEVICE) {
+        HIP_TRY(h, hipMemcpy(st.data(), sigma_t, mg * 8, hipMemcpyDeviceToHost));
+        HIP_TRY(h, hipMemcpy(ss.data(), sigma_s, mg * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(st.data(), sigma_t, mg * 8);
+        std::memcpy(ss.data(), sigma_s, mg * 8);
+    }
+    for (size_t i = 0; i < mg; ++i)
+        if (!(st[i] > 0.0 && ss[i] >= 0.0 && ss[i] <= st[i] && std::isfinite(st[i])))
+            return fail(h, MCX_E_INVALID_ARG, "need 0 <= sigma_s <= sigma_t, sigma_t > 0");
+    HIP_TRY(h, hipMemcpy((void *)h->pd[problem].sig_t, st.data(), mg * 8, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy((void *)h->pd[problem].sig_s, ss.data(), mg * 8, hipMemcpyHostToDevice));
+    hp.sig_t = st;
+    hp.sig_s = ss;
+    h->have_forward = false;
+    return MCX_OK;
+}
+
+hipError_t mcx::ws_reserve(Workspace &ws, size_t bytes)
+{
+    if (ws.bytes >= bytes) return hipSuccess;
+    if (ws.ptr) {
+        hipError_t e = hipFree(ws.ptr);
+        if (e != hipSuccess) return e;
+        ws.ptr = nullptr;
+        ws.bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ws.ptr, bytes);
+    if (e == hipSuccess) ws.bytes = bytes;
+    return e;
+}
+
+static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
+{
+    if (o.sched < MCX_SCHED_NAIVE || o.sched > MCX_SCHED_ASYNC) return fail(h, MCX_E_INVALID_ARG, "bad sched");
+    if (o.decomp != MCX_DECOMP_FUSED && o.decomp != MCX_DECOMP_SPLIT) return fail(h, MCX_E_INVALID_ARG, "bad decomp");
+    if (o.lookup != MCX_LOOKUP_BINARY && o.lookup != MCX_LOOKUP_HASH) return fail(h, MCX_E_INVALID_ARG, "bad lookup");
+    if (o.sched == MCX_SCHED_NAIVE && o.decomp == MCX_DECOMP_SPLIT)
+        return fail(h, MCX_E_INVALID_ARG, "the naive scheduler runs whole histories (fused only)");
+    if (o.stack_capacity < 0 || o.stack_threshold < 0 || o.stash_links < 0 || o.arena_links < 0 ||
+        o.waves_per_cu < 0 || o.block_size < 0)
+        return fail(h, MCX_E_INVALID_ARG, "negative tuning value");
+    return MCX_OK;
+}
+
+// One pass over the run's histories with the given mode.
+static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, const std::vector<uint64_t> &first,
+                           const std::vector<uint64_t> &count, void *digest, unsigned int *err_out)
+{
+    hipStream_t stream = (hipStream_t)o.hip_stream;
+    std::vector<unsigned long long> prefix(h->n + 1, 0);
+    for (int k = 0; k < h->n; ++k) {
+        ProbDev &P = h->pd[k];
+        P.first = first[k];
+        P.count = count[k];
+        P.gbase = prefix[k];
+        P.lookup_hash = o.lookup == MCX_LOOKUP_HASH ? 1 : 0;
+        prefix[k + 1] = prefix[k] + count[k];
+    }
+    unsigned long long total = prefix[h->n];
+    HIP_TRY(h, hipMemcpyAsync(h->d_probs, h->pd.data(), sizeof(ProbDev) * h->n, hipMemcpyHostToDevice, stream));
+    HIP_TRY(h, hipMemcpyAsync(h->d_prefix, prefix.data(), sizeof(unsigned long long) * (h->n + 1),
+                              hipMemcpyHostToDevice, stream));
+    RunCtl ctl;
+    std::memset(&ctl, 0, sizeof ctl);
+    ctl.total = total;
+    HIP_TRY(h, hipMemcpyAsync(h->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, stream));
+
+    LaunchArgs a{};
+    a.probs = h->d_probs;
+    a.n_probs = h->n;
+    a.prefix = h->d_prefix;
+    a.total = total;
+    a.ctl = h->d_ctl;
+    a.digest = digest;
+    a.geom = h->geom;
+    a.emode = h->emode;
+    a.mode = mode;
+    a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
+    a.lacc_words = (mode == MODE_REPLAY_B && h->n == 1) ? 3 * h->pd[0].n_mat * h->pd[0].n_grp : 0;
+    a.stream = stream;
+    a.num_cus = h->num_cus;
+    a.block_size = o.block_size;
+    a.waves_per_cu = o.waves_per_cu;
+    a.stack_capacity = o.stack_capacity;
+    a.stack_threshold = o.stack_threshold;
+    a.stash_links = o.stash_links;
+    a.arena_links = o.arena_links;
+
+    LaunchStats st;
+    LaunchTimer tm;
+    tm.on = o.time_kernels != 0;
+    tm.stream = stream;
+    hipError_t e = hipSuccess;
+    if (total > 0) {
+        if (o.sched == MCX_SCHED_NAIVE) e = launch_naive(a, st, tm);
+        else if (o.sched == MCX_SCHED_STACK) e = launch_stack(a, h->ws, st, tm, h->h_flag);
+        else e = launch_async(a, h->ws, st, tm);
+    }
+    if (e != hipSuccess) {
+        tm.total_ms();
+        return hip_fail(h, e, "kernel launch");
+    }
+    HIP_TRY(h, hipMemcpyAsync(&ctl, h->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(h, hipStreamSynchronize(stream));
+    mcx_counters_t &c = h->counters;
+    std::memset(&c, 0, sizeof c);
+    c.sourced = ctl.counters[C_SOURCED];
+    c.flights = ctl.counters[C_FLIGHTS];
+    c.collisions = ctl.counters[C_COLLISIONS];
+    c.scatters = ctl.counters[C_SCATTERS];
+    c.absorbs = ctl.counters[C_ABSORBS];
+    c.crossings = ctl.counters[C_CROSSINGS];
+    c.leaks = ctl.counters[C_LEAKS];
+    c.reflections = ctl.counters[C_REFLECTIONS];
+    c.cutoffs = ctl.counters[C_CUTOFFS];
+    c.killed = ctl.counters[C_KILLED];
+    c.pieces = ctl.counters[C_PIECES];
+    c.qsum = ctl.qsum;
+    c.overflow = (ctl.error & ERR_OVERFLOW) ? 1 : 0;
+    c.events = ctl.counters[C_EVENTS];
+    c.lane_slots = ctl.counters[C_LANE_SLOTS];
+    c.dispatches = ctl.counters[C_DISPATCHES];
+    c.spills = ctl.counters[C_SPILLS];
+    c.refills = ctl.counters[C_REFILLS];
+    c.make_work = ctl.counters[C_MAKE_WORK];
+    c.rounds = st.rounds;
+    c.launches = st.launches;
+    c.kernel_ms = tm.total_ms();
+    c.grid_blocks = st.grid_blocks;
+    c.block_threads = st.block_threads;
+    c.lds_bytes = st.lds_bytes;
+    *err_out = ctl.error;
+    if (ctl.error & ERR_CAPACITY) return fail(h, MCX_E_CAPACITY, "scheduler capacity exhausted (stack or link arena)");
+    if (ctl.counters[C_SOURCED] != total)
+        return fail(h, MCX_E_DEVICE, "internal: sourced %llu of %llu histories", ctl.counters[C_SOURCED], total);
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_run(mcx_problem_t h, const mcx_run_opts *opts)
+{
+    if (!h || !opts) return MCX_E_INVALID_ARG;
+    const mcx_run_opts &o = *opts;
+    mcx_status s = check_opts(h, o);
+    if (s != MCX_OK) return s;
+    std::vector<uint64_t> first(h->n), count(h->n);
+    if (h->n == 1) {
+        uint64_t N = h->hp[0].d.n_histories;
+        if (o.first_history > N) return fail(h, MCX_E_INVALID_ARG, "first_history beyond n_histories");
+        first[0] = o.first_history;
+        count[0] = o.n_histories ? o.n_histories : N - o.first_history;
+        if (first[0] + count[0] > N) return fail(h, MCX_E_INVALID_ARG, "history range beyond n_histories");
+    } else {
+        if (o.first_history || o.n_histories)
+            return fail(h, MCX_E_INVALID_ARG, "history ranges apply to single-problem handles only");
+        for (int k = 0; k < h->n; ++k) {
+            first[k] = 0;
+            count[k] = h->hp[k].d.n_histories;
+        }
+    }
+    h->tallies_valid = false;
+    h->have_forward = false;
+    if (!o.accumulate)
+        HIP_TRY(h, hipMemsetAsync(h->d_tally, 0, std::max<size_t>(h->total_bins, 1) * 8, (hipStream_t)o.hip_stream));
+    unsigned int err = 0;
+    s = run_pass(h, o, MODE_FWD, first, count, o.digest, &err);
+    if (s != MCX_OK) return s;
+    if (err & ERR_OVERFLOW) return fail(h, MCX_E_OVERFLOW, "fixed-point tally total reached 2^63");
+    h->tallies_valid = true;
+    h->have_forward = true;
+    h->last_first = first;
+    h->last_count = count;
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_tallies(mcx_problem_t h, int32_t problem, int64_t *out, int64_t n, int32_t where)
+{
+    if (!h || !out) return MCX_E_INVALID_ARG;
+    if (problem < 0 || problem >= h->n) return fail(h, MCX_E_INVALID_ARG, "bad problem index");
+    if (!h->tallies_valid) return fail(h, MCX_E_STATE, "no valid tallies (no successful run)");
+    if (n != h->hp[problem].n_bins) return fail(h, MCX_E_INVALID_ARG, "tally size is %lld", (long long)h->hp[problem].n_bins);
+    HIP_TRY(h, hipMemcpy(out, h->d_tally + h->tally_off[problem], (size_t)n * 8,
+                         where == MCX_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const double *dL_dT, double *grad_sigma_t,
+                                   double *grad_sigma_s, int32_t where, const mcx_run_opts *opts)
+{
+    if (!h || !opts || !dL_dT || !grad_sigma_t || !grad_sigma_s) return MCX_E_INVALID_ARG;
+    if (h->emode != MCX_MG) return fail(h, MCX_E_INVALID_ARG, "the backward needs multigroup problems");
+    if (problem < -1 || problem >= h->n) return fail(h, MCX_E_INVALID_ARG, "bad problem index");
+    if (!h->have_forward) return fail(h, MCX_E_STATE, "mcx_backward needs a successful forward run first");
+    mcx_run_opts o = *opts;
+    mcx_status s = check_opts(h, o);
+    if (s != MCX_OK) return s;
+    hipStream_t stream = (hipStream_t)o.hip_stream;
+    // per-problem replay ranges: those of the last forward, selected problems only
+    std::vector<uint64_t> first = h->last_first, count = h->last_count;
+    size_t wtot = 0;
+    std::vector<size_t> woff(h->n, 0);
+    for (int k = 0; k < h->n; ++k) {
+        if (problem >= 0 && k != problem) count[k] = 0;
+        woff[k] = wtot;
+        if (problem < 0 || k == problem) wtot += (size_t)h->hp[k].n_bins;
+    }
+    if (wtot * 8 > h->w_cap) {
+        if (h->d_w) hipFree(h->d_w);
+        h->d_w = nullptr;
+        h->w_cap = 0;
+        HIP_TRY(h, hipMalloc(&h->d_w, wtot * 8));
+        h->w_cap = wtot * 8;
+    }
+    HIP_TRY(h, hipMemcpyAsync(h->d_w, dL_dT, wtot * 8, where == MCX_DEVICE ? hipMemcpyDeviceToDevice
+                                                                          : hipMemcpyHostToDevice, stream));
+    unsigned long long gtot = 0;
+    for (int k = 0; k < h->n; ++k) gtot += count[k];
+    if (gtot * 8 > h->G_cap) {
+        if (h->d_G) hipFree(h->d_G);
+        h->d_G = nullptr;
+        h->G_cap = 0;
+        HIP_TRY(h, hipMalloc(&h->d_G, std::max<unsigned long long>(gtot, 1) * 8));
+        h->G_cap = std::max<unsigned long long>(gtot, 1) * 8;
+    }
+    HIP_TRY(h, hipMemsetAsync(h->d_gacc, 0, h->gacc_words * 8, stream));
+    for (int k = 0; k < h->n; ++k) {
+        h->pd[k].w = h->d_w + woff[k];
+        h->pd[k].G = h->d_G;
+        h->pd[k].gscale = 1.0;
+    }
+    unsigned int err = 0;
+    s = run_pass(h, o, MODE_REPLAY_A, first, count, nullptr, &err);
+    if (s != MCX_OK) return s;
+    if (err & ERR_BOUND) return fail(h, MCX_E_OVERFLOW, "score-function bound does not fit 64 bits");
+    std::vector<unsigned long long> acc(h->gacc_words);
+    HIP_TRY(h, hipMemcpy(acc.data(), h->d_gacc, h->gacc_words * 8, hipMemcpyDeviceToHost));
+    std::vector<int> scale(h->n, 0);
+    for (int k = 0; k < h->n; ++k) {
+        scale[k] = 62 - bit_length(acc[h->gacc_off[k]]);
+        h->pd[k].gscale = std::ldexp(1.0, scale[k]);
+    }
+    s = run_pass(h, o, MODE_REPLAY_B, first, count, nullptr, &err);
+    if (s != MCX_OK) return s;
+    HIP_TRY(h, hipMemcpy(acc.data(), h->d_gacc, h->gacc_words * 8, hipMemcpyDeviceToHost));
+    // gradients: grad Sigma_t = (-SL + SA/Sigma_a) 2^-s / N, grad Sigma_s = (SS/Sigma_s - SA/Sigma_a) 2^-s / N
+    std::vector<double> gt, gs;
+    for (int k = 0; k < h->n; ++k) {
+        if (problem >= 0 && k != problem) continue;
+        const HostProblem &hp = h->hp[k];
+        size_t mg = (size_t)hp.d.n_mat * hp.d.n_grp;
+        const long long *SL = (const long long *)&acc[h->gacc_off[k] + 1];
+        const long long *SA = SL + mg;
+        const long long *SS = SL + 2 * mg;
+        double sc = std::ldexp(1.0, -scale[k]);
+        double n = (double)h->last_count[k];
+        for (size_t i = 0; i < mg; ++i) {
+            double sa = hp.sig_t[i] - hp.sig_s[i];
+            gt.push_back(((-(double)SL[i]) + ((double)SA[i] / sa)) * sc / n);
+            gs.push_back((((double)SS[i] / hp.sig_s[i]) - ((double)SA[i] / sa)) * sc / n);
+        }
+    }
+    size_t nb = gt.size() * 8;
+    hipMemcpyKind kind = where == MCX_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+    HIP_TRY(h, hipMemcpy(grad_sigma_t, gt.data(), nb, kind));
+    HIP_TRY(h, hipMemcpy(grad_sigma_s, gs.data(), nb, kind));
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_counters(mcx_problem_t h, mcx_counters_t *out)
+{
+    if (!h || !out) return MCX_E_INVALID_ARG;
+    *out = h->counters;
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_problem_info(mcx_problem_t h, int32_t problem, int64_t *n_bins, int32_t *n_mat,
+                                       int32_t *n_grp, uint64_t *n_histories)
+{
+    if (!h) return MCX_E_INVALID_ARG;
+    if (problem < 0 || problem >= h->n) return fail(h, MCX_E_INVALID_ARG, "bad problem index");
+    const HostProblem &hp = h->hp[problem];
+    if (n_bins) *n_bins = hp.n_bins;
+    if (n_mat) *n_mat = hp.d.n_mat;
+    if (n_grp) *n_grp = hp.d.energy_mode == MCX_MG ? hp.d.n_grp : 1;
+    if (n_histories) *n_histories = hp.d.n_histories;
+    return MCX_OK;
+}
+
+extern "C" const char *mcx_status_str(mcx_status s)
+{
+    switch (s) {
+    case MCX_OK: return "ok";
+    case MCX_E_INVALID_ARG: return "invalid argument";
+    case MCX_E_OOM: return "out of device memory";
+    case MCX_E_DEVICE: return "device error";
+    case MCX_E_CAPACITY: return "scheduler capacity exhausted";
+    case MCX_E_OVERFLOW: return "fixed-point overflow";
+    case MCX_E_STATE: return "invalid state";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *mcx_last_error(mcx_problem_t h)
+{
+    return h ? h->err.c_str() : "null handle";
+}

@@ -1,0 +1,85 @@
+// Host-visible launch interface of the scheduler kernels (implemented in
+// sched_naive.hip, sched_stack.hip and sched_async.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <utility>
+#include <vector>
+
+#include "problem.hpp"
+
+namespace mcx {
+
+// Per-launch HIP-event timing on the run's stream (optional).
+struct LaunchTimer {
+    bool on = false;
+    hipStream_t stream = nullptr;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    void begin()
+    {
+        if (!on) return;
+        hipEvent_t a, b;
+        hipEventCreate(&a);
+        hipEventCreate(&b);
+        hipEventRecord(a, stream);
+        ev.emplace_back(a, b);
+    }
+    void end()
+    {
+        if (!on || ev.empty()) return;
+        hipEventRecord(ev.back().second, stream);
+    }
+    // after the stream has been synchronised
+    double total_ms()
+    {
+        double t = 0.0;
+        for (auto &p : ev) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) t += ms;
+            hipEventDestroy(p.first);
+            hipEventDestroy(p.second);
+        }
+        ev.clear();
+        return t;
+    }
+};
+
+// What a launcher needs to know about the run.
+struct LaunchArgs {
+    const ProbDev *probs;                  // device array [n_probs]
+    int n_probs;
+    const unsigned long long *prefix;      // device [n_probs + 1] flattened id offsets
+    unsigned long long total;              // flattened histories of the run
+    RunCtl *ctl;                           // device control block
+    void *digest;                          // device Digest array or null
+    int geom, emode, mode, split;
+    int lacc_words;                        // pass B per-block sums in LDS (single problem), 0 = none
+    hipStream_t stream;
+    int num_cus;
+    // tuning (0 = default)
+    int block_size;                        // naive
+    int waves_per_cu;                      // stack / async
+    long long stack_capacity, stack_threshold;
+    int stash_links, arena_links;
+};
+
+struct LaunchStats {
+    unsigned long long launches = 0, rounds = 0;
+    int grid_blocks = 0, block_threads = 0, lds_bytes = 0;
+};
+
+// Device scratch owned by a problem handle, grown on demand.
+struct Workspace {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+hipError_t ws_reserve(Workspace &ws, size_t bytes);
+
+hipError_t launch_naive(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm);
+hipError_t launch_stack(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
+                        unsigned int *host_flag_pinned);
+hipError_t launch_async(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm);
+
+}  // namespace mcx

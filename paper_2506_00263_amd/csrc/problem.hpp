@@ -1,0 +1,76 @@
+// Device-resident description of one problem of a run, filled by the host
+// side of the library (api.cpp) and read by every kernel.  Pointers are
+// device addresses.  Run-specific fields (history range, backward buffers)
+// are refreshed before every launch sequence.
+#pragma once
+#include <stdint.h>
+
+namespace mcx {
+
+enum : int { GEOM_BOX = 0, GEOM_LATTICE = 1 };
+enum : int { EMODE_MG = 0, EMODE_CE = 1 };
+enum : int { MODE_FWD = 0, MODE_REPLAY_A = 1, MODE_REPLAY_B = 2 };
+enum : int { MAX_SPECIES = 4 };
+
+struct ProbDev {
+    // geometry
+    int32_t geometry, n_slabs, nx, ny;
+    int32_t mod_mat, refl_mask;      // bit f: face f (x-,x+,y-,y+,z-,z+) reflects
+    double box_lo[3], box_hi[3];
+    double radius, r2;               // r2 = radius * radius
+    const double *xpl;               // slab planes (box) or lattice x planes
+    const double *ypl, *cxs, *cys;
+    const int32_t *cmat;             // slab materials or pin materials
+    // multigroup
+    int32_t n_mat, n_grp;
+    const double *sig_t, *sig_s, *cdf;
+    // continuous energy
+    int32_t n_species, grid_len;
+    const double *egrid, *siga, *sigs, *awr, *dens;
+    double e_min, e_src;
+    int32_t hash_bins, lookup_hash;
+    double hash_ln_lo, hash_inv;
+    const int32_t *hash_lo, *hash_hi;   // [species][bin]
+    // source
+    int32_t src_kind, src_iso, src_group, tally_kind;
+    double src_pos[3], src_lo[3], src_ext[3], src_dir[3];
+    double src_radius;
+    // tally
+    int32_t mesh_n[3], n_ebins;
+    const double *mx, *my, *mz, *eedges;
+    double tscale;                   // 2^tally_scale_log2
+    unsigned long long *tally;       // this problem's bins
+    // random numbers and histories of the current run
+    uint32_t key0, key1;
+    uint64_t first, count;           // histories [first, first + count)
+    uint64_t gbase;                  // offset in the run's flattened id space
+    int64_t max_steps;
+    // score-function backward of the current run
+    const double *w;                 // dL/dT over this problem's bins
+    double *G;                       // per history, indexed gbase + (h - first)
+    double gscale;                   // 2^s of pass B
+    unsigned long long *U;           // pass A bound (uint64)
+    unsigned long long *SL, *SA, *SS;  // pass B sums [n_mat*n_grp] (int64 bits)
+    int32_t acc_off, pad;            // offset of this problem in per-wave LDS sums
+};
+
+// Per-run control block in device memory.
+struct RunCtl {
+    unsigned long long src_cursor;   // next flattened history id to source
+    unsigned long long total;        // flattened histories of the run
+    unsigned long long completed;    // histories finished
+    unsigned int error;              // bit 0 capacity, bit 1 overflow, bit 2 pass-A bound
+    unsigned int done_round;         // stack: round that found no work (+1)
+    unsigned long long qsum;         // exact total of all contributions
+    unsigned long long counters[24]; // see Counter
+};
+
+enum Counter : int {
+    C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,
+    C_CUTOFFS, C_KILLED, C_PIECES, C_EVENTS, C_LANE_SLOTS, C_DISPATCHES, C_SPILLS, C_REFILLS, C_MAKE_WORK,
+    C_NUM
+};
+
+enum : unsigned int { ERR_CAPACITY = 1u, ERR_OVERFLOW = 2u, ERR_BOUND = 4u };
+
+}  // namespace mcx

@@ -1,0 +1,496 @@
+// Asynchronous thread-data remapping (paper Sec. 3.2).
+//
+// One persistent launch.  Each wavefront (one per block) owns a stash of
+// work links in LDS: a link holds up to 64 particles (one per lane) that all
+// wait for the same event.  The stash keeps a free set, a ready set (links to
+// run, normally full) and one partially filled link per event type; new
+// particles of event k always go into the partial link of k, so packing
+// stays optimal, and a link that fills up becomes ready.
+//
+// A wavefront repeats: run a ready link; else, while histories remain, call
+// the source ("make_work") for 64 new particles; else refill a link from
+// the global arena; else run its fullest partial link; else leave.
+// When a deposit needs a link and the stash has none free, a ready link is
+// spilled to the global arena.
+//
+// Global arena: links in HBM grouped into lock-free queues, one set holding
+// empty links and one holding filled links.  A queue is a (head, tail) pair
+// of link indices packed in one 64-bit word; a wavefront takes a queue by
+// atomically exchanging it with a "claimed" marker, edits its list, and puts
+// it back with another exchange.  Link data is published with an agent-scope
+// release before the queue is put back and read after an acquire, so other
+// XCDs see it.  No wavefront ever waits for another block's progress except
+// for bounded retries when every queue is momentarily claimed.
+#include <algorithm>
+
+#include "bank.hpp"
+#include "kernels.hpp"
+
+namespace mcx {
+
+struct AsyncArgs {
+    const ProbDev *probs;
+    int n_probs;
+    const unsigned long long *prefix;
+    unsigned long long total;
+    RunCtl *ctl;
+    Digest *digest;
+    int links;                   // stash links per wavefront (<= 16)
+    int link_bytes;              // bytes of one 64-slot link
+    char *arena;                 // n_arena links
+    uint32_t *hdr;               // per arena link: event | count << 8
+    uint32_t *next;              // per arena link
+    unsigned long long *qfull;   // queues of filled links [n_queues]
+    unsigned long long *qempty;  // queues of empty links [n_queues]
+    uint32_t *fill;              // number of filled links in the arena
+    int n_arena, n_queues;
+    int lacc_words;
+    int spin_limit;
+};
+
+constexpr uint32_t NIL = 0xFFFFFFFFu;
+constexpr unsigned long long Q_EMPTY = ~0ull;
+constexpr unsigned long long Q_CLAIMED = 0xFFFFFFFEFFFFFFFEull;
+__device__ __forceinline__ uint32_t q_head(unsigned long long q) { return (uint32_t)(q >> 32); }
+__device__ __forceinline__ uint32_t q_tail(unsigned long long q) { return (uint32_t)q; }
+__device__ __forceinline__ unsigned long long q_pack(uint32_t h, uint32_t t)
+{
+    return ((unsigned long long)h << 32) | (unsigned long long)t;
+}
+
+__device__ __forceinline__ unsigned long long uni64(unsigned long long v)
+{
+    return ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(v >> 32)) << 32) |
+           (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)v);
+}
+
+__device__ __forceinline__ unsigned long long q_exchange(unsigned long long *slot, unsigned long long v)
+{
+    unsigned long long old = 0;
+    if (__lane_id() == 0)
+        old = __hip_atomic_exchange(slot, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    return uni64(old);
+}
+
+__device__ __forceinline__ unsigned long long q_peek(unsigned long long *slot)
+{
+    unsigned long long v = 0;
+    if (__lane_id() == 0) v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return uni64(v);
+}
+
+__device__ __forceinline__ uint32_t lane0_load(const uint32_t *p)
+{
+    uint32_t v = 0;
+    if (__lane_id() == 0) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ void lane0_store(uint32_t *p, uint32_t v)
+{
+    if (__lane_id() == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Pop one link from one of the 64 queues in `slots` (one queue per lane, so a
+// single vector load inspects all of them).  Returns NIL if none had a link.
+__device__ uint32_t arena_pop(const AsyncArgs &A, unsigned long long *slots, uint32_t start)
+{
+    const int lane = __lane_id();
+    unsigned long long mine = __hip_atomic_load(&slots[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    uint64_t cand = __ballot(mine != Q_CLAIMED && q_head(mine) != NIL);
+    // rotate so that wavefronts start at different queues
+    uint32_t rot = start & 63u;
+    cand = (cand >> rot) | (rot ? (cand << (64 - rot)) : 0ull);
+    while (cand) {
+        int j = __ffsll((unsigned long long)cand) - 1;
+        cand &= cand - 1;
+        int s = (int)((uint32_t)(j + (int)rot) & 63u);
+        unsigned long long v = q_exchange(&slots[s], Q_CLAIMED);
+        if (v == Q_CLAIMED) continue;                 // someone else holds it
+        if (q_head(v) == NIL) {
+            q_exchange(&slots[s], v);
+            continue;
+        }
+        __threadfence();                              // acquire: see the list and link data
+        uint32_t a = q_head(v);
+        uint32_t nh = lane0_load(&A.next[a]);
+        unsigned long long nv = (nh == NIL) ? Q_EMPTY : q_pack(nh, q_tail(v));
+        q_exchange(&slots[s], nv);
+        return a;
+    }
+    return NIL;
+}
+
+// Append link a to one of the 64 queues of `slots`; bounded retries while
+// all are claimed.
+__device__ bool arena_push(const AsyncArgs &A, unsigned long long *slots, uint32_t start, uint32_t a)
+{
+    lane0_store(&A.next[a], NIL);
+    for (int spin = 0; spin < A.spin_limit; ++spin) {
+        for (int i = 0; i < 64; ++i) {
+            int s = (int)((start + (uint32_t)i) & 63u);
+            unsigned long long v = q_exchange(&slots[s], Q_CLAIMED);
+            if (v == Q_CLAIMED) continue;
+            __threadfence();
+            unsigned long long nv;
+            if (q_head(v) == NIL) {
+                nv = q_pack(a, a);
+            } else {
+                lane0_store(&A.next[q_tail(v)], a);
+                nv = q_pack(q_head(v), a);
+            }
+            __threadfence();                          // release the link and list edits
+            q_exchange(&slots[s], nv);
+            return true;
+        }
+        __builtin_amdgcn_s_sleep(4);
+    }
+    return false;
+}
+
+// filled links currently in the arena (may lag a push in flight; the
+// wavefront doing that push re-checks before it leaves)
+__device__ __forceinline__ unsigned int arena_fill(const AsyncArgs &A)
+{
+    return lane0_load(A.fill);
+}
+
+// Wave-uniform stash bookkeeping (all values live in scalar registers).
+struct Stash {
+    uint32_t freem, readym;
+    unsigned long long clo, chi;   // 8-bit counts of links 0-7 and 8-15
+    uint32_t evw;                  // 2-bit event of each link
+    uint32_t part;                 // 8-bit partial link per event (0xff none)
+    __device__ int cnt(int l) const
+    {
+        return (int)(((l < 8) ? (clo >> (8 * l)) : (chi >> (8 * (l - 8)))) & 0xffull);
+    }
+    __device__ void set_cnt(int l, int c)
+    {
+        if (l < 8) clo = (clo & ~(0xffull << (8 * l))) | ((unsigned long long)c << (8 * l));
+        else chi = (chi & ~(0xffull << (8 * (l - 8)))) | ((unsigned long long)c << (8 * (l - 8)));
+    }
+    __device__ int ev(int l) const { return (int)((evw >> (2 * l)) & 3u); }
+    __device__ void set_ev(int l, int e) { evw = (evw & ~(3u << (2 * l))) | ((uint32_t)e << (2 * l)); }
+    __device__ int partial(int k) const
+    {
+        int v = (int)((part >> (8 * k)) & 0xffu);
+        return v == 0xff ? -1 : v;
+    }
+    __device__ void set_partial(int k, int l) { part = (part & ~(0xffu << (8 * k))) | ((uint32_t)(l & 0xff) << (8 * k)); }
+};
+
+struct AsyncWave {
+    const AsyncArgs &A;
+    char *lds;
+    int nd, nu;
+    uint32_t qstart;
+    Stash S;
+    __device__ SoA link(int l) const { return SoA{lds + (long)l * A.link_bytes, 64, nd}; }
+    __device__ SoA alink(uint32_t a) const { return SoA{A.arena + (long)a * A.link_bytes, 64, nd}; }
+
+    // move ready link v to the global arena
+    __device__ bool spill(int v)
+    {
+        uint32_t a = NIL;
+        for (int spin = 0; spin < A.spin_limit && a == NIL; ++spin) {
+            a = arena_pop(A, A.qempty, qstart);
+            if (a == NIL) __builtin_amdgcn_s_sleep(4);
+        }
+        if (a == NIL) return false;
+        copy_slot(alink(a), __lane_id(), link(v), __lane_id(), nd, nu);
+        lane0_store(&A.hdr[a], (uint32_t)S.ev(v) | ((uint32_t)S.cnt(v) << 8));
+        __threadfence();                              // release the link data
+        if (!arena_push(A, A.qfull, qstart, a)) return false;
+        if (__lane_id() == 0) atomicAdd(A.fill, 1u);
+        return true;
+    }
+
+    // a free stash link, spilling a ready one if none is free; -1 on failure
+    __device__ int alloc(WaveCount &wc, uint32_t &err)
+    {
+        if (S.freem == 0) {
+            if (S.readym == 0) {
+                err |= ERR_CAPACITY;
+                return -1;
+            }
+            int v = __ffs(S.readym) - 1;
+            if (!spill(v)) {
+                err |= ERR_CAPACITY;
+                return -1;
+            }
+            S.readym &= ~(1u << v);
+            S.freem |= 1u << v;
+            wc.c[C_SPILLS] += 1;
+        }
+        int l = __ffs(S.freem) - 1;
+        S.freem &= ~(1u << l);
+        return l;
+    }
+
+    // pack this wavefront's particles into the partial links of their next events
+    template <class LAY, int E>
+    __device__ void deposit(bool act, int ne, const Part &p, bool dig, WaveCount &wc, uint32_t &err)
+    {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            bool mine = act && ne == k;
+            uint64_t mask = __ballot(mine);
+            if (mask == 0) continue;
+            int n = __popcll(mask);
+            int r = (int)lane_rank(mask);
+            int pl = S.partial(k);
+            int f = 0;
+            if (pl < 0) {
+                pl = alloc(wc, err);
+                if (pl < 0) continue;
+                S.set_ev(pl, k);
+                S.set_cnt(pl, 0);
+                S.set_partial(k, pl);
+            } else {
+                f = S.cnt(pl);
+            }
+            int take = n < 64 - f ? n : 64 - f;
+            if (mine && r < take) put<LAY>(link(pl), f + r, p, dig);
+            if (f + take < 64) {
+                S.set_cnt(pl, f + take);
+                continue;
+            }
+            S.set_cnt(pl, 64);
+            S.readym |= 1u << pl;
+            S.set_partial(k, 0xff);
+            if (n > take) {
+                int p2 = alloc(wc, err);
+                if (p2 < 0) continue;
+                S.set_ev(p2, k);
+                S.set_cnt(p2, n - take);
+                S.set_partial(k, p2);
+                if (mine && r >= take) put<LAY>(link(p2), r - take, p, dig);
+            }
+        }
+    }
+
+    // bring one filled link back from the global arena; false if none
+    __device__ bool refill(WaveCount &wc, uint32_t &err)
+    {
+        if (S.freem == 0 || arena_fill(A) == 0) return false;
+        uint32_t a = arena_pop(A, A.qfull, qstart);
+        if (a == NIL) return false;
+        if (__lane_id() == 0) atomicSub(A.fill, 1u);
+        int l = __ffs(S.freem) - 1;
+        S.freem &= ~(1u << l);
+        uint32_t h = lane0_load(&A.hdr[a]);
+        copy_slot(link(l), __lane_id(), alink(a), __lane_id(), nd, nu);
+        S.set_ev(l, (int)(h & 0xffu));
+        S.set_cnt(l, (int)(h >> 8));
+        S.readym |= 1u << l;
+        wc.c[C_REFILLS] += 1;
+        if (!arena_push(A, A.qempty, qstart, a)) err |= ERR_CAPACITY;
+        return true;
+    }
+};
+
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) async_kernel(AsyncArgs A)
+{
+    using LAY = Layout<EMODE, MODE, SPLIT>;
+    constexpr int E = SPLIT ? 4 : 1;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const bool dig = A.digest != nullptr;
+    const int L = A.links;
+    unsigned long long *lacc = (unsigned long long *)(lds + (long)L * A.link_bytes);
+    EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
+    if (cx.lacc) {
+        lacc_zero(lacc, A.lacc_words);
+        __syncthreads();
+    }
+    Lane ln{0, 0, 0, 0};
+    WaveCount wc;
+    wc.zero();
+    const int lane = __lane_id();
+    AsyncWave W{A, lds, LAY::nd(dig), LAY::nu(dig), blockIdx.x * 2654435761u, Stash{}};
+    W.S.freem = (L >= 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
+    W.S.readym = 0;
+    W.S.clo = 0;
+    W.S.chi = 0;
+    W.S.evw = 0;
+    W.S.part = 0xFFFFFFFFu;
+    bool src_done = false;
+    int idle = 0;
+    for (;;) {
+        int l = -1;
+        if (W.S.readym) {
+            l = __ffs(W.S.readym) - 1;
+            W.S.readym &= ~(1u << l);
+        } else if (!src_done) {
+            // make_work: 64 new histories from the shared source counter
+            unsigned long long b = 0;
+            if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 64ull);
+            b = uni64(b);
+            if (b >= A.total) {
+                src_done = true;
+                continue;
+            }
+            unsigned long long gid = b + lane;
+            bool act = gid < A.total;
+            Part p;
+            if (act) {
+                int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
+                const ProbDev &P = A.probs[pi];
+                source<GEOM, MODE>(P, p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+            }
+            wc.outcomes(act, O_SOURCE);
+            wc.c[C_MAKE_WORK] += 1;
+            W.template deposit<LAY, E>(act, EV_STEP, p, dig, wc, ln.err);
+            continue;
+        } else if (W.refill(wc, ln.err)) {
+            continue;
+        } else {
+            int best = -1, bc = 0;
+#pragma unroll
+            for (int k = 0; k < E; ++k) {
+                int pl = W.S.partial(k);
+                if (pl >= 0 && W.S.cnt(pl) > bc) {
+                    bc = W.S.cnt(pl);
+                    best = k;
+                }
+            }
+            if (best < 0) {
+                // links may still be in flight to the arena; wait a bounded time
+                if (arena_fill(A) != 0 && !(ln.err & ERR_CAPACITY) && ++idle < A.spin_limit) {
+                    __builtin_amdgcn_s_sleep(8);
+                    continue;
+                }
+                break;
+            }
+            l = W.S.partial(best);
+            W.S.set_partial(best, 0xff);
+        }
+        // run the event of link l on its particles
+        int ev = W.S.ev(l);
+        int c = W.S.cnt(l);
+        bool act = lane < c;
+        Part p;
+        if (act) get<LAY>(W.link(l), lane, p, dig);
+        W.S.freem |= 1u << l;
+        int ne = EV_DEAD;
+        uint32_t out = 0;
+        if (act) {
+            const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
+            ne = run_event<GEOM, EMODE, MODE, SPLIT>(ev, P, cx, ln, p, out);
+        }
+        wc.dispatch(act);
+        wc.outcomes(act, out);
+        W.template deposit<LAY, E>(act, ne, p, dig, wc, ln.err);
+    }
+    flush_wave(A.ctl, wc, ln, A.probs, BATCH ? 0 : 1, MODE);
+    if (cx.lacc) {
+        __syncthreads();
+        lacc_flush(lacc, A.probs[0]);
+    }
+}
+
+__global__ void arena_init(AsyncArgs A)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Q = A.n_queues, N = A.n_arena;
+    if (i < N) A.next[i] = (i + Q < N) ? (uint32_t)(i + Q) : NIL;
+    if (i == 0) A.fill[0] = 0;
+    if (i < Q) {
+        A.qfull[i] = Q_EMPTY;
+        if (i < N) {
+            uint32_t tail = (uint32_t)(i + Q * ((N - 1 - i) / Q));
+            A.qempty[i] = q_pack((uint32_t)i, tail);
+        } else {
+            A.qempty[i] = Q_EMPTY;
+        }
+    }
+}
+
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
+static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
+{
+    using LAY = Layout<EMODE, MODE, SPLIT>;
+    constexpr int E = SPLIT ? 4 : 1;
+    const bool dig = a.digest != nullptr;
+    int L = a.stash_links > 0 ? a.stash_links : E + 2;
+    if (L < E + 2) L = E + 2;       // one partial per event plus two: a full stash always has a ready link
+    if (L > 16) L = 16;
+    int link_bytes = 64 * LAY::bytes(dig);
+    size_t lds = (size_t)L * link_bytes + (size_t)a.lacc_words * 8;
+    auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH>;
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int wpc = a.waves_per_cu > 0 ? std::min(a.waves_per_cu, per_cu) : per_cu;
+    long blocks = (long)a.num_cus * wpc;
+    const int Q = 64;                 // one queue per lane of a wavefront
+    int n_arena = a.arena_links > 0 ? a.arena_links : (int)std::max<long>(1024, blocks * 4);
+    size_t arena_bytes = (size_t)n_arena * link_bytes;
+    size_t need = arena_bytes + (size_t)n_arena * 8 + (size_t)Q * 16 + 1024;
+    e = ws_reserve(ws, need);
+    if (e != hipSuccess) return e;
+    AsyncArgs A;
+    A.probs = a.probs;
+    A.n_probs = a.n_probs;
+    A.prefix = a.prefix;
+    A.total = a.total;
+    A.ctl = a.ctl;
+    A.digest = (Digest *)a.digest;
+    A.links = L;
+    A.link_bytes = link_bytes;
+    A.arena = (char *)ws.ptr;
+    char *meta = (char *)ws.ptr + (arena_bytes + 255) / 256 * 256;
+    A.hdr = (uint32_t *)meta;
+    A.next = A.hdr + n_arena;
+    A.qfull = (unsigned long long *)(((uintptr_t)(A.next + n_arena) + 255) / 256 * 256);
+    A.qempty = A.qfull + Q;
+    A.fill = (uint32_t *)(A.qempty + Q);
+    A.n_arena = n_arena;
+    A.n_queues = Q;
+    A.lacc_words = a.lacc_words;
+    A.spin_limit = 1 << 20;
+    int ib = (std::max(n_arena, Q) + 255) / 256;
+    hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A);
+    st.grid_blocks = (int)blocks;
+    st.block_threads = 64;
+    st.lds_bytes = (int)lds;
+    tm.begin();
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), lds, a.stream, A);
+    tm.end();
+    st.launches += 2;
+    st.rounds = 1;
+    return hipGetLastError();
+}
+
+template <int GEOM, int EMODE, int MODE, int SPLIT>
+static hipError_t async_b(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
+{
+    return a.n_probs > 1 ? async_t<GEOM, EMODE, MODE, SPLIT, true>(a, ws, st, tm)
+                         : async_t<GEOM, EMODE, MODE, SPLIT, false>(a, ws, st, tm);
+}
+
+template <int GEOM, int EMODE, int MODE>
+static hipError_t async_s(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
+{
+    return a.split ? async_b<GEOM, EMODE, MODE, 1>(a, ws, st, tm) : async_b<GEOM, EMODE, MODE, 0>(a, ws, st, tm);
+}
+
+hipError_t launch_async(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
+{
+    if (a.emode == EMODE_CE) {
+        if (a.geom != GEOM_LATTICE || a.mode != MODE_FWD) return hipErrorInvalidValue;
+        return async_s<GEOM_LATTICE, EMODE_CE, MODE_FWD>(a, ws, st, tm);
+    }
+    if (a.geom == GEOM_BOX) {
+        if (a.mode == MODE_FWD) return async_s<GEOM_BOX, EMODE_MG, MODE_FWD>(a, ws, st, tm);
+        if (a.mode == MODE_REPLAY_A) return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_A>(a, ws, st, tm);
+        return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_B>(a, ws, st, tm);
+    }
+    if (a.mode == MODE_FWD) return async_s<GEOM_LATTICE, EMODE_MG, MODE_FWD>(a, ws, st, tm);
+    if (a.mode == MODE_REPLAY_A) return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A>(a, ws, st, tm);
+    return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B>(a, ws, st, tm);
+}
+
+}  // namespace mcx

@@ -1,0 +1,102 @@
+// History-based baseline: one lane runs one whole history, flight after
+// flight, until it ends.  Lanes of a wavefront diverge as soon as their
+// histories take different paths or lengths (the divergence thread-data
+// remapping removes, paper Sec. 2); the wavefront runs until its longest
+// history ends.
+#include "kernels.hpp"
+#include "transport.hpp"
+
+namespace mcx {
+
+template <int GEOM, int EMODE, int MODE, bool BATCH>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) naive_kernel(const ProbDev *__restrict__ probs, int n_probs,
+                                                    const unsigned long long *__restrict__ prefix,
+                                                    unsigned long long total, RunCtl *ctl, Digest *digest,
+                                                    int lacc_words)
+{
+    extern __shared__ unsigned long long lacc[];
+    EvCtx cx{probs, digest, (MODE == MODE_REPLAY_B && lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
+    if (cx.lacc) {
+        lacc_zero(lacc, lacc_words);
+        __syncthreads();
+    }
+    Lane ln{0, 0, 0, 0};
+    WaveCount wc;
+    wc.zero();
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < total; base += stride) {
+        unsigned long long gid = base + threadIdx.x;
+        bool act = gid < total;
+        Part p;
+        int ev = EV_DEAD;
+        if (act) {
+            int pi = BATCH ? find_problem(prefix, n_probs, gid) : 0;
+            const ProbDev &P = probs[pi];
+            source<GEOM, MODE>(P, p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+            ev = EV_STEP;
+        }
+        wc.outcomes(act, O_SOURCE);
+        while (__ballot(ev != EV_DEAD)) {
+            bool alive = ev != EV_DEAD;
+            uint32_t out = 0;
+            if (alive) {
+                const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
+                ev = ev_step<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+            }
+            wc.dispatch(alive);
+            wc.outcomes(alive, out);
+        }
+    }
+    flush_wave(ctl, wc, ln, probs, BATCH ? 0 : 1, MODE);
+    if (cx.lacc) {
+        __syncthreads();
+        lacc_flush(lacc, probs[0]);
+    }
+}
+
+template <int GEOM, int EMODE, int MODE, bool BATCH>
+static hipError_t launch_naive_t(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
+{
+    int bs = a.block_size > 0 ? a.block_size : 256;
+    if (bs > 256) bs = 256;
+    bs = (bs + 63) / 64 * 64;
+    unsigned long long blocks = (a.total + bs - 1) / bs;
+    unsigned long long cap = (unsigned long long)a.num_cus * 64;   // grid-stride beyond this
+    if (blocks > cap) blocks = cap;
+    if (blocks == 0) blocks = 1;
+    size_t lds = (size_t)a.lacc_words * sizeof(unsigned long long);
+    st.grid_blocks = (int)blocks;
+    st.block_threads = bs;
+    st.lds_bytes = (int)lds;
+    tm.begin();
+    hipLaunchKernelGGL((naive_kernel<GEOM, EMODE, MODE, BATCH>), dim3((unsigned)blocks), dim3(bs), lds, a.stream,
+                       a.probs, a.n_probs, a.prefix, a.total, a.ctl, (Digest *)a.digest, a.lacc_words);
+    tm.end();
+    st.launches += 1;
+    return hipGetLastError();
+}
+
+template <int GEOM, int EMODE, int MODE>
+static hipError_t naive_b(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
+{
+    return a.n_probs > 1 ? launch_naive_t<GEOM, EMODE, MODE, true>(a, st, tm)
+                         : launch_naive_t<GEOM, EMODE, MODE, false>(a, st, tm);
+}
+
+hipError_t launch_naive(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
+{
+    if (a.emode == EMODE_CE) {
+        if (a.geom != GEOM_LATTICE || a.mode != MODE_FWD) return hipErrorInvalidValue;
+        return naive_b<GEOM_LATTICE, EMODE_CE, MODE_FWD>(a, st, tm);
+    }
+    if (a.geom == GEOM_BOX) {
+        if (a.mode == MODE_FWD) return naive_b<GEOM_BOX, EMODE_MG, MODE_FWD>(a, st, tm);
+        if (a.mode == MODE_REPLAY_A) return naive_b<GEOM_BOX, EMODE_MG, MODE_REPLAY_A>(a, st, tm);
+        return naive_b<GEOM_BOX, EMODE_MG, MODE_REPLAY_B>(a, st, tm);
+    }
+    if (a.mode == MODE_FWD) return naive_b<GEOM_LATTICE, EMODE_MG, MODE_FWD>(a, st, tm);
+    if (a.mode == MODE_REPLAY_A) return naive_b<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A>(a, st, tm);
+    return naive_b<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B>(a, st, tm);
+}
+
+}  // namespace mcx

@@ -1,0 +1,804 @@
+// Event programs of analog fixed-source Monte Carlo transport.
+//
+// A history is: a source event (position, direction, group or energy from
+// the history's own random numbers), then flights.  One flight samples a
+// distance to collision, finds the nearest surface, moves the particle to
+// whichever is closer (a collision only if strictly closer) while scoring
+// the track length into the tally, and then either collides (absorb or
+// scatter) or crosses the surface (leak, reflect or enter the next cell).
+//
+// The paper (Sec. 4) runs this loop either as one monolithic "step" event
+// per flight or decomposed into separate events at the points where lanes
+// diverge.  Both forms are here: ev_step (fused) and ev_lookup, ev_move,
+// ev_surface, ev_collide (split).  Random numbers are keyed by (history,
+// flight, slot), never by event, so the two forms and every scheduler give
+// identical bits.
+//
+// Random-number slots per flight k >= 1: 0 distance; 1 absorb/scatter (MG)
+// or species (CE); 2 outgoing group (MG) or absorb/scatter (CE); 3 polar
+// cosine (MG) or centre-of-mass cosine (CE); 4 azimuth.  Source (k = 0):
+// 0-2 position, 3 polar cosine, 4 azimuth.
+#pragma once
+#include "problem.hpp"
+#include "rng_math.hpp"
+
+#pragma clang fp contract(off)
+
+namespace mcx {
+
+enum : int { EV_STEP = 0, EV_LOOKUP = 0, EV_MOVE = 1, EV_SURFACE = 2, EV_COLLIDE = 3, EV_DEAD = 7 };
+enum : uint32_t {
+    O_SOURCE = 1u << 0, O_FLIGHT = 1u << 1, O_COLL = 1u << 2, O_SCAT = 1u << 3, O_ABS = 1u << 4,
+    O_CROSS = 1u << 5, O_LEAK = 1u << 6, O_REFL = 1u << 7, O_CUT = 1u << 8, O_KILL = 1u << 9
+};
+enum : uint32_t { FATE_LEAK = 0, FATE_ABSORB = 1, FATE_CUTOFF = 2, FATE_KILLED = 3 };
+
+struct Digest {   // same layout as mcx_digest
+    long long qsum;
+    uint32_t flights, collisions, fate, pad;
+};
+
+// A particle in registers while an event runs.
+struct Part {
+    double x, y, z, u, v, w;
+    double e;         // energy (continuous energy)
+    double sigt;      // total cross section of the current flight (split events)
+    double G, L;      // backward accumulators
+    long long hq;     // this history's tally sum (digest)
+    uint32_t hid;     // history index within its problem
+    uint32_t step;    // flight counter (0 = source)
+    uint32_t gc;      // packed group | cell | inside | surface
+    uint32_t prob;    // problem index in the batch
+    uint32_t ncoll;   // collisions so far (digest)
+};
+
+// gc: bits 0-7 group, 8-17 cell x / slab, 18-27 cell y, 28 inside pin,
+// 29-30 surface to cross (split events)
+__device__ __forceinline__ int gc_group(uint32_t gc) { return (int)(gc & 0xffu); }
+__device__ __forceinline__ int gc_c0(uint32_t gc) { return (int)((gc >> 8) & 0x3ffu); }
+__device__ __forceinline__ int gc_c1(uint32_t gc) { return (int)((gc >> 18) & 0x3ffu); }
+__device__ __forceinline__ int gc_in(uint32_t gc) { return (int)((gc >> 28) & 1u); }
+__device__ __forceinline__ int gc_surf(uint32_t gc) { return (int)((gc >> 29) & 3u); }
+__device__ __forceinline__ uint32_t gc_pack(int g, int c0, int c1, int in, int surf)
+{
+    return (uint32_t)g | ((uint32_t)c0 << 8) | ((uint32_t)c1 << 18) | ((uint32_t)in << 28) | ((uint32_t)surf << 29);
+}
+
+// Per-lane accumulators of a run.
+struct Lane {
+    unsigned long long q;    // exact sum of contributions
+    unsigned long long u;    // pass A bound (single-problem runs)
+    uint32_t pieces;
+    uint32_t err;
+};
+
+// Everything an event needs besides the particle.
+struct EvCtx {
+    const ProbDev *probs;
+    Digest *digest;                  // optional per-history records
+    unsigned long long *lacc;        // pass B per-block sums (LDS) or null
+    int single;                      // one problem in the run
+};
+
+__device__ __forceinline__ double inf() { return __builtin_huge_val(); }
+
+// largest i in [0, n-1] with e[i] <= x; a point on edge i moving in the
+// negative direction belongs to cell i-1
+__device__ __forceinline__ int edge_index(const double *__restrict__ e, int n, double x, double dir)
+{
+    int i = 0;
+    if (e[0] <= x) {
+        int lo = 0, hi = n;
+        while (lo < hi) {
+            int mid = lo + ((hi - lo + 1) >> 1);
+            if (e[mid] <= x) lo = mid;
+            else hi = mid - 1;
+        }
+        i = lo;
+    }
+    if (i > n - 1) i = n - 1;
+    if (x == e[i] && dir < 0.0 && i > 0) i = i - 1;
+    return i;
+}
+
+__device__ __forceinline__ double plane_dist(double lo, double hi, double x, double u)
+{
+    double d = inf();
+    if (u > 0.0) d = (hi - x) / u;
+    else if (u < 0.0) d = (lo - x) / u;
+    if (d < 0.0) d = 0.0;
+    return d;
+}
+
+template <int GEOM>
+__device__ __forceinline__ int material(const ProbDev &P, uint32_t gc)
+{
+    if (GEOM == GEOM_BOX) return P.cmat[gc_c0(gc)];
+    if (gc_in(gc)) return P.cmat[gc_c1(gc) * P.nx + gc_c0(gc)];
+    return P.mod_mat;
+}
+
+template <int GEOM>
+__device__ __forceinline__ uint32_t locate(const ProbDev &P, double x, double y, double u, double v, int g)
+{
+    if (GEOM == GEOM_BOX) return gc_pack(g, edge_index(P.xpl, P.n_slabs, x, u), 0, 0, 0);
+    int i = edge_index(P.xpl, P.nx, x, u);
+    int j = edge_index(P.ypl, P.ny, y, v);
+    double ddx = x - P.cxs[i], ddy = y - P.cys[j];
+    int in = (((ddx * ddx) + (ddy * ddy)) < P.r2) ? 1 : 0;
+    return gc_pack(g, i, j, in, 0);
+}
+
+// Distance to the nearest bounding surface of the particle's cell; surf:
+// 0 x-plane, 1 y-plane, 2 z-plane, 3 cylinder; ties go to the lower number.
+template <int GEOM>
+__device__ __forceinline__ double surface_distance(const ProbDev &P, const Part &p, int &surf)
+{
+    double dx = inf(), dy = inf(), dz, dc = inf();
+    int c0 = gc_c0(p.gc);
+    if (GEOM == GEOM_BOX) {
+        dx = plane_dist(P.xpl[c0], P.xpl[c0 + 1], p.x, p.u);
+        dy = plane_dist(P.box_lo[1], P.box_hi[1], p.y, p.v);
+        dz = plane_dist(P.box_lo[2], P.box_hi[2], p.z, p.w);
+    } else {
+        int c1 = gc_c1(p.gc);
+        dz = plane_dist(P.box_lo[2], P.box_hi[2], p.z, p.w);
+        double ddx = p.x - P.cxs[c0], ddy = p.y - P.cys[c1];
+        double a = (p.u * p.u) + (p.v * p.v);
+        double k = (ddx * p.u) + (ddy * p.v);
+        double c = ((ddx * ddx) + (ddy * ddy)) - P.r2;
+        double disc = (k * k) - (a * c);
+        if (gc_in(p.gc)) {
+            if (a > 0.0) {
+                if (disc < 0.0) disc = 0.0;
+                dc = (root(disc) - k) / a;
+            }
+        } else {
+            dx = plane_dist(P.xpl[c0], P.xpl[c0 + 1], p.x, p.u);
+            dy = plane_dist(P.ypl[c1], P.ypl[c1 + 1], p.y, p.v);
+            if (a > 0.0 && k < 0.0 && disc >= 0.0) dc = c / (root(disc) - k);
+        }
+        if (dc < 0.0) dc = 0.0;
+    }
+    int s = 0;
+    double d = dx;
+    if (dy < d) { d = dy; s = 1; }
+    if (dz < d) { d = dz; s = 2; }
+    if (dc < d) { d = dc; s = 3; }
+    surf = s;
+    return d;
+}
+
+// ------------------------------------------------------ continuous energy
+
+struct CEXS {
+    double sa[MAX_SPECIES], ss[MAX_SPECIES], cum[MAX_SPECIES];
+};
+
+// largest i <= n-2 with g[i] <= e (e within [g[0], g[n-1]]), starting from a
+// bracket lo <= answer that ends with g[hi] > e or hi = n-1
+__device__ __forceinline__ int bisect(const double *__restrict__ g, int lo, int hi, double e)
+{
+    while (hi - lo > 1) {
+        int mid = lo + ((hi - lo) >> 1);
+        if (g[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int ce_bracket(const ProbDev &P, int s, const double *__restrict__ g, double e, double lnE)
+{
+    int n = P.grid_len;
+    int lo = 0, hi = n - 1;
+    if (P.lookup_hash) {
+        // hashed grid: uniform bins in ln E give a starting bracket that is
+        // widened until it provably contains the answer
+        double t = (lnE - P.hash_ln_lo) * P.hash_inv;
+        int b = 0;
+        if (t > 0.0) b = (t < (double)P.hash_bins) ? (int)t : P.hash_bins - 1;
+        lo = P.hash_lo[s * P.hash_bins + b];
+        hi = P.hash_hi[s * P.hash_bins + b];
+        while (lo > 0 && g[lo] > e) lo = lo - 1;
+        while (hi < n - 1 && g[hi] <= e) hi = hi + 1;
+    }
+    int i = bisect(g, lo, hi, e);
+    if (i > n - 2) i = n - 2;
+    return i;
+}
+
+// Per species: clamp E to the grid, bracket it, interpolate sigma_a and
+// sigma_s linearly in E; macroscopic total in ascending species order.
+__device__ __forceinline__ double ce_lookup(const ProbDev &P, int m, double e, CEXS &X)
+{
+    double lnE = 0.0;
+    if (P.lookup_hash) lnE = -neg_log(e);
+    double cum = 0.0;
+    const int n = P.grid_len;
+#pragma unroll
+    for (int s = 0; s < MAX_SPECIES; ++s) {
+        X.sa[s] = 0.0;
+        X.ss[s] = 0.0;
+        X.cum[s] = cum;
+        if (s < P.n_species) {
+            const double *g = P.egrid + (long)s * n;
+            const double *a = P.siga + (long)s * n;
+            const double *b = P.sigs + (long)s * n;
+            double ec = e;
+            if (ec < g[0]) ec = g[0];
+            if (ec > g[n - 1]) ec = g[n - 1];
+            int i = ce_bracket(P, s, g, ec, lnE);
+            double f = (ec - g[i]) / (g[i + 1] - g[i]);
+            double sa = a[i] + (f * (a[i + 1] - a[i]));
+            double ss = b[i] + (f * (b[i + 1] - b[i]));
+            X.sa[s] = sa;
+            X.ss[s] = ss;
+            cum = cum + (P.dens[m * P.n_species + s] * (sa + ss));
+            X.cum[s] = cum;
+        }
+    }
+    return cum;
+}
+
+// elastic scattering off a target at rest with mass ratio A, isotropic in the
+// centre-of-mass frame; returns E' and rotates the direction by the lab
+// cosine about the old direction at azimuth 2 pi xi_phi
+__device__ __forceinline__ double elastic(double A, double e, double xi_mu, double xi_phi, Part &p)
+{
+    double muc = (2.0 * xi_mu) - 1.0;
+    double D = ((A * A) + ((2.0 * A) * muc)) + 1.0;
+    double enew = (e * D) / ((A + 1.0) * (A + 1.0));
+    double mul = (1.0 + (A * muc)) / root(D);
+    double cp, sphi;
+    turn_cos_sin(xi_phi, cp, sphi);
+    double aa = root((1.0 - mul) * (1.0 + mul));
+    double u = p.u, v = p.v, w = p.w;
+    double bb = root((1.0 - w) * (1.0 + w));
+    if (bb > 1e-10) {
+        p.u = (mul * u) + ((aa * (((u * w) * cp) - (v * sphi))) / bb);
+        p.v = (mul * v) + ((aa * (((v * w) * cp) + (u * sphi))) / bb);
+        p.w = (mul * w) - ((aa * bb) * cp);
+    } else {
+        p.u = aa * cp;
+        p.v = aa * sphi;
+        p.w = (w >= 0.0) ? mul : -mul;
+    }
+    return enew;
+}
+
+__device__ __forceinline__ void isotropic(double xi_mu, double xi_phi, Part &p)
+{
+    double mu = (2.0 * xi_mu) - 1.0;
+    double c, s;
+    turn_cos_sin(xi_phi, c, s);
+    double st = root((1.0 - mu) * (1.0 + mu));
+    p.u = st * c;
+    p.v = st * s;
+    p.w = mu;
+}
+
+// ---------------------------------------------------------------- tallies
+
+template <int MODE>
+__device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long bin, double len)
+{
+    if (MODE == MODE_FWD) {
+        long long q = (long long)to_fixed(len, P.tscale);
+        if (q != 0) {
+            __hip_atomic_fetch_add(P.tally + bin, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            p.hq += q;
+            unsigned long long before = ln.q;
+            ln.q = before + (unsigned long long)q;
+            if (ln.q < before) ln.err |= ERR_OVERFLOW;
+            ln.pieces += 1;
+        }
+    } else if (MODE == MODE_REPLAY_A) {
+        p.G = p.G + (P.w[bin] * len);
+    }
+}
+
+__device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, double x0, double u)
+{
+    double t = inf();
+    if (u > 0.0) t = (e[i + 1] - x0) / u;
+    else if (u < 0.0) t = (e[i] - x0) / u;
+    if (t < 0.0) t = 0.0;
+    return t;
+}
+
+// Track-length mesh tally of one flight of length d from the current
+// position: visit the mesh cells the segment crosses; every crossing
+// parameter is measured from the flight start; ties go x, y, z.
+template <int MODE>
+__device__ __forceinline__ void walk_mesh(const ProbDev &P, Lane &ln, Part &p, double d, int g)
+{
+    const int n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2];
+    int i0 = edge_index(P.mx, n0, p.x, p.u);
+    int i1 = edge_index(P.my, n1, p.y, p.v);
+    int i2 = edge_index(P.mz, n2, p.z, p.w);
+    double t0 = axis_t(P.mx, i0, p.x, p.u);
+    double t1 = axis_t(P.my, i1, p.y, p.v);
+    double t2 = axis_t(P.mz, i2, p.z, p.w);
+    double tprev = 0.0;
+    for (;;) {
+        int a = 0;
+        double tm = t0;
+        if (t1 < tm) { tm = t1; a = 1; }
+        if (t2 < tm) { tm = t2; a = 2; }
+        double tend = (tm < d) ? tm : d;
+        long bin = (((long)g * n2 + i2) * n1 + i1) * n0 + i0;
+        score<MODE>(P, ln, p, bin, tend - tprev);
+        if (tm >= d) break;
+        if (a == 0) {
+            i0 += (p.u > 0.0) ? 1 : -1;
+            if (i0 < 0 || i0 >= n0) break;
+            t0 = (P.mx[i0 + ((p.u > 0.0) ? 1 : 0)] - p.x) / p.u;
+            if (t0 < 0.0) t0 = 0.0;
+        } else if (a == 1) {
+            i1 += (p.v > 0.0) ? 1 : -1;
+            if (i1 < 0 || i1 >= n1) break;
+            t1 = (P.my[i1 + ((p.v > 0.0) ? 1 : 0)] - p.y) / p.v;
+            if (t1 < 0.0) t1 = 0.0;
+        } else {
+            i2 += (p.w > 0.0) ? 1 : -1;
+            if (i2 < 0 || i2 >= n2) break;
+            t2 = (P.mz[i2 + ((p.w > 0.0) ? 1 : 0)] - p.z) / p.w;
+            if (t2 < 0.0) t2 = 0.0;
+        }
+        tprev = tend;
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void pass_b_add(const ProbDev &P, const EvCtx &cx, int which, int mg, long long q)
+{
+    if (q == 0) return;
+    if (cx.lacc) {
+        atomicAdd(cx.lacc + (which * P.n_mat * P.n_grp + mg), (unsigned long long)q);
+    } else {
+        unsigned long long *dst = (which == 0) ? P.SL : (which == 1) ? P.SA : P.SS;
+        __hip_atomic_fetch_add(dst + mg, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Score a flight of length d that started at the particle's position.
+template <int EMODE, int MODE>
+__device__ __forceinline__ void score_flight(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, double d, int m)
+{
+    int g = gc_group(p.gc);
+    if (MODE == MODE_REPLAY_B) {
+        pass_b_add<MODE>(P, cx, 0, m * P.n_grp + g, (long long)to_fixed(p.G * d, P.gscale));
+        return;
+    }
+    if (P.tally_kind == 0) {
+        walk_mesh<MODE>(P, ln, p, d, g);
+    } else {
+        int k = edge_index(P.eedges, P.n_ebins, p.e, 1.0);
+        score<MODE>(P, ln, p, k, d);
+    }
+    if (MODE == MODE_REPLAY_A) p.L = p.L + d;
+}
+
+// ---------------------------------------------------------------- events
+
+template <int MODE>
+__device__ __forceinline__ void finish(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t fate)
+{
+    uint32_t flights = (fate == FATE_KILLED) ? p.step - 1 : p.step;
+    uint64_t idx = P.gbase + (uint64_t)(p.hid - P.first);
+    if (MODE == MODE_FWD) {
+        if (cx.digest) {
+            Digest dg;
+            dg.qsum = p.hq;
+            dg.flights = flights;
+            dg.collisions = p.ncoll;
+            dg.fate = fate;
+            dg.pad = 0;
+            cx.digest[idx] = dg;
+        }
+    } else if (MODE == MODE_REPLAY_A) {
+        P.G[idx] = p.G;
+        double bound = ceil(fabs(p.G) * (p.L + (double)flights));
+        if (!(bound < 0x1p63)) {
+            ln.err |= ERR_BOUND;
+        } else if (cx.single) {
+            unsigned long long before = ln.u;
+            ln.u = before + (unsigned long long)bound;
+            if (ln.u < before) ln.err |= ERR_BOUND;
+        } else {
+            unsigned long long old = __hip_atomic_fetch_add(P.U, (unsigned long long)bound, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_AGENT);
+            if (old + (unsigned long long)bound < old) ln.err |= ERR_BOUND;
+        }
+    }
+}
+
+// Source event ("make_work" output): the history's start state.
+template <int GEOM, int MODE>
+__device__ __forceinline__ void source(const ProbDev &P, Part &p, uint32_t hid, uint32_t prob)
+{
+    Key k{P.key0, P.key1};
+    double x0, x1, x2, x3, x4, x5;
+    uniform_pair(k, hid, 0, 0, x0, x1);
+    uniform_pair(k, hid, 0, 1, x2, x3);
+    uniform_pair(k, hid, 0, 2, x4, x5);
+    if (P.src_kind == 0) {
+        p.x = P.src_pos[0]; p.y = P.src_pos[1]; p.z = P.src_pos[2];
+    } else if (P.src_kind == 1) {
+        p.x = P.src_lo[0] + (x0 * P.src_ext[0]);
+        p.y = P.src_lo[1] + (x1 * P.src_ext[1]);
+        p.z = P.src_lo[2] + (x2 * P.src_ext[2]);
+    } else {
+        double r = P.src_radius * root(x0);
+        double c, s;
+        turn_cos_sin(x1, c, s);
+        p.x = P.src_pos[0] + (r * c);
+        p.y = P.src_pos[1] + (r * s);
+        p.z = P.src_pos[2];
+    }
+    if (P.src_iso) {
+        isotropic(x3, x4, p);
+    } else {
+        p.u = P.src_dir[0]; p.v = P.src_dir[1]; p.w = P.src_dir[2];
+    }
+    p.e = P.e_src;
+    p.gc = locate<GEOM>(P, p.x, p.y, p.u, p.v, P.src_group);
+    p.hid = hid;
+    p.prob = prob;
+    p.step = 1;
+    p.ncoll = 0;
+    p.hq = 0;
+    p.sigt = 0.0;
+    p.L = 0.0;
+    p.G = 0.0;
+    if (MODE == MODE_REPLAY_B) p.G = P.G[P.gbase + (uint64_t)(hid - P.first)];
+}
+
+// flight cap; true if the history was killed
+template <int MODE>
+__device__ __forceinline__ bool kill_check(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    if ((long long)p.step > P.max_steps) {
+        out |= O_KILL;
+        finish<MODE>(P, cx, ln, p, FATE_KILLED);
+        return true;
+    }
+    return false;
+}
+
+template <int GEOM, int EMODE, int MODE>
+__device__ __forceinline__ int ev_lookup(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
+    int m = material<GEOM>(P, p.gc);
+    if (EMODE == EMODE_MG) {
+        p.sigt = P.sig_t[m * P.n_grp + gc_group(p.gc)];
+    } else {
+        CEXS X;
+        p.sigt = ce_lookup(P, m, p.e, X);
+    }
+    return EV_MOVE;
+}
+
+// Move to the next collision site or surface, scoring the track on the way.
+template <int GEOM, int EMODE, int MODE>
+__device__ __forceinline__ bool fly(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, double sigt, double xi0,
+                                    int m, int &surf)
+{
+    double dcol = neg_log(xi0) / sigt;
+    double dsurf = surface_distance<GEOM>(P, p, surf);
+    bool collide = dcol < dsurf;
+    double d = collide ? dcol : dsurf;
+    score_flight<EMODE, MODE>(P, cx, ln, p, d, m);
+    p.x = p.x + (d * p.u);
+    p.y = p.y + (d * p.v);
+    p.z = p.z + (d * p.w);
+    return collide;
+}
+
+// Cross the surface `surf`: snap to the plane, then leak, reflect or enter
+// the neighbouring cell.  Returns false if the particle leaked.
+template <int GEOM>
+__device__ __forceinline__ bool cross(const ProbDev &P, Part &p, int surf, uint32_t &out)
+{
+    // new values are formed in scalars and stored unconditionally, so no
+    // field of the particle is ever addressed through a computed index
+    out |= O_CROSS;
+    int g = gc_group(p.gc), c0 = gc_c0(p.gc), c1 = gc_c1(p.gc), in = gc_in(p.gc);
+    double x = p.x, y = p.y, z = p.z;
+    int face = -1;
+    if (surf == 3) {
+        in = 1 - in;
+    } else if (surf == 0) {
+        int n = (GEOM == GEOM_BOX) ? P.n_slabs : P.nx;
+        if (p.u > 0.0) {
+            x = P.xpl[c0 + 1];
+            if (c0 + 1 == n) face = 1; else c0 = c0 + 1;
+        } else {
+            x = P.xpl[c0];
+            if (c0 == 0) face = 0; else c0 = c0 - 1;
+        }
+    } else if (surf == 1) {
+        if (GEOM == GEOM_BOX) {
+            y = (p.v > 0.0) ? P.box_hi[1] : P.box_lo[1];
+            face = (p.v > 0.0) ? 3 : 2;
+        } else if (p.v > 0.0) {
+            y = P.ypl[c1 + 1];
+            if (c1 + 1 == P.ny) face = 3; else c1 = c1 + 1;
+        } else {
+            y = P.ypl[c1];
+            if (c1 == 0) face = 2; else c1 = c1 - 1;
+        }
+    } else {
+        z = (p.w > 0.0) ? P.box_hi[2] : P.box_lo[2];
+        face = (p.w > 0.0) ? 5 : 4;
+    }
+    p.x = x;
+    p.y = y;
+    p.z = z;
+    if (face >= 0) {
+        if (!((P.refl_mask >> face) & 1)) {
+            out |= O_LEAK;
+            return false;
+        }
+        out |= O_REFL;
+        int axis = face >> 1;
+        double u = p.u, v = p.v, w = p.w;
+        p.u = (axis == 0) ? -u : u;
+        p.v = (axis == 1) ? -v : v;
+        p.w = (axis == 2) ? -w : w;
+    }
+    p.gc = gc_pack(g, c0, c1, in, 0);
+    return true;
+}
+
+// Collision at the current site with the flight's random numbers xi1..xi4.
+// Returns false if the history ends (absorption or energy cutoff).
+template <int EMODE, int MODE>
+__device__ __forceinline__ bool collide(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, int m, double sigt,
+                                        const CEXS &X, double xi1, double xi2, double xi3, double xi4, uint32_t &out)
+{
+    out |= O_COLL;
+    p.ncoll += 1;
+    if (EMODE == EMODE_MG) {
+        int g = gc_group(p.gc);
+        int mg = m * P.n_grp + g;
+        double ss = P.sig_s[mg];
+        if (!((xi1 * sigt) < ss)) {
+            out |= O_ABS;
+            if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 1, mg, (long long)to_fixed(p.G, P.gscale));
+            finish<MODE>(P, cx, ln, p, FATE_ABSORB);
+            return false;
+        }
+        out |= O_SCAT;
+        if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 2, mg, (long long)to_fixed(p.G, P.gscale));
+        const double *row = P.cdf + (long)mg * P.n_grp;
+        int gn = P.n_grp - 1;
+        for (int k = 0; k < P.n_grp; ++k) {
+            if (xi2 < row[k]) {
+                gn = k;
+                break;
+            }
+        }
+        p.gc = (p.gc & ~0xffu) | (uint32_t)gn;
+        isotropic(xi3, xi4, p);
+        return true;
+    } else {
+        double target = xi1 * sigt;
+        int sp = P.n_species - 1;
+#pragma unroll
+        for (int s = MAX_SPECIES - 1; s >= 0; --s)
+            if (s < P.n_species && target < X.cum[s]) sp = s;
+        double sa = 0.0, ss = 0.0;
+#pragma unroll
+        for (int s = 0; s < MAX_SPECIES; ++s)
+            if (s == sp) { sa = X.sa[s]; ss = X.ss[s]; }
+        if (!((xi2 * (sa + ss)) < ss)) {
+            out |= O_ABS;
+            finish<MODE>(P, cx, ln, p, FATE_ABSORB);
+            return false;
+        }
+        out |= O_SCAT;
+        double enew = elastic(P.awr[sp], p.e, xi3, xi4, p);
+        if (enew < P.e_min) {
+            out |= O_CUT;
+            finish<MODE>(P, cx, ln, p, FATE_CUTOFF);
+            return false;
+        }
+        p.e = enew;
+        return true;
+    }
+}
+
+// Monolithic event: one whole flight (lookup, move with tally, collide or cross).
+template <int GEOM, int EMODE, int MODE>
+__device__ __forceinline__ int ev_step(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
+    int m = material<GEOM>(P, p.gc);
+    CEXS X;
+    double sigt;
+    if (EMODE == EMODE_MG) sigt = P.sig_t[m * P.n_grp + gc_group(p.gc)];
+    else sigt = ce_lookup(P, m, p.e, X);
+    Key k{P.key0, P.key1};
+    double xi0, xi1;
+    uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
+    int surf;
+    bool coll = fly<GEOM, EMODE, MODE>(P, cx, ln, p, sigt, xi0, m, surf);
+    out |= O_FLIGHT;
+    if (coll) {
+        double xi2, xi3, xi4, xi5;
+        uniform_pair(k, p.hid, p.step, 1, xi2, xi3);
+        uniform_pair(k, p.hid, p.step, 2, xi4, xi5);
+        if (!collide<EMODE, MODE>(P, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
+    } else {
+        if (!cross<GEOM>(P, p, surf, out)) {
+            finish<MODE>(P, cx, ln, p, FATE_LEAK);
+            return EV_DEAD;
+        }
+    }
+    p.step += 1;
+    return EV_STEP;
+}
+
+// Decomposed events ------------------------------------------------------
+
+template <int GEOM, int EMODE, int MODE>
+__device__ __forceinline__ int ev_move(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    int m = material<GEOM>(P, p.gc);
+    Key k{P.key0, P.key1};
+    double xi0, xi1;
+    uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
+    int surf;
+    bool coll = fly<GEOM, EMODE, MODE>(P, cx, ln, p, p.sigt, xi0, m, surf);
+    out |= O_FLIGHT;
+    p.gc = (p.gc & ~(3u << 29)) | ((uint32_t)surf << 29);
+    return coll ? EV_COLLIDE : EV_SURFACE;
+}
+
+template <int GEOM, int EMODE, int MODE>
+__device__ __forceinline__ int ev_surface(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    if (!cross<GEOM>(P, p, gc_surf(p.gc), out)) {
+        finish<MODE>(P, cx, ln, p, FATE_LEAK);
+        return EV_DEAD;
+    }
+    p.step += 1;
+    return EV_LOOKUP;
+}
+
+template <int GEOM, int EMODE, int MODE>
+__device__ __forceinline__ int ev_collide(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    int m = material<GEOM>(P, p.gc);
+    CEXS X;
+    if (EMODE == EMODE_CE) ce_lookup(P, m, p.e, X);
+    Key k{P.key0, P.key1};
+    double xi0, xi1, xi2, xi3, xi4, xi5;
+    uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
+    uniform_pair(k, p.hid, p.step, 1, xi2, xi3);
+    uniform_pair(k, p.hid, p.step, 2, xi4, xi5);
+    if (!collide<EMODE, MODE>(P, cx, ln, p, m, p.sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
+    p.step += 1;
+    return EV_LOOKUP;
+}
+
+template <int GEOM, int EMODE, int MODE, int SPLIT>
+__device__ __forceinline__ int run_event(int ev, const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    if (!SPLIT) return ev_step<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+    if (ev == EV_LOOKUP) return ev_lookup<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+    if (ev == EV_SURFACE) return ev_surface<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+    return ev_collide<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+}
+
+// ------------------------------------------------------- wavefront helpers
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// wave-uniform event counters (32-bit per wavefront; flushed once into the
+// 64-bit run totals)
+struct WaveCount {
+    uint32_t c[C_NUM];
+    __device__ __forceinline__ void zero()
+    {
+#pragma unroll
+        for (int i = 0; i < C_NUM; ++i) c[i] = 0;
+    }
+    __device__ __forceinline__ void outcomes(bool act, uint32_t out)
+    {
+        c[C_SOURCED] += (uint32_t)__popcll(__ballot(act && (out & O_SOURCE)));
+        c[C_FLIGHTS] += (uint32_t)__popcll(__ballot(act && (out & O_FLIGHT)));
+        c[C_COLLISIONS] += (uint32_t)__popcll(__ballot(act && (out & O_COLL)));
+        c[C_SCATTERS] += (uint32_t)__popcll(__ballot(act && (out & O_SCAT)));
+        c[C_ABSORBS] += (uint32_t)__popcll(__ballot(act && (out & O_ABS)));
+        c[C_CROSSINGS] += (uint32_t)__popcll(__ballot(act && (out & O_CROSS)));
+        c[C_LEAKS] += (uint32_t)__popcll(__ballot(act && (out & O_LEAK)));
+        c[C_REFLECTIONS] += (uint32_t)__popcll(__ballot(act && (out & O_REFL)));
+        c[C_CUTOFFS] += (uint32_t)__popcll(__ballot(act && (out & O_CUT)));
+        c[C_KILLED] += (uint32_t)__popcll(__ballot(act && (out & O_KILL)));
+    }
+    __device__ __forceinline__ void dispatch(bool act)
+    {
+        c[C_EVENTS] += (uint32_t)__popcll(__ballot(act));
+        c[C_LANE_SLOTS] += 64;
+        c[C_DISPATCHES] += 1;
+    }
+};
+
+// Flush wave counters and lane accumulators into the run control block.
+__device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, const Lane &ln, const ProbDev *probs,
+                                           int single, int mode)
+{
+    // exact wave sum of the lanes' contribution totals, with wrap detection
+    unsigned long long q = ln.q;
+    uint32_t err = ln.err;
+    unsigned long long pieces = ln.pieces;
+    unsigned long long u = ln.u;
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned long long oq = __shfl_xor(q, off);
+        unsigned long long ou = __shfl_xor(u, off);
+        uint32_t oe = __shfl_xor(err, off);
+        unsigned long long op = __shfl_xor(pieces, off);
+        unsigned long long nq = q + oq;
+        if (nq < q) err |= ERR_OVERFLOW;
+        q = nq;
+        unsigned long long nu = u + ou;
+        if (nu < u) err |= ERR_BOUND;
+        u = nu;
+        err |= oe;
+        pieces += op;
+    }
+    if (__lane_id() == 0) {
+        if (mode == MODE_FWD) {
+            unsigned long long old = atomicAdd(&ctl->qsum, q);
+            if (old + q < old || old + q >= 0x8000000000000000ull) err |= ERR_OVERFLOW;
+        }
+        if (mode == MODE_REPLAY_A && single && u) {
+            unsigned long long old = atomicAdd(probs[0].U, u);
+            if (old + u < old) err |= ERR_BOUND;
+        }
+        if (err) atomicOr(&ctl->error, err);
+#pragma unroll
+        for (int i = 0; i < C_NUM; ++i)
+            if (wc.c[i]) atomicAdd(&ctl->counters[i], (unsigned long long)wc.c[i]);
+        if (pieces) atomicAdd(&ctl->counters[C_PIECES], pieces);
+    }
+}
+
+// Flattened history id -> problem (prefix[p] <= gid < prefix[p+1]).
+__device__ __forceinline__ int find_problem(const unsigned long long *__restrict__ prefix, int n, unsigned long long gid)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= gid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Pass B per-block sums: zero at block start, add to global at block end.
+__device__ __forceinline__ void lacc_zero(unsigned long long *lacc, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) lacc[i] = 0;
+}
+
+__device__ __forceinline__ void lacc_flush(unsigned long long *lacc, const ProbDev &P)
+{
+    int mg = P.n_mat * P.n_grp;
+    for (int i = threadIdx.x; i < 3 * mg; i += blockDim.x) {
+        unsigned long long v = lacc[i];
+        if (v) {
+            unsigned long long *dst = (i < mg) ? P.SL : (i < 2 * mg) ? P.SA : P.SS;
+            atomicAdd(dst + (i % mg), v);
+        }
+    }
+}
+
+}  // namespace mcx

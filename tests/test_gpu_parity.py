@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Tallies are int64 fixed point and must match bit for bit; so must every
+scheduler-invariant counter and every per-history digest.  Sizes are small
+enough for the oracle to finish in seconds while spanning many wavefronts,
+remapping rounds and ragged tails.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_00263_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+INVARIANT = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks", "reflections",
+             "cutoffs", "killed", "pieces", "qsum", "overflow"]
+SCHEDS = [("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"), ("async", "split")]
+
+
+@pytest.fixture(scope="module")
+def mcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_00263_amd import mcx as M
+    M.lib()
+    return M
+
+
+def _check_counts(got, ref):
+    for k in INVARIANT:
+        assert got[k] == ref[k], (k, got[k], ref[k])
+
+
+def _digest(mcx, n):
+    import torch
+    return torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+
+
+def _digest_np(t, mcx):
+    return t.cpu().numpy().view(mcx.DIGEST_DTYPE)
+
+
+@pytest.fixture(scope="module")
+def cfg1(oracle):
+    d = inputs.cfg1_box(10_000)
+    return d, oracle.run(d, digest=True)
+
+
+@pytest.fixture(scope="module")
+def cfg2(oracle):
+    d = inputs.cfg2_lattice(20_000)
+    return d, oracle.run(d, digest=True)
+
+
+@pytest.mark.parametrize("sched,decomp", SCHEDS)
+def test_cfg1_box(mcx, cfg1, sched, decomp):
+    d, ref = cfg1
+    P = mcx.Problem(d)
+    dg = _digest(mcx, d["n_histories"])
+    P.run(sched=sched, decomp=decomp, digest=dg)
+    assert np.array_equal(P.tallies(), ref["tally"])
+    _check_counts(P.counters(), ref["counts"])
+    assert np.array_equal(_digest_np(dg, mcx), ref["digest"])
+
+
+@pytest.mark.parametrize("sched,decomp", SCHEDS)
+def test_cfg2_lattice(mcx, cfg2, sched, decomp):
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    dg = _digest(mcx, d["n_histories"])
+    P.run(sched=sched, decomp=decomp, digest=dg)
+    assert np.array_equal(P.tallies(), ref["tally"])
+    _check_counts(P.counters(), ref["counts"])
+    assert np.array_equal(_digest_np(dg, mcx), ref["digest"])
+
+
+@pytest.mark.parametrize("n_ebins", [100, 1000, 10000])
+def test_cfg3_pincell_ce(mcx, oracle, n_ebins):
+    d = inputs.pincell_ce(n_ebins=n_ebins, n_histories=1500)
+    ref = oracle.run(d)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        for lookup in ("binary", "hash"):
+            if n_ebins != 1000 and lookup == "hash" and sched == "naive":
+                continue
+            P.run(sched=sched, decomp=decomp, lookup=lookup)
+            assert np.array_equal(P.tallies(), ref["tally"]), (sched, decomp, lookup)
+            _check_counts(P.counters(), ref["counts"])
+
+
+def test_ce_jittered_grid_hash(mcx, oracle):
+    # arbitrary sorted grids: the hashed bracket must still give the binary-search index
+    d = inputs.pincell_ce(n_ebins=300, n_histories=800, grid_len=20000, jitter_grid=True)
+    d["hash_bins"] = 37
+    ref = oracle.run(d)
+    P = mcx.Problem(d)
+    for lookup in ("binary", "hash"):
+        P.run(sched="async", decomp="split", lookup=lookup)
+        assert np.array_equal(P.tallies(), ref["tally"])
+
+
+def test_batch_cfg5(mcx, oracle):
+    probs = inputs.cfg5_batch(n_problems=40, hist_scale=0.03)
+    refs = [oracle.run(d) for d in probs]
+    P = mcx.Problem(probs)
+    for sched, decomp in SCHEDS:
+        P.run(sched=sched, decomp=decomp)
+        for k, ref in enumerate(refs):
+            assert np.array_equal(P.tallies(k), ref["tally"]), (sched, decomp, k)
+        c = P.counters()
+        assert c["flights"] == sum(r["counts"]["flights"] for r in refs)
+    # batch[i] == problem i alone
+    for k in (0, 7, 39):
+        Q = mcx.Problem(probs[k])
+        Q.run(sched="async")
+        assert np.array_equal(Q.tallies(), refs[k]["tally"])
+
+
+def test_ranges_and_accumulate(mcx, cfg2):
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    P.run(sched="stack", first=0, n=7001)
+    P.run(sched="async", first=7001, n=0, accumulate=True)
+    assert np.array_equal(P.tallies(), ref["tally"])
+
+
+def test_single_history_and_tiny(mcx, oracle):
+    d = inputs.cfg2_lattice(1)
+    ref = oracle.run(d)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        P.run(sched=sched, decomp=decomp)
+        assert np.array_equal(P.tallies(), ref["tally"])
+    d = inputs.cfg1_box(65)
+    ref = oracle.run(d)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        P.run(sched=sched, decomp=decomp)
+        assert np.array_equal(P.tallies(), ref["tally"])
+
+
+def test_stack_small_capacity_many_rounds(mcx, cfg2):
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    for decomp in ("fused", "split"):
+        P.run(sched="stack", decomp=decomp, stack_capacity=64 * 1024 * 8, stack_threshold=4096, waves_per_cu=2)
+        assert np.array_equal(P.tallies(), ref["tally"])
+        assert P.counters()["rounds"] > 20
+
+
+def test_async_spills(mcx, cfg2):
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    P.run(sched="async", decomp="split", stash_links=6, waves_per_cu=1)
+    assert np.array_equal(P.tallies(), ref["tally"])
+    c = P.counters()
+    assert c["spills"] == c["refills"]
+
+
+def test_max_steps(mcx, oracle):
+    d = inputs.cfg2_lattice(3000)
+    d["max_steps"] = 4
+    ref = oracle.run(d, digest=True)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        dg = _digest(mcx, 3000)
+        P.run(sched=sched, decomp=decomp, digest=dg)
+        assert np.array_equal(P.tallies(), ref["tally"])
+        assert P.counters()["killed"] == ref["counts"]["killed"] > 0
+        assert np.array_equal(_digest_np(dg, mcx), ref["digest"])
+
+
+def test_overflow_reported(mcx):
+    d = inputs.cfg1_box(300)
+    d["tally_scale_log2"] = 62
+    P = mcx.Problem(d)
+    with pytest.raises(mcx.McxError) as e:
+        P.run(sched="async")
+    assert e.value.status == 5
+    with pytest.raises(mcx.McxError) as e:
+        P.tallies()
+    assert e.value.status == 6
+
+
+def test_invalid_descriptor_rejected(mcx):
+    d = inputs.cfg1_box(10)
+    d["sigma_s"] = d["sigma_t"] * 2.0
+    with pytest.raises(mcx.McxError) as e:
+        mcx.Problem(d)
+    assert e.value.status == 1
+
+
+@pytest.mark.parametrize("sched", ["naive", "stack", "async"])
+def test_backward_matches_oracle(mcx, oracle, sched):
+    d = inputs.lattice_mg(n_histories=6000)
+    nb = 51 * 51 * 20 * 7
+    w = np.random.default_rng(7).normal(size=nb)
+    ref = oracle.backward(d, w)
+    P = mcx.Problem(d)
+    P.run(sched=sched)
+    for decomp in (("fused", "split") if sched != "naive" else ("fused",)):
+        gt, gs = P.backward(w, sched=sched, decomp=decomp)
+        assert np.array_equal(gt, ref["grad_sigma_t"]), (decomp, gt[:4], ref["grad_sigma_t"][:4])
+        assert np.array_equal(gs, ref["grad_sigma_s"])
+
+
+def test_backward_batch(mcx, oracle):
+    probs = inputs.cfg5_batch(n_problems=12, hist_scale=0.02)
+    P = mcx.Problem(probs)
+    P.run(sched="async")
+    ws = [np.random.default_rng(k).normal(size=inputs.n_bins(d)) for k, d in enumerate(probs)]
+    gt, gs = P.backward(np.concatenate(ws), problem=-1, sched="async")
+    off = 0
+    for d, w in zip(probs, ws):
+        ref = oracle.backward(d, w)
+        mg = d["n_mat"] * d["n_grp"]
+        assert np.array_equal(gt[off:off + mg], ref["grad_sigma_t"])
+        assert np.array_equal(gs[off:off + mg], ref["grad_sigma_s"])
+        off += mg
+
+
+def test_full_size_lattice_sampled(mcx, oracle):
+    """1e6 lattice histories in the benchmark's launch configuration: every
+    history's digest is checked for a seeded sample against the oracle run
+    one history at a time; bins, counters and digests must add up."""
+    d = inputs.cfg2_lattice(1_000_000)
+    P = mcx.Problem(d)
+    dg = _digest(mcx, d["n_histories"])
+    P.run(sched="async", decomp="fused", digest=dg)
+    tally = P.tallies()
+    c = P.counters()
+    g = _digest_np(dg, mcx)
+    assert int(tally.sum()) == c["qsum"] == int(g["qsum"].sum())
+    assert int(g["flights"].sum()) == c["flights"]
+    assert int(g["collisions"].sum()) == c["collisions"]
+    rng = np.random.default_rng(2024)
+    sample = np.sort(rng.choice(d["n_histories"], size=1500, replace=False))
+    sample = np.concatenate([sample, [0, d["n_histories"] - 1]])
+    for h in sample:
+        ref = oracle.run(d, int(h), int(h) + 1, digest=True, threads=1)
+        assert ref["digest"][0] == g[h], h
