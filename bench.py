@@ -1,0 +1,173 @@
+"""Benchmark: particle histories per second on one MI355X.
+
+Workload: the multigroup pin lattice (17x17 pins, 7 materials x 7 groups,
+reflective box, uniform source, 51x51x20x7 mesh tally), 1e6 histories.
+One step = one forward transport run of all histories through the selected
+thread-data-remapping scheduler, with inputs resident in HBM.  Also
+reported: the other schedulers (naive one-lane-per-history baseline, stack,
+async; fused and split events), the score-function backward/forward time
+ratio, the batched 256-problem launch, the roofline of the dominant kernel
+and the CPU oracle timed on the host cores over the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--sched async|stack|naive] [--decomp fused|split]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+N_HIST = 1_000_000
+
+
+def algorithmic_bytes(c: dict) -> int:
+    """Bytes the method itself must touch: one int64 tally update per scored
+    piece, Sigma_t per flight, Sigma_s and one transfer-CDF entry per
+    collision (8 bytes each)."""
+    return 8 * c["pieces"] + 8 * c["flights"] + 16 * c["collisions"]
+
+
+def timed_runs(P, reps, **kw):
+    import torch
+    times, kms = [], []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.run(time_kernels=True, **kw)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        kms.append(P.counters()["kernel_ms"])
+    return times, kms
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--sched", default="async")
+    ap.add_argument("--decomp", default="fused")
+    ap.add_argument("--no-extras", action="store_true", help="time only the headline configuration")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (histories would shard "
+              "across GPUs with one int64 all-reduce of the tallies; not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2506_00263_amd import inputs, mcx
+
+    torch.cuda.set_device(0)
+    d = inputs.cfg2_lattice(N_HIST)
+    P = mcx.Problem(d)
+    stream = torch.cuda.current_stream()
+
+    # headline: warmup, then exactly `steps` timed steps
+    for _ in range(args.warmup):
+        P.run(sched=args.sched, decomp=args.decomp, stream=stream)
+    torch.cuda.synchronize()
+    kernel_ms = 0.0
+    launches = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        P.run(sched=args.sched, decomp=args.decomp, stream=stream, time_kernels=True)
+        c = P.counters()
+        kernel_ms += c["kernel_ms"]
+        launches += c["rounds"] if args.sched == "stack" else 1
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    value = N_HIST / (wall / args.steps)
+    c = P.counters()
+    tally = P.tallies()
+
+    # roofline of the dominant kernel: algorithmic bytes per launch over the
+    # mean launch duration measured with HIP events on the run's stream
+    per_launch_bytes = algorithmic_bytes(c) / max(1, launches // args.steps)
+    mean_launch_ms = kernel_ms / max(1, launches)
+    achieved = per_launch_bytes / (mean_launch_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "kernel": {"async": "async_kernel", "stack": "stack_round", "naive": "naive_kernel"}[args.sched],
+                "mean_launch_ms": mean_launch_ms, "bytes_per_launch": per_launch_bytes}
+
+    out = {
+        "metric": "particle histories/sec on 1 GPU (stack vs async TDR); backward/forward time ratio",
+        "value": value, "unit": "histories/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "multigroup 17x17 pin lattice, 7 materials x 7 groups, 1e6 histories, "
+                               "51x51x20x7 mesh tally", "histories": N_HIST,
+                   "scheduler": args.sched, "decomposition": args.decomp},
+        "roofline": roofline,
+        "counters": {k: c[k] for k in ("flights", "collisions", "crossings", "pieces", "events", "lane_slots",
+                                       "dispatches", "spills", "refills", "rounds", "grid_blocks",
+                                       "block_threads", "lds_bytes")},
+        "active_lane_frac": c["events"] / max(1, c["lane_slots"]),
+    }
+
+    if not args.no_extras:
+        sched = {}
+        for s, dc in (("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"),
+                      ("async", "split")):
+            P.run(sched=s, decomp=dc)
+            ts, kms = timed_runs(P, 5, sched=s, decomp=dc)
+            cc = P.counters()
+            sched[f"{s}_{dc}"] = {"hist_per_s": N_HIST / float(np.median(ts)), "ms": 1e3 * float(np.median(ts)),
+                                  "kernel_ms": float(np.median(kms)),
+                                  "active_lane_frac": cc["events"] / max(1, cc["lane_slots"]),
+                                  "launches": cc["launches"]}
+            if not np.array_equal(P.tallies(), tally):
+                raise SystemExit(f"tally mismatch between schedulers: {s}/{dc}")
+        out["schedulers"] = sched
+        # backward: two replays (pass A, pass B) of the same histories
+        w = np.random.default_rng(4).normal(size=inputs.n_bins(d))
+        P.run(sched=args.sched, decomp=args.decomp)
+        fwd = []
+        bwd = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            P.run(sched=args.sched, decomp=args.decomp)
+            torch.cuda.synchronize()
+            fwd.append(time.perf_counter() - t1)
+            t1 = time.perf_counter()
+            P.backward(w, sched=args.sched, decomp=args.decomp)
+            torch.cuda.synchronize()
+            bwd.append(time.perf_counter() - t1)
+        out["backward"] = {"fwd_ms": 1e3 * float(np.median(fwd)), "bwd_ms": 1e3 * float(np.median(bwd)),
+                           "bwd_fwd_ratio": float(np.median(bwd) / np.median(fwd))}
+        # batched: 256 problems of uneven size in one launch
+        probs = inputs.cfg5_batch()
+        B = mcx.Problem(probs)
+        nb = sum(p["n_histories"] for p in probs)
+        bres = {}
+        for s in ("async", "stack", "naive"):
+            B.run(sched=s)
+            ts, kms = timed_runs(B, 3, sched=s)
+            bres[s] = {"hist_per_s": nb / float(np.median(ts)), "ms": 1e3 * float(np.median(ts))}
+        out["batched"] = {"problems": len(probs), "histories": nb, **bres}
+
+    if not args.no_cpu:
+        from oracle import oracle as O
+        threads = min(16, os.cpu_count() or 1)
+        t1 = time.perf_counter()
+        ref = O.run(d, threads=threads)
+        cpu_s = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": N_HIST / cpu_s, "unit": "histories/s", "cores": threads, "kind": "oracle",
+                               "sample": f"all {N_HIST} histories of the benchmark workload ({cpu_s:.1f} s)"}
+        out["oracle_match"] = bool(np.array_equal(ref["tally"], tally))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
