@@ -316,6 +316,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
     W.S.evw = 0;
     W.S.part = 0xFFFFFFFFu;
     bool src_done = false;
+    unsigned long long res_next = 0, res_end = 0;   // reserved source ids
     int idle = 0;
     for (;;) {
         int l = -1;
@@ -323,16 +324,23 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
             l = __ffs(W.S.readym) - 1;
             W.S.readym &= ~(1u << l);
         } else if (!src_done) {
-            // make_work: 64 new histories from the shared source counter
-            unsigned long long b = 0;
-            if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 64ull);
-            b = uni64(b);
-            if (b >= A.total) {
-                src_done = true;
-                continue;
+            // make_work: 64 new histories, reserved 256 at a time from the
+            // shared source counter (one atomic per four calls)
+            if (res_next >= res_end) {
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 256ull);
+                b = uni64(b);
+                if (b >= A.total) {
+                    src_done = true;
+                    continue;
+                }
+                res_next = b;
+                res_end = b + 256ull < A.total ? b + 256ull : A.total;
             }
+            unsigned long long b = res_next;
+            res_next += 64ull;
             unsigned long long gid = b + lane;
-            bool act = gid < A.total;
+            bool act = gid < res_end;
             Part p;
             if (act) {
                 int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;

@@ -12,16 +12,27 @@
 //
 // Round r reads bank r&1 and writes bank (r+1)&1.  Stack sizes rotate over
 // three counter sets so that consecutive launches can be queued without a
-// host round trip: round r reads sizes[r%3], pops with heads[r%3], pushes
-// with sizes[(r+1)%3], and clears the sets round r+1 will need
-// (sizes[(r+2)%3], heads[(r+1)%3]).  The host polls a done flag (first round
-// that finds no input and no source left) every few rounds.
+// host round trip: round r reads sizes[r%3], pushes with sizes[(r+1)%3], and
+// clears sizes[(r+2)%3] for round r+1.  The host polls a done flag (first
+// round that finds no input and no source left) every few rounds.
+//
+// MI355X layout: each stack is cut into stripes with separate counters (see
+// NSTRIPE); the input chunks of a round are dealt to wavefronts in a fixed
+// order because the input stacks do not change during the round.
 #include <algorithm>
 
 #include "bank.hpp"
 #include "kernels.hpp"
 
 namespace mcx {
+
+// Stripes per event stack.  Stripe s < NSTRIPE-1 holds up to `scap`
+// particles; the last stripe is the overflow stripe with room for every live
+// particle, so a push never fails.  Each stripe has its own counter on its
+// own 128-byte line: on MI355X a device-scope atomic on one hot address
+// serialises every wavefront of all eight XCDs, striping spreads them.
+constexpr int NSTRIPE = 64;
+constexpr int CTR_STRIDE = 32;   // 32 x 4 bytes = one counter per 128-byte line
 
 struct StackArgs {
     const ProbDev *probs;
@@ -30,24 +41,32 @@ struct StackArgs {
     unsigned long long total;
     RunCtl *ctl;
     Digest *digest;
-    char *bank[2];              // [event][nd doubles, nu words] x cap
-    long cap;
-    long region_bytes;          // bytes of one event stack
-    unsigned int *sizes;        // [3][E]
-    unsigned int *heads;        // [3][E]
-    unsigned int threshold;
+    char *bank[2];              // [event][stripe] regions
+    long scap;                  // particles per ordinary stripe
+    long ocap;                  // particles in the overflow stripe
+    long stripe_bytes;          // bytes of one ordinary stripe region
+    long event_bytes;           // bytes of one event (all stripes)
+    unsigned int *sizes;        // [3][E][NSTRIPE] counters, CTR_STRIDE apart
+    unsigned long long threshold;
     int lacc_words;
 };
 
-__device__ __forceinline__ unsigned int wave_claim(unsigned int *ctr, unsigned int n)
+__device__ __forceinline__ unsigned int *stripe_ctr(const StackArgs &A, int set, int E, int e, int s)
 {
-    unsigned int b = 0;
-    if (__lane_id() == 0) b = atomicAdd(ctr, n);
-    return __builtin_amdgcn_readfirstlane(b);
+    return A.sizes + ((long)(set * E + e) * NSTRIPE + s) * CTR_STRIDE;
 }
 
+__device__ __forceinline__ SoA stripe_soa(const StackArgs &A, char *bank, int e, int s, int nd)
+{
+    long cap = (s == NSTRIPE - 1) ? A.ocap : A.scap;
+    return SoA{bank + (long)e * A.event_bytes + (long)s * A.stripe_bytes, cap, nd};
+}
+
+// push the wavefront's survivors onto the output stacks of their next
+// events: per destination one ballot, one prefix count and one atomic on the
+// wavefront's home stripe (a second one on the overflow stripe if full)
 template <class LAY, int E>
-__device__ __forceinline__ void push(const StackArgs &A, char *bank, unsigned int *size_out, bool act, int ne,
+__device__ __forceinline__ void push(const StackArgs &A, char *bank, int set, int home, bool act, int ne,
                                      const Part &p, bool dig, uint32_t &err)
 {
 #pragma unroll
@@ -57,18 +76,53 @@ __device__ __forceinline__ void push(const StackArgs &A, char *bank, unsigned in
         if (mask == 0) continue;
         unsigned int cnt = (unsigned int)__popcll(mask);
         unsigned int b = 0;
-        if (__lane_id() == 0) b = atomicAdd(&size_out[k], cnt);
+        if (__lane_id() == 0) b = atomicAdd(stripe_ctr(A, set, E, k, home), cnt);
         b = __builtin_amdgcn_readfirstlane(b);
-        if (mine) {
-            unsigned long slot = (unsigned long)b + lane_rank(mask);
-            if (slot < (unsigned long)A.cap) {
-                SoA s{bank + (long)k * A.region_bytes, A.cap, LAY::nd(dig)};
-                put<LAY>(s, (long)slot, p, dig);
-            } else {
-                err |= ERR_CAPACITY;
+        unsigned long slot = (unsigned long)b + lane_rank(mask);
+        bool spill = (unsigned long)b + cnt > (unsigned long)A.scap;
+        unsigned int ob = 0;
+        if (spill) {
+            unsigned long first_over = (unsigned long)b > (unsigned long)A.scap ? (unsigned long)b
+                                                                                : (unsigned long)A.scap;
+            unsigned int n_over = (unsigned int)((unsigned long)b + cnt - first_over);
+            if (__lane_id() == 0) ob = atomicAdd(stripe_ctr(A, set, E, k, NSTRIPE - 1), n_over);
+            ob = __builtin_amdgcn_readfirstlane(ob);
+            if (mine && slot >= (unsigned long)A.scap) {
+                unsigned long o = (unsigned long)ob + (slot - first_over);
+                if (o < (unsigned long)A.ocap) put<LAY>(stripe_soa(A, bank, k, NSTRIPE - 1, LAY::nd(dig)), (long)o, p, dig);
+                else err |= ERR_CAPACITY;
             }
         }
+        if (mine && slot < (unsigned long)A.scap)
+            put<LAY>(stripe_soa(A, bank, k, home, LAY::nd(dig)), (long)slot, p, dig);
     }
+}
+
+// wave-uniform view of one event's input stripes: chunk counts and prefixes
+struct StripeView {
+    unsigned int n_lane;         // this lane's stripe size (clamped)
+    unsigned int excl, incl;     // exclusive / inclusive chunk prefix of this lane's stripe
+    unsigned int chunks;         // total chunks of the event
+};
+
+__device__ __forceinline__ StripeView stripe_view(const StackArgs &A, int set, int E, int e)
+{
+    const int lane = __lane_id();
+    unsigned int n = __hip_atomic_load(stripe_ctr(A, set, E, e, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned int cap = (lane == NSTRIPE - 1) ? (unsigned int)A.ocap : (unsigned int)A.scap;
+    n = n < cap ? n : cap;
+    unsigned int c = (n + 63u) >> 6;
+    unsigned int incl = c;
+    for (int off = 1; off < 64; off <<= 1) {
+        unsigned int o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+    }
+    StripeView v;
+    v.n_lane = n;
+    v.incl = incl;
+    v.excl = incl - c;
+    v.chunks = __shfl(incl, 63);
+    return v;
 }
 
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
@@ -78,21 +132,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
     constexpr int E = SPLIT ? 4 : 1;
     extern __shared__ unsigned long long lacc[];
     const bool dig = A.digest != nullptr;
-    unsigned int *size_in = A.sizes + (round % 3) * E;
-    unsigned int *head = A.heads + (round % 3) * E;
-    unsigned int *size_out = A.sizes + ((round + 1) % 3) * E;
+    const int set_in = round % 3, set_out = (round + 1) % 3;
     char *bin = A.bank[round & 1];
     char *bout = A.bank[(round + 1) & 1];
-    if (blockIdx.x == 0 && threadIdx.x < E) {
-        A.sizes[((round + 2) % 3) * E + threadIdx.x] = 0;
-        A.heads[((round + 1) % 3) * E + threadIdx.x] = 0;
-    }
-    // no input and no source left: the previous round finished the run
-    unsigned int n_any = 0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) n_any |= size_in[e];
-    unsigned long long cursor = __hip_atomic_load(&A.ctl->src_cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (n_any == 0 && cursor >= A.total) {
+    if (blockIdx.x == 0 && threadIdx.x < E * NSTRIPE)
+        __hip_atomic_store(&A.sizes[((long)((round + 2) % 3) * E * NSTRIPE + threadIdx.x) * CTR_STRIDE], 0u,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int lane = __lane_id();
+    const unsigned int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const unsigned int n_waves = (gridDim.x * blockDim.x) >> 6;
+    const int home = (int)(wave % (NSTRIPE - 1));
+    // every history has ended (wavefronts add their ended histories once, at
+    // the end of a round, so this count can only reach the total when no
+    // particle is left anywhere): the run is over
+    unsigned long long ended = __hip_atomic_load(&A.ctl->completed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ended >= A.total) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && A.ctl->done_round == 0) A.ctl->done_round = (unsigned)round + 1;
         return;
     }
@@ -104,58 +158,64 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
     Lane ln{0, 0, 0, 0};
     WaveCount wc;
     wc.zero();
-    const int lane = __lane_id();
-    // drain the input stacks
+    // pop: the input stacks are read-only during a round, so the 64-particle
+    // chunks are dealt to wavefronts in a fixed order (no pop atomics)
 #pragma unroll 1
     for (int e = 0; e < E; ++e) {
-        unsigned int n_in = size_in[e];
-        if (n_in > (unsigned int)A.cap) n_in = (unsigned int)A.cap;
-        SoA sin{bin + (long)e * A.region_bytes, A.cap, LAY::nd(dig)};
-        for (;;) {
-            unsigned int base = wave_claim(&head[e], 64);
-            if (base >= n_in) break;
-            bool act = base + lane < n_in;
+        StripeView v = stripe_view(A, set_in, E, e);
+        for (unsigned int c = wave; c < v.chunks; c += n_waves) {
+            uint64_t in_stripe = __ballot(c < v.incl);
+            int s = __ffsll((unsigned long long)in_stripe) - 1;
+            unsigned int excl = __shfl(v.excl, s);
+            unsigned int ns = __shfl(v.n_lane, s);
+            unsigned int base = (c - excl) * 64u;
+            bool act = base + (unsigned int)lane < ns;
             Part p;
             int ne = EV_DEAD;
             uint32_t out = 0;
             if (act) {
-                get<LAY>(sin, (long)(base + lane), p, dig);
+                get<LAY>(stripe_soa(A, bin, e, s, LAY::nd(dig)), (long)(base + lane), p, dig);
                 const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
                 ne = run_event<GEOM, EMODE, MODE, SPLIT>(e, P, cx, ln, p, out);
             }
             wc.dispatch(act);
             wc.outcomes(act, out);
-            push<LAY, E>(A, bout, size_out, act, ne, p, dig, ln.err);
+            push<LAY, E>(A, bout, set_out, home, act, ne, p, dig, ln.err);
         }
     }
-    // make_work: source new histories until the fullest output stack passes
-    // the threshold or the source is exhausted
+    // make_work: source new histories (256 per claim) until the fullest
+    // output stack passes the threshold or the source is exhausted
     for (;;) {
         unsigned long long cur = __hip_atomic_load(&A.ctl->src_cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur >= A.total) break;
-        unsigned int fullest = 0;
+        unsigned long long fullest = 0;
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-            unsigned int s = __hip_atomic_load(&size_out[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            fullest = s > fullest ? s : fullest;
+            unsigned long long t = __hip_atomic_load(stripe_ctr(A, set_out, E, k, lane), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+            fullest = t > fullest ? t : fullest;
         }
         if (fullest >= A.threshold) break;
         unsigned long long b = 0;
-        if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 64ull);
+        if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 256ull);
         b = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(b >> 32)) << 32) |
             (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)b);
         if (b >= A.total) break;
-        unsigned long long gid = b + lane;
-        bool act = gid < A.total;
-        Part p;
-        if (act) {
-            int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
-            const ProbDev &P = A.probs[pi];
-            source<GEOM, MODE>(P, p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+        for (int j = 0; j < 4; ++j) {
+            unsigned long long gid = b + 64ull * j + lane;
+            bool act = gid < A.total;
+            if (b + 64ull * j >= A.total) break;
+            Part p;
+            if (act) {
+                int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
+                const ProbDev &P = A.probs[pi];
+                source<GEOM, MODE>(P, p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+            }
+            wc.outcomes(act, O_SOURCE);
+            wc.c[C_MAKE_WORK] += 1;
+            push<LAY, E>(A, bout, set_out, home, act, EV_STEP, p, dig, ln.err);
         }
-        wc.outcomes(act, O_SOURCE);
-        wc.c[C_MAKE_WORK] += 1;
-        push<LAY, E>(A, bout, size_out, act, EV_STEP, p, dig, ln.err);
     }
     flush_wave(A.ctl, wc, ln, A.probs, BATCH ? 0 : 1, MODE);
     if (cx.lacc) {
@@ -173,7 +233,8 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     const int block = 256;
     int wpc = a.waves_per_cu > 0 ? a.waves_per_cu : 16;
     long blocks = std::max(1L, (long)a.num_cus * wpc / (block / 64));
-    long slack = 2 * (blocks * (block / 64) * 64 + 64);
+    long waves = blocks * (block / 64);
+    long slack = 2 * (waves * 256 + 64);          // particles sourced past the threshold
     long cap = a.stack_capacity > 0 ? (long)a.stack_capacity : (long)a.total + slack;
     const long cap_max = 1L << 24;
     if (cap > cap_max + slack) cap = cap_max + slack;
@@ -181,11 +242,14 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     long thr;
     if (a.stack_threshold > 0) thr = (long)a.stack_threshold;
     else if (cap >= (long)a.total + slack) thr = cap;
-    else thr = std::max(64L, (cap - slack) / E);
-    if (thr > 0xFFFFFFFFL) thr = 0xFFFFFFFFL;
-    long region = (long)LAY::bytes(dig) * cap;
-    region = (region + 255) / 256 * 256;
-    size_t need = (size_t)region * E * 2 + 256 * 2;
+    else thr = std::max(256L, (cap - slack) / E);
+    long scap = ((2 * cap) / (NSTRIPE - 1) + 63) / 64 * 64 + 64;
+    long ocap = cap;
+    long bytes = LAY::bytes(dig);
+    long stripe_bytes = (scap * bytes + 255) / 256 * 256;
+    long event_bytes = stripe_bytes * (NSTRIPE - 1) + (ocap * bytes + 255) / 256 * 256;
+    size_t ctr_bytes = (size_t)3 * E * NSTRIPE * CTR_STRIDE * 4;
+    size_t need = (size_t)event_bytes * E * 2 + ctr_bytes;
     hipError_t e = ws_reserve(ws, need);
     if (e != hipSuccess) return e;
     StackArgs A;
@@ -196,14 +260,15 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.ctl = a.ctl;
     A.digest = (Digest *)a.digest;
     A.bank[0] = (char *)ws.ptr;
-    A.bank[1] = (char *)ws.ptr + (size_t)region * E;
-    A.cap = cap;
-    A.region_bytes = region;
-    A.sizes = (unsigned int *)((char *)ws.ptr + (size_t)region * E * 2);
-    A.heads = A.sizes + 32;
-    A.threshold = (unsigned int)thr;
+    A.bank[1] = (char *)ws.ptr + (size_t)event_bytes * E;
+    A.scap = scap;
+    A.ocap = ocap;
+    A.stripe_bytes = stripe_bytes;
+    A.event_bytes = event_bytes;
+    A.sizes = (unsigned int *)((char *)ws.ptr + (size_t)event_bytes * E * 2);
+    A.threshold = (unsigned long long)thr;
     A.lacc_words = a.lacc_words;
-    e = hipMemsetAsync(A.sizes, 0, 512, a.stream);
+    e = hipMemsetAsync(A.sizes, 0, ctr_bytes, a.stream);
     if (e != hipSuccess) return e;
     size_t lds = (size_t)a.lacc_words * 8;
     st.grid_blocks = (int)blocks;
@@ -236,7 +301,7 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
             break;
         }
         if (batch < 64) batch *= 2;
-        if (round > (1 << 30)) return hipErrorLaunchTimeOut;
+        if (round > (1 << 26)) return hipErrorLaunchTimeOut;
     }
     return hipSuccess;
 }

@@ -764,6 +764,9 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
             if (old + u < old) err |= ERR_BOUND;
         }
         if (err) atomicOr(&ctl->error, err);
+        unsigned long long ended = (unsigned long long)wc.c[C_LEAKS] + wc.c[C_ABSORBS] + wc.c[C_CUTOFFS] +
+                                   wc.c[C_KILLED];
+        if (ended) atomicAdd(&ctl->completed, ended);
 #pragma unroll
         for (int i = 0; i < C_NUM; ++i)
             if (wc.c[i]) atomicAdd(&ctl->counters[i], (unsigned long long)wc.c[i]);
