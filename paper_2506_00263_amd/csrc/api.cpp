@@ -55,11 +55,13 @@ struct mcx_problem_s {
     std::vector<size_t> gacc_off;
     size_t gacc_words = 0;
     unsigned int *h_flag = nullptr;       // pinned
+    RunCtl *h_ctl = nullptr;              // pinned
     Workspace ws;
     // state
     bool tallies_valid = false;
     bool have_forward = false;
     std::vector<uint64_t> last_first, last_count;
+    unsigned long long passa_u = 0;       // single-problem pass A bound (summed stripes)
     mcx_counters_t counters{};
     std::string err;
 };
@@ -331,6 +333,7 @@ static mcx_status upload(mcx_problem_t h)
     HIP_TRY(h, hipMalloc(&h->d_prefix, sizeof(unsigned long long) * (h->n + 1)));
     HIP_TRY(h, hipMalloc(&h->d_ctl, sizeof(RunCtl)));
     HIP_TRY(h, hipHostMalloc((void **)&h->h_flag, 64, hipHostMallocDefault));
+    HIP_TRY(h, hipHostMalloc((void **)&h->h_ctl, sizeof(RunCtl), hipHostMallocDefault));
     // host image of the problem table (static part)
     char *base = (char *)h->blob;
     h->pd.resize(h->n);
@@ -456,6 +459,7 @@ extern "C" void mcx_destroy_problem(mcx_problem_t h)
     if (h->d_w) hipFree(h->d_w);
     if (h->d_gacc) hipFree(h->d_gacc);
     if (h->h_flag) hipHostFree(h->h_flag);
+    if (h->h_ctl) hipHostFree(h->h_ctl);
     if (h->ws.ptr) hipFree(h->ws.ptr);
     delete h;
 }
@@ -533,7 +537,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     HIP_TRY(h, hipMemcpyAsync(h->d_probs, h->pd.data(), sizeof(ProbDev) * h->n, hipMemcpyHostToDevice, stream));
     HIP_TRY(h, hipMemcpyAsync(h->d_prefix, prefix.data(), sizeof(unsigned long long) * (h->n + 1),
                               hipMemcpyHostToDevice, stream));
-    RunCtl ctl;
+    RunCtl &ctl = *h->h_ctl;   // pinned host image of the control block
     std::memset(&ctl, 0, sizeof ctl);
     ctl.total = total;
     HIP_TRY(h, hipMemcpyAsync(h->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, stream));
@@ -575,37 +579,47 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     }
     HIP_TRY(h, hipMemcpyAsync(&ctl, h->d_ctl, sizeof ctl, hipMemcpyDeviceToHost, stream));
     HIP_TRY(h, hipStreamSynchronize(stream));
+    unsigned long long tot[C_NUM] = {0};
+    unsigned __int128 qsum = 0;
+    for (int s = 0; s < CTL_STRIPES; ++s) {
+        for (int i = 0; i < C_NUM; ++i) tot[i] += ctl.stripe[s].c[i];
+        qsum += ctl.stripe[s].c[C_QSUM];
+    }
+    // overflow rule: the exact total of all contributions reached 2^63
+    if (qsum >= ((unsigned __int128)1 << 63)) ctl.error |= ERR_OVERFLOW;
     mcx_counters_t &c = h->counters;
     std::memset(&c, 0, sizeof c);
-    c.sourced = ctl.counters[C_SOURCED];
-    c.flights = ctl.counters[C_FLIGHTS];
-    c.collisions = ctl.counters[C_COLLISIONS];
-    c.scatters = ctl.counters[C_SCATTERS];
-    c.absorbs = ctl.counters[C_ABSORBS];
-    c.crossings = ctl.counters[C_CROSSINGS];
-    c.leaks = ctl.counters[C_LEAKS];
-    c.reflections = ctl.counters[C_REFLECTIONS];
-    c.cutoffs = ctl.counters[C_CUTOFFS];
-    c.killed = ctl.counters[C_KILLED];
-    c.pieces = ctl.counters[C_PIECES];
-    c.qsum = ctl.qsum;
+    c.sourced = tot[C_SOURCED];
+    c.flights = tot[C_FLIGHTS];
+    c.collisions = tot[C_COLLISIONS];
+    c.scatters = tot[C_SCATTERS];
+    c.absorbs = tot[C_ABSORBS];
+    c.crossings = tot[C_CROSSINGS];
+    c.leaks = tot[C_LEAKS];
+    c.reflections = tot[C_REFLECTIONS];
+    c.cutoffs = tot[C_CUTOFFS];
+    c.killed = tot[C_KILLED];
+    c.pieces = tot[C_PIECES];
+    c.qsum = (uint64_t)qsum;
     c.overflow = (ctl.error & ERR_OVERFLOW) ? 1 : 0;
-    c.events = ctl.counters[C_EVENTS];
-    c.lane_slots = ctl.counters[C_LANE_SLOTS];
-    c.dispatches = ctl.counters[C_DISPATCHES];
-    c.spills = ctl.counters[C_SPILLS];
-    c.refills = ctl.counters[C_REFILLS];
-    c.make_work = ctl.counters[C_MAKE_WORK];
+    c.events = tot[C_EVENTS];
+    c.lane_slots = tot[C_LANE_SLOTS];
+    c.dispatches = tot[C_DISPATCHES];
+    c.spills = tot[C_SPILLS];
+    c.refills = tot[C_REFILLS];
+    c.make_work = tot[C_MAKE_WORK];
     c.rounds = st.rounds;
     c.launches = st.launches;
     c.kernel_ms = tm.total_ms();
     c.grid_blocks = st.grid_blocks;
     c.block_threads = st.block_threads;
     c.lds_bytes = st.lds_bytes;
+    h->passa_u = tot[C_PASSA_U];
     *err_out = ctl.error;
     if (ctl.error & ERR_CAPACITY) return fail(h, MCX_E_CAPACITY, "scheduler capacity exhausted (stack or link arena)");
-    if (ctl.counters[C_SOURCED] != total)
-        return fail(h, MCX_E_DEVICE, "internal: sourced %llu of %llu histories", ctl.counters[C_SOURCED], total);
+    if (tot[C_SOURCED] != total || tot[C_COMPLETED] != total)
+        return fail(h, MCX_E_DEVICE, "internal: sourced %llu, ended %llu of %llu histories", tot[C_SOURCED],
+                    tot[C_COMPLETED], total);
     return MCX_OK;
 }
 
@@ -706,6 +720,7 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
     if (err & ERR_BOUND) return fail(h, MCX_E_OVERFLOW, "score-function bound does not fit 64 bits");
     std::vector<unsigned long long> acc(h->gacc_words);
     HIP_TRY(h, hipMemcpy(acc.data(), h->d_gacc, h->gacc_words * 8, hipMemcpyDeviceToHost));
+    if (h->n == 1) acc[h->gacc_off[0]] += h->passa_u;   // single-problem runs sum U per wavefront
     std::vector<int> scale(h->n, 0);
     for (int k = 0; k < h->n; ++k) {
         scale[k] = 62 - bit_length(acc[h->gacc_off[k]]);

@@ -54,21 +54,29 @@ struct ProbDev {
     int32_t acc_off, pad;            // offset of this problem in per-wave LDS sums
 };
 
+enum Counter : int {
+    C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,
+    C_CUTOFFS, C_KILLED, C_PIECES, C_EVENTS, C_LANE_SLOTS, C_DISPATCHES, C_SPILLS, C_REFILLS, C_MAKE_WORK,
+    C_COMPLETED, C_QSUM, C_PASSA_U, C_NUM
+};
+constexpr int C_WAVE = C_COMPLETED;   // entries counted per wavefront (32-bit)
+
+// Run totals are kept in CTL_STRIPES copies, one 256-byte block each; a
+// wavefront adds into copy (wave id mod CTL_STRIPES) and the host sums the
+// copies.  One shared copy would serialise every wavefront's atomics.
+constexpr int CTL_STRIPES = 64;
+struct CtlStripe {
+    unsigned long long c[32];        // Counter entries, padded to 256 bytes
+};
+
 // Per-run control block in device memory.
 struct RunCtl {
     unsigned long long src_cursor;   // next flattened history id to source
     unsigned long long total;        // flattened histories of the run
-    unsigned long long completed;    // histories finished
     unsigned int error;              // bit 0 capacity, bit 1 overflow, bit 2 pass-A bound
-    unsigned int done_round;         // stack: round that found no work (+1)
-    unsigned long long qsum;         // exact total of all contributions
-    unsigned long long counters[24]; // see Counter
-};
-
-enum Counter : int {
-    C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,
-    C_CUTOFFS, C_KILLED, C_PIECES, C_EVENTS, C_LANE_SLOTS, C_DISPATCHES, C_SPILLS, C_REFILLS, C_MAKE_WORK,
-    C_NUM
+    unsigned int done_round;         // stack: round that found every history ended (+1)
+    unsigned long long pad[13];
+    CtlStripe stripe[CTL_STRIPES];
 };
 
 enum : unsigned int { ERR_CAPACITY = 1u, ERR_OVERFLOW = 2u, ERR_BOUND = 4u };

@@ -145,7 +145,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
     // every history has ended (wavefronts add their ended histories once, at
     // the end of a round, so this count can only reach the total when no
     // particle is left anywhere): the run is over
-    unsigned long long ended = __hip_atomic_load(&A.ctl->completed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long ended = __hip_atomic_load(&A.ctl->stripe[lane].c[C_COMPLETED], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    for (int off = 32; off > 0; off >>= 1) ended += __shfl_xor(ended, off);
     if (ended >= A.total) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && A.ctl->done_round == 0) A.ctl->done_round = (unsigned)round + 1;
         return;

@@ -704,11 +704,11 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 // wave-uniform event counters (32-bit per wavefront; flushed once into the
 // 64-bit run totals)
 struct WaveCount {
-    uint32_t c[C_NUM];
+    uint32_t c[C_WAVE];
     __device__ __forceinline__ void zero()
     {
 #pragma unroll
-        for (int i = 0; i < C_NUM; ++i) c[i] = 0;
+        for (int i = 0; i < C_WAVE; ++i) c[i] = 0;
     }
     __device__ __forceinline__ void outcomes(bool act, uint32_t out)
     {
@@ -731,7 +731,8 @@ struct WaveCount {
     }
 };
 
-// Flush wave counters and lane accumulators into the run control block.
+// Flush wave counters and lane accumulators into this wavefront's stripe of
+// the run control block (only non-zero entries: one atomic each).
 __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, const Lane &ln, const ProbDev *probs,
                                            int single, int mode)
 {
@@ -755,22 +756,24 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
         pieces += op;
     }
     if (__lane_id() == 0) {
-        if (mode == MODE_FWD) {
-            unsigned long long old = atomicAdd(&ctl->qsum, q);
-            if (old + q < old || old + q >= 0x8000000000000000ull) err |= ERR_OVERFLOW;
+        const unsigned int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+        unsigned long long *S = ctl->stripe[wave % CTL_STRIPES].c;
+        if (mode == MODE_FWD && q) {
+            unsigned long long old = atomicAdd(&S[C_QSUM], q);
+            if (old + q < old) err |= ERR_OVERFLOW;
         }
         if (mode == MODE_REPLAY_A && single && u) {
-            unsigned long long old = atomicAdd(probs[0].U, u);
+            unsigned long long old = atomicAdd(&S[C_PASSA_U], u);
             if (old + u < old) err |= ERR_BOUND;
         }
         if (err) atomicOr(&ctl->error, err);
         unsigned long long ended = (unsigned long long)wc.c[C_LEAKS] + wc.c[C_ABSORBS] + wc.c[C_CUTOFFS] +
                                    wc.c[C_KILLED];
-        if (ended) atomicAdd(&ctl->completed, ended);
+        if (ended) atomicAdd(&S[C_COMPLETED], ended);
 #pragma unroll
-        for (int i = 0; i < C_NUM; ++i)
-            if (wc.c[i]) atomicAdd(&ctl->counters[i], (unsigned long long)wc.c[i]);
-        if (pieces) atomicAdd(&ctl->counters[C_PIECES], pieces);
+        for (int i = 0; i < C_WAVE; ++i)
+            if (wc.c[i]) atomicAdd(&S[i], (unsigned long long)wc.c[i]);
+        if (pieces) atomicAdd(&S[C_PIECES], pieces);
     }
 }
 
