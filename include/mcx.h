@@ -159,7 +159,9 @@ typedef struct {
     void *digest;             /* optional device array of mcx_digest, one per
                                  history (all problems, in order)               */
     int32_t time_kernels;     /* 1: time every launch with HIP events           */
-    int32_t reserved[7];
+    int32_t force_spill;      /* async, testing: send every k-th filled link
+                                 through the global arena (0 = never)           */
+    int32_t reserved[6];
 } mcx_run_opts;
 
 /* one record per history, written by runs that pass opts.digest */

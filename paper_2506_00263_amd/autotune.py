@@ -1,0 +1,88 @@
+"""Autotuner for the remapping schedulers.
+
+Grid search over the tuning knobs of a scheduler (resident wavefronts per
+CU, stash links, stack capacity/threshold) on a short calibration run, timed
+with HIP events inside the library.  Knobs never change results: every
+candidate's tally is checked against the first candidate's.  The best choice
+is cached per (problem class, scheduler, decomposition, device).
+"""
+from __future__ import annotations
+
+import hashlib
+import json
+import os
+
+import numpy as np
+
+from . import mcx
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_autotune_cache.json")
+
+
+def candidates(sched: str, decomp: str) -> list:
+    events = 4 if decomp == "split" else 1
+    if sched == "async":
+        out = []
+        for wpc in (0, 8, 12):
+            for links in sorted({events + 1, events + 2, events + 3}):
+                out.append(dict(waves_per_cu=wpc, stash_links=links))
+        return out
+    if sched == "stack":
+        return [dict(waves_per_cu=w) for w in (4, 8, 12, 16, 20)]
+    return [dict(block_size=b) for b in (64, 128, 256)]
+
+
+def problem_key(P: "mcx.Problem", sched: str, decomp: str, lookup: str, device: str) -> str:
+    d0 = P.descs[0]
+    shape = dict(n=P.n_problems, geometry=int(d0["geometry"]), energy=int(d0["energy_mode"]),
+                 tally=int(d0["tally_kind"]), n_mat=int(d0["n_mat"]), n_grp=int(d0["n_grp"]),
+                 hist=int(sum(d["n_histories"] for d in P.descs)), sched=sched, decomp=decomp, lookup=lookup,
+                 device=device)
+    return hashlib.sha1(json.dumps(shape, sort_keys=True).encode()).hexdigest()[:16]
+
+
+def _load_cache() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save_cache(c: dict) -> None:
+    tmp = CACHE + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, CACHE)
+
+
+def tune(P: "mcx.Problem", sched: str = "async", decomp: str = "fused", lookup: str = "binary",
+         calib_histories: int | None = None, reps: int = 2, use_cache: bool = True, device: str = "gpu0",
+         stream=None) -> dict:
+    """Return the fastest knob setting for this problem and scheduler."""
+    key = problem_key(P, sched, decomp, lookup, device)
+    cache = _load_cache() if use_cache else {}
+    if key in cache:
+        return cache[key]["best"]
+    run_kw = dict(sched=sched, decomp=decomp, lookup=lookup, stream=stream)
+    if P.n_problems == 1 and calib_histories:
+        run_kw.update(first=0, n=min(calib_histories, P.descs[0]["n_histories"]))
+    results = []
+    ref = None
+    for cand in candidates(sched, decomp):
+        times = []
+        for _ in range(reps + 1):
+            P.run(time_kernels=True, **run_kw, **cand)
+            times.append(P.counters()["kernel_ms"])
+        tally = [P.tallies(k) for k in range(P.n_problems)]
+        if ref is None:
+            ref = tally
+        elif not all(np.array_equal(a, b) for a, b in zip(ref, tally)):
+            raise RuntimeError(f"tuning knob changed the result: {cand}")
+        results.append((float(np.median(times[1:])), cand))
+    results.sort(key=lambda r: r[0])
+    best = results[0][1]
+    if use_cache:
+        cache[key] = dict(best=best, table=[dict(ms=t, **c) for t, c in results])
+        _save_cache(cache)
+    return best

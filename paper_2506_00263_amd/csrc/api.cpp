@@ -122,6 +122,21 @@ static int host_bracket(const double *g, int n, double e)
     return i;
 }
 
+// n / (e[n] - e[0]) if the n+1 edges are uniform (in ln e when logscale) to
+// within a tenth of a cell, else 0.
+static double uniform_inverse(const double *e, int n, bool logscale)
+{
+    if (n < 1) return 0.0;
+    if (logscale && !(e[0] > 0.0)) return 0.0;
+    auto f = [&](int i) { return logscale ? std::log(e[i]) : e[i]; };
+    double lo = f(0), hi = f(n);
+    double w = (hi - lo) / n;
+    if (!(w > 0.0)) return 0.0;
+    for (int i = 1; i < n; ++i)
+        if (std::fabs(f(i) - (lo + w * i)) > 0.1 * w) return 0.0;
+    return (double)n / (hi - lo);
+}
+
 // Validate one descriptor and deep-copy its arrays.
 static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int k, HostProblem &hp)
 {
@@ -398,6 +413,17 @@ static mcx_status upload(mcx_problem_t h)
         P.my = (const double *)(base + o.my);
         P.mz = (const double *)(base + o.mz);
         P.eedges = (const double *)(base + o.ee);
+        // guesses for uniform mesh axes and log-uniform energy bins (only a
+        // starting point: the device corrects it against the edges)
+        const std::vector<double> *axes[3] = {&hp.mx, &hp.my, &hp.mz};
+        for (int a = 0; a < 3; ++a) {
+            const std::vector<double> &e = *axes[a];
+            int n = (int)e.size() - 1;
+            P.mesh_lo[a] = e[0];
+            P.mesh_inv[a] = uniform_inverse(e.data(), n, false);
+        }
+        P.ebin_lnlo = hp.eedges[0] > 0.0 ? std::log(hp.eedges[0]) : 0.0;
+        P.ebin_inv = d.tally_kind == MCX_TALLY_ENERGY ? uniform_inverse(hp.eedges.data(), d.n_ebins, true) : 0.0;
         P.tscale = std::ldexp(1.0, d.tally_scale_log2);
         P.tally = h->d_tally + h->tally_off[k];
         P.key0 = (uint32_t)d.seed;
@@ -514,7 +540,7 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
     if (o.sched == MCX_SCHED_NAIVE && o.decomp == MCX_DECOMP_SPLIT)
         return fail(h, MCX_E_INVALID_ARG, "the naive scheduler runs whole histories (fused only)");
     if (o.stack_capacity < 0 || o.stack_threshold < 0 || o.stash_links < 0 || o.arena_links < 0 ||
-        o.waves_per_cu < 0 || o.block_size < 0)
+        o.waves_per_cu < 0 || o.block_size < 0 || o.force_spill < 0)
         return fail(h, MCX_E_INVALID_ARG, "negative tuning value");
     return MCX_OK;
 }
@@ -562,6 +588,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.stack_threshold = o.stack_threshold;
     a.stash_links = o.stash_links;
     a.arena_links = o.arena_links;
+    a.force_spill = o.force_spill;
 
     LaunchStats st;
     LaunchTimer tm;

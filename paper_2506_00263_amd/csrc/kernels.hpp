@@ -62,6 +62,7 @@ struct LaunchArgs {
     int waves_per_cu;                      // stack / async
     long long stack_capacity, stack_threshold;
     int stash_links, arena_links;
+    int force_spill;                       // async, testing
 };
 
 struct LaunchStats {

@@ -38,6 +38,10 @@ struct ProbDev {
     // tally
     int32_t mesh_n[3], n_ebins;
     const double *mx, *my, *mz, *eedges;
+    // index guesses for (nearly) uniform edges: cell ~ (x - lo) * inv, then
+    // corrected against the edges; inv = 0 means search instead
+    double mesh_lo[3], mesh_inv[3];
+    double ebin_lnlo, ebin_inv;      // energy bins uniform in ln E
     double tscale;                   // 2^tally_scale_log2
     unsigned long long *tally;       // this problem's bins
     // random numbers and histories of the current run

@@ -27,8 +27,10 @@ __device__ __forceinline__ uint4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     uint32_t k0 = k.k0, k1 = k.k1;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = M0 * c0, hi0 = __umulhi(M0, c0);
-        uint32_t lo1 = M1 * c2, hi1 = __umulhi(M1, c2);
+        uint64_t p0 = (uint64_t)M0 * c0;     // one 32x32->64 multiply each
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         uint32_t n0 = hi1 ^ c1 ^ k0;
         uint32_t n2 = hi0 ^ c3 ^ k1;
         c0 = n0;

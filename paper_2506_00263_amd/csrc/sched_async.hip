@@ -46,6 +46,7 @@ struct AsyncArgs {
     int n_arena, n_queues;
     int lacc_words;
     int spin_limit;
+    int force_spill;             // testing: spill every k-th filled link
 };
 
 constexpr uint32_t NIL = 0xFFFFFFFFu;
@@ -186,6 +187,7 @@ struct AsyncWave {
     int nd, nu;
     uint32_t qstart;
     Stash S;
+    uint32_t tick;               // filled links so far (forced spills)
     __device__ SoA link(int l) const { return SoA{lds + (long)l * A.link_bytes, 64, nd}; }
     __device__ SoA alink(uint32_t a) const { return SoA{A.arena + (long)a * A.link_bytes, 64, nd}; }
 
@@ -259,6 +261,15 @@ struct AsyncWave {
             S.set_cnt(pl, 64);
             S.readym |= 1u << pl;
             S.set_partial(k, 0xff);
+            if (A.force_spill > 0 && ++tick % (uint32_t)A.force_spill == 0) {
+                if (spill(pl)) {
+                    S.readym &= ~(1u << pl);
+                    S.freem |= 1u << pl;
+                    wc.c[C_SPILLS] += 1;
+                } else {
+                    err |= ERR_CAPACITY;
+                }
+            }
             if (n > take) {
                 int p2 = alloc(wc, err);
                 if (p2 < 0) continue;
@@ -308,7 +319,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
     WaveCount wc;
     wc.zero();
     const int lane = __lane_id();
-    AsyncWave W{A, lds, LAY::nd(dig), LAY::nu(dig), blockIdx.x * 2654435761u, Stash{}};
+    AsyncWave W{A, lds, LAY::nd(dig), LAY::nu(dig), blockIdx.x * 2654435761u, Stash{}, 0u};
     W.S.freem = (L >= 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
     W.S.readym = 0;
     W.S.clo = 0;
@@ -421,8 +432,11 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     using LAY = Layout<EMODE, MODE, SPLIT>;
     constexpr int E = SPLIT ? 4 : 1;
     const bool dig = a.digest != nullptr;
-    int L = a.stash_links > 0 ? a.stash_links : E + 2;
-    if (L < E + 2) L = E + 2;       // one partial per event plus two: a full stash always has a ready link
+    // one partial link per event plus one: a stash with no free link then
+    // always holds a ready link to spill.  Split events default to one more,
+    // which keeps spills rare.
+    int L = a.stash_links > 0 ? a.stash_links : (SPLIT ? E + 2 : E + 1);
+    if (L < E + 1) L = E + 1;
     if (L > 16) L = 16;
     int link_bytes = 64 * LAY::bytes(dig);
     size_t lds = (size_t)L * link_bytes + (size_t)a.lacc_words * 8;
@@ -459,6 +473,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.n_queues = Q;
     A.lacc_words = a.lacc_words;
     A.spin_limit = 1 << 20;
+    A.force_spill = a.force_spill;
     int ib = (std::max(n_arena, Q) + 255) / 256;
     hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A);
     st.grid_blocks = (int)blocks;

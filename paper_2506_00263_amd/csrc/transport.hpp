@@ -101,6 +101,30 @@ __device__ __forceinline__ int edge_index(const double *__restrict__ e, int n, d
     return i;
 }
 
+// The same index from a guess g (any value in [0, n-1]): walk up while the
+// next edge is <= x, down while this edge is > x; the result is the largest
+// i in [0, n-1] with e[i] <= x (0 if none), whatever the guess.
+__device__ __forceinline__ int edge_index_from(const double *__restrict__ e, int n, double x, double dir, int g)
+{
+    int i = g < 0 ? 0 : (g > n - 1 ? n - 1 : g);
+    while (i < n - 1 && e[i + 1] <= x) i = i + 1;
+    while (i > 0 && e[i] > x) i = i - 1;
+    if (x == e[i] && dir < 0.0 && i > 0) i = i - 1;
+    return i;
+}
+
+// cell index on an axis whose edges are (nearly) uniform: one multiply for
+// the guess, usually no correction step
+__device__ __forceinline__ int edge_index_guess(const double *__restrict__ e, int n, double x, double dir, double lo,
+                                                double inv)
+{
+    if (inv == 0.0) return edge_index(e, n, x, dir);
+    double t = (x - lo) * inv;
+    int g = 0;
+    if (t > 0.0) g = (t < (double)n) ? (int)t : n - 1;
+    return edge_index_from(e, n, x, dir, g);
+}
+
 __device__ __forceinline__ double plane_dist(double lo, double hi, double x, double u)
 {
     double d = inf();
@@ -313,9 +337,9 @@ template <int MODE>
 __device__ __forceinline__ void walk_mesh(const ProbDev &P, Lane &ln, Part &p, double d, int g)
 {
     const int n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2];
-    int i0 = edge_index(P.mx, n0, p.x, p.u);
-    int i1 = edge_index(P.my, n1, p.y, p.v);
-    int i2 = edge_index(P.mz, n2, p.z, p.w);
+    int i0 = edge_index_guess(P.mx, n0, p.x, p.u, P.mesh_lo[0], P.mesh_inv[0]);
+    int i1 = edge_index_guess(P.my, n1, p.y, p.v, P.mesh_lo[1], P.mesh_inv[1]);
+    int i2 = edge_index_guess(P.mz, n2, p.z, p.w, P.mesh_lo[2], P.mesh_inv[2]);
     double t0 = axis_t(P.mx, i0, p.x, p.u);
     double t1 = axis_t(P.my, i1, p.y, p.v);
     double t2 = axis_t(P.mz, i2, p.z, p.w);
@@ -373,7 +397,15 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const EvCtx &cx, 
     if (P.tally_kind == 0) {
         walk_mesh<MODE>(P, ln, p, d, g);
     } else {
-        int k = edge_index(P.eedges, P.n_ebins, p.e, 1.0);
+        int k;
+        if (P.ebin_inv != 0.0) {
+            double t = ((-neg_log(p.e)) - P.ebin_lnlo) * P.ebin_inv;
+            int g = 0;
+            if (t > 0.0) g = (t < (double)P.n_ebins) ? (int)t : P.n_ebins - 1;
+            k = edge_index_from(P.eedges, P.n_ebins, p.e, 1.0, g);
+        } else {
+            k = edge_index(P.eedges, P.n_ebins, p.e, 1.0);
+        }
         score<MODE>(P, ln, p, k, d);
     }
     if (MODE == MODE_REPLAY_A) p.L = p.L + d;

@@ -56,7 +56,7 @@ class RunOpts(C.Structure):
         ("first_history", C.c_uint64), ("n_histories", C.c_uint64), ("stack_capacity", C.c_int64),
         ("stack_threshold", C.c_int64), ("stash_links", C.c_int32), ("arena_links", C.c_int32),
         ("waves_per_cu", C.c_int32), ("block_size", C.c_int32), ("hip_stream", C.c_void_p), ("digest", C.c_void_p),
-        ("time_kernels", C.c_int32), ("reserved", C.c_int32 * 7),
+        ("time_kernels", C.c_int32), ("force_spill", C.c_int32), ("reserved", C.c_int32 * 6),
     ]
 
 
@@ -186,7 +186,7 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
 
 def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, first=0, n=0, stack_capacity=0,
              stack_threshold=0, stash_links=0, arena_links=0, waves_per_cu=0, block_size=0, stream=None,
-             digest=None, time_kernels=False) -> RunOpts:
+             digest=None, time_kernels=False, force_spill=0) -> RunOpts:
     o = RunOpts()
     o.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     o.decomp = DECOMP[decomp] if isinstance(decomp, str) else int(decomp)
@@ -203,6 +203,7 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
     o.hip_stream = _stream_handle(stream)
     o.digest = _ptr(digest)
     o.time_kernels = int(bool(time_kernels))
+    o.force_spill = int(force_spill)
     return o
 
 

@@ -150,12 +150,20 @@ def test_stack_small_capacity_many_rounds(mcx, cfg2):
 
 
 def test_async_spills(mcx, cfg2):
+    # the smallest stash (one partial link per event plus one) forces links
+    # through the global arena; results must not change
     d, ref = cfg2
     P = mcx.Problem(d)
-    P.run(sched="async", decomp="split", stash_links=6, waves_per_cu=1)
+    P.run(sched="async", decomp="split", stash_links=5, waves_per_cu=1)
     assert np.array_equal(P.tallies(), ref["tally"])
     c = P.counters()
     assert c["spills"] == c["refills"]
+    # every k-th filled link goes through the lock-free global queues
+    for decomp, k, wpc in (("fused", 1, 0), ("fused", 3, 2), ("split", 2, 0), ("split", 1, 1)):
+        P.run(sched="async", decomp=decomp, force_spill=k, waves_per_cu=wpc)
+        assert np.array_equal(P.tallies(), ref["tally"]), (decomp, k)
+        c = P.counters()
+        assert c["spills"] == c["refills"] > 100, (decomp, k, c["spills"])
 
 
 def test_max_steps(mcx, oracle):
