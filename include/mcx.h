@@ -161,7 +161,11 @@ typedef struct {
     int32_t time_kernels;     /* 1: time every launch with HIP events           */
     int32_t force_spill;      /* async, testing: send every k-th filled link
                                  through the global arena (0 = never)           */
-    int32_t reserved[6];
+    int32_t consolidate;      /* async: a drained wavefront whose stash holds
+                                 few particles hands them to the arena, where
+                                 other wavefronts merge them into full links:
+                                 0 = library default, 1 = on, 2 = off           */
+    int32_t reserved[5];
 } mcx_run_opts;
 
 /* one record per history, written by runs that pass opts.digest */

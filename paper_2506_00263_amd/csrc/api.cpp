@@ -542,6 +542,7 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
     if (o.stack_capacity < 0 || o.stack_threshold < 0 || o.stash_links < 0 || o.arena_links < 0 ||
         o.waves_per_cu < 0 || o.block_size < 0 || o.force_spill < 0)
         return fail(h, MCX_E_INVALID_ARG, "negative tuning value");
+    if (o.consolidate < 0 || o.consolidate > 2) return fail(h, MCX_E_INVALID_ARG, "bad consolidate");
     return MCX_OK;
 }
 
@@ -589,6 +590,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.stash_links = o.stash_links;
     a.arena_links = o.arena_links;
     a.force_spill = o.force_spill;
+    a.consolidate = o.consolidate;
 
     LaunchStats st;
     LaunchTimer tm;

@@ -63,6 +63,7 @@ struct LaunchArgs {
     long long stack_capacity, stack_threshold;
     int stash_links, arena_links;
     int force_spill;                       // async, testing
+    int consolidate;                       // async: 0 default, 1 on, 2 off
 };
 
 struct LaunchStats {

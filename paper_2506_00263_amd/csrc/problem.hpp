@@ -79,7 +79,9 @@ struct RunCtl {
     unsigned long long total;        // flattened histories of the run
     unsigned int error;              // bit 0 capacity, bit 1 overflow, bit 2 pass-A bound
     unsigned int done_round;         // stack: round that found every history ended (+1)
-    unsigned long long pad[13];
+    unsigned int active;             // async: wavefronts still running
+    unsigned int pad0;
+    unsigned long long pad[12];
     CtlStripe stripe[CTL_STRIPES];
 };
 

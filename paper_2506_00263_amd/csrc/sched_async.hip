@@ -47,9 +47,11 @@ struct AsyncArgs {
     int lacc_words;
     int spin_limit;
     int force_spill;             // testing: spill every k-th filled link
+    int consolidate;             // drained sparse stashes are handed to the arena and merged
 };
 
 constexpr uint32_t NIL = 0xFFFFFFFFu;
+constexpr int DONATE_BELOW = 32;   // a drained stash with fewer particles is donated
 constexpr unsigned long long Q_EMPTY = ~0ull;
 constexpr unsigned long long Q_CLAIMED = 0xFFFFFFFEFFFFFFFEull;
 __device__ __forceinline__ uint32_t q_head(unsigned long long q) { return (uint32_t)(q >> 32); }
@@ -59,32 +61,26 @@ __device__ __forceinline__ unsigned long long q_pack(uint32_t h, uint32_t t)
     return ((unsigned long long)h << 32) | (unsigned long long)t;
 }
 
-__device__ __forceinline__ unsigned long long uni64(unsigned long long v)
-{
-    return ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(v >> 32)) << 32) |
-           (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)v);
-}
-
 __device__ __forceinline__ unsigned long long q_exchange(unsigned long long *slot, unsigned long long v)
 {
     unsigned long long old = 0;
     if (__lane_id() == 0)
         old = __hip_atomic_exchange(slot, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    return uni64(old);
+    return first_lane_u64(old);
 }
 
 __device__ __forceinline__ unsigned long long q_peek(unsigned long long *slot)
 {
     unsigned long long v = 0;
     if (__lane_id() == 0) v = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return uni64(v);
+    return first_lane_u64(v);
 }
 
-__device__ __forceinline__ uint32_t lane0_load(const uint32_t *p)
+__device__ __forceinline__ uint32_t lane0_load(uint32_t *p)
 {
     uint32_t v = 0;
     if (__lane_id() == 0) v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __builtin_amdgcn_readfirstlane(v);
+    return first_lane_u32(v);
 }
 
 __device__ __forceinline__ void lane0_store(uint32_t *p, uint32_t v)
@@ -281,8 +277,12 @@ struct AsyncWave {
         }
     }
 
-    // bring one filled link back from the global arena; false if none
-    __device__ bool refill(WaveCount &wc, uint32_t &err)
+    // bring one link back from the global arena; false if the arena had
+    // none.  A full link is run as it is; with consolidation a partial one
+    // (a donated remnant) is packed into the partial link of its event, so
+    // remnants of many wavefronts merge into full links.
+    template <class LAY, int E>
+    __device__ bool refill(bool dig, WaveCount &wc, uint32_t &err)
     {
         if (S.freem == 0 || arena_fill(A) == 0) return false;
         uint32_t a = arena_pop(A, A.qfull, qstart);
@@ -292,11 +292,35 @@ struct AsyncWave {
         S.freem &= ~(1u << l);
         uint32_t h = lane0_load(&A.hdr[a]);
         copy_slot(link(l), __lane_id(), alink(a), __lane_id(), nd, nu);
-        S.set_ev(l, (int)(h & 0xffu));
-        S.set_cnt(l, (int)(h >> 8));
-        S.readym |= 1u << l;
         wc.c[C_REFILLS] += 1;
         if (!arena_push(A, A.qempty, qstart, a)) err |= ERR_CAPACITY;
+        int ev = (int)(h & 0xffu), c = (int)(h >> 8);
+        if (!A.consolidate || c == 64) {
+            S.set_ev(l, ev);
+            S.set_cnt(l, c);
+            S.readym |= 1u << l;
+            return true;
+        }
+        bool act = __lane_id() < c;
+        Part p;
+        if (act) get<LAY>(link(l), __lane_id(), p, dig);
+        S.freem |= 1u << l;
+        deposit<LAY, E>(act, ev, p, dig, wc, err);
+        return true;
+    }
+
+    // leave: one less live wavefront.  Donors publish their links before
+    // they count themselves out, so when the last one finds the arena
+    // non-empty those links are all visible; it stays (returns true) and
+    // counts itself back in.
+    __device__ bool last_with_work(RunCtl *ctl)
+    {
+        unsigned int old = 0;
+        if (__lane_id() == 0) old = __hip_atomic_fetch_sub(&ctl->active, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        old = first_lane_u32(old);
+        if (old != 1u) return false;
+        if (arena_fill(A) == 0) return false;
+        if (__lane_id() == 0) __hip_atomic_fetch_add(&ctl->active, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         return true;
     }
 };
@@ -327,8 +351,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
     W.S.evw = 0;
     W.S.part = 0xFFFFFFFFu;
     bool src_done = false;
-    unsigned long long res_next = 0, res_end = 0;   // reserved source ids
+    bool may_donate = true;
     int idle = 0;
+    unsigned long long res_next = 0, res_end = 0;   // reserved source ids
     for (;;) {
         int l = -1;
         if (W.S.readym) {
@@ -340,7 +365,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
             if (res_next >= res_end) {
                 unsigned long long b = 0;
                 if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 256ull);
-                b = uni64(b);
+                b = first_lane_u64(b);
                 if (b >= A.total) {
                     src_done = true;
                     continue;
@@ -362,28 +387,64 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
             wc.c[C_MAKE_WORK] += 1;
             W.template deposit<LAY, E>(act, EV_STEP, p, dig, wc, ln.err);
             continue;
-        } else if (W.refill(wc, ln.err)) {
+        } else if (W.template refill<LAY, E>(dig, wc, ln.err)) {
             continue;
         } else {
-            int best = -1, bc = 0;
+            // drained: run the fullest partial link; a sparse stash is donated
+            // to the arena instead so that the particles of many wavefronts
+            // are packed into few full links
+            int best = -1, bc = 0, tot = 0;
 #pragma unroll
             for (int k = 0; k < E; ++k) {
                 int pl = W.S.partial(k);
-                if (pl >= 0 && W.S.cnt(pl) > bc) {
-                    bc = W.S.cnt(pl);
-                    best = k;
+                if (pl >= 0) {
+                    int c = W.S.cnt(pl);
+                    tot += c;
+                    if (c > bc) {
+                        bc = c;
+                        best = k;
+                    }
                 }
             }
-            if (best < 0) {
-                // links may still be in flight to the arena; wait a bounded time
-                if (arena_fill(A) != 0 && !(ln.err & ERR_CAPACITY) && ++idle < A.spin_limit) {
-                    __builtin_amdgcn_s_sleep(8);
-                    continue;
+            if (!A.consolidate) {
+                if (tot > 0) {
+                    l = W.S.partial(best);
+                    W.S.set_partial(best, 0xff);
+                } else {
+                    // links may still be in flight to the arena; wait a bounded time
+                    if (arena_fill(A) != 0 && !(ln.err & ERR_CAPACITY) && ++idle < A.spin_limit) {
+                        __builtin_amdgcn_s_sleep(8);
+                        continue;
+                    }
+                    break;
+                }
+            } else if (tot > 0 && (tot >= DONATE_BELOW || !may_donate)) {
+                l = W.S.partial(best);
+                W.S.set_partial(best, 0xff);
+            } else {
+                if (tot > 0) {
+#pragma unroll
+                    for (int k = 0; k < E; ++k) {
+                        int pl = W.S.partial(k);
+                        if (pl < 0) continue;
+                        if (W.spill(pl)) {
+                            W.S.set_partial(k, 0xff);
+                            W.S.freem |= 1u << pl;
+                            wc.c[C_SPILLS] += 1;
+                        } else {
+                            ln.err |= ERR_CAPACITY;
+                        }
+                    }
+                    if (ln.err & ERR_CAPACITY) may_donate = false;   // keep what could not be donated
+                    if (!may_donate) continue;
+                }
+                if (W.last_with_work(A.ctl)) {
+                    may_donate = false;
+                    if (++idle < A.spin_limit) continue;
+                    ln.err |= ERR_CAPACITY;   // arena count never drained: report, do not spin
                 }
                 break;
             }
-            l = W.S.partial(best);
-            W.S.set_partial(best, 0xff);
         }
         // run the event of link l on its particles
         int ev = W.S.ev(l);
@@ -409,9 +470,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
     }
 }
 
-__global__ void arena_init(AsyncArgs A)
+__global__ void arena_init(AsyncArgs A, unsigned int waves)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) A.ctl->active = waves;
     const int Q = A.n_queues, N = A.n_arena;
     if (i < N) A.next[i] = (i + Q < N) ? (uint32_t)(i + Q) : NIL;
     if (i == 0) A.fill[0] = 0;
@@ -448,7 +510,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     int wpc = a.waves_per_cu > 0 ? std::min(a.waves_per_cu, per_cu) : per_cu;
     long blocks = (long)a.num_cus * wpc;
     const int Q = 64;                 // one queue per lane of a wavefront
-    int n_arena = a.arena_links > 0 ? a.arena_links : (int)std::max<long>(1024, blocks * 4);
+    int n_arena = a.arena_links > 0 ? a.arena_links : (int)(blocks * (E + 2) + 1024);
     size_t arena_bytes = (size_t)n_arena * link_bytes;
     size_t need = arena_bytes + (size_t)n_arena * 8 + (size_t)Q * 16 + 1024;
     e = ws_reserve(ws, need);
@@ -474,8 +536,9 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.lacc_words = a.lacc_words;
     A.spin_limit = 1 << 20;
     A.force_spill = a.force_spill;
+    A.consolidate = a.consolidate == 1 ? 1 : 0;   // off unless asked for
     int ib = (std::max(n_arena, Q) + 255) / 256;
-    hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A);
+    hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A, (unsigned int)blocks);
     st.grid_blocks = (int)blocks;
     st.block_threads = 64;
     st.lds_bytes = (int)lds;

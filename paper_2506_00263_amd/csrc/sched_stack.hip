@@ -77,7 +77,7 @@ __device__ __forceinline__ void push(const StackArgs &A, char *bank, int set, in
         unsigned int cnt = (unsigned int)__popcll(mask);
         unsigned int b = 0;
         if (__lane_id() == 0) b = atomicAdd(stripe_ctr(A, set, E, k, home), cnt);
-        b = __builtin_amdgcn_readfirstlane(b);
+        b = first_lane_u32(b);
         unsigned long slot = (unsigned long)b + lane_rank(mask);
         bool spill = (unsigned long)b + cnt > (unsigned long)A.scap;
         unsigned int ob = 0;
@@ -86,7 +86,7 @@ __device__ __forceinline__ void push(const StackArgs &A, char *bank, int set, in
                                                                                 : (unsigned long)A.scap;
             unsigned int n_over = (unsigned int)((unsigned long)b + cnt - first_over);
             if (__lane_id() == 0) ob = atomicAdd(stripe_ctr(A, set, E, k, NSTRIPE - 1), n_over);
-            ob = __builtin_amdgcn_readfirstlane(ob);
+            ob = first_lane_u32(ob);
             if (mine && slot >= (unsigned long)A.scap) {
                 unsigned long o = (unsigned long)ob + (slot - first_over);
                 if (o < (unsigned long)A.ocap) put<LAY>(stripe_soa(A, bank, k, NSTRIPE - 1, LAY::nd(dig)), (long)o, p, dig);
@@ -201,8 +201,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
         if (fullest >= A.threshold) break;
         unsigned long long b = 0;
         if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 256ull);
-        b = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(b >> 32)) << 32) |
-            (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)b);
+        b = first_lane_u64(b);
         if (b >= A.total) break;
         for (int j = 0; j < 4; ++j) {
             unsigned long long gid = b + 64ull * j + lane;

@@ -728,6 +728,20 @@ __device__ __forceinline__ int run_event(int ev, const ProbDev &P, const EvCtx &
 
 // ------------------------------------------------------- wavefront helpers
 
+// Value of the first active lane.  The builtin returns a signed int, so the
+// 64-bit form must zero-extend the low half: a sign extension would smear
+// bit 31 over the high half.
+__device__ __forceinline__ uint32_t first_lane_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+
+__device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long v)
+{
+    return ((unsigned long long)first_lane_u32((uint32_t)(v >> 32)) << 32) |
+           (unsigned long long)first_lane_u32((uint32_t)v);
+}
+
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

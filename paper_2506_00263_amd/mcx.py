@@ -56,7 +56,8 @@ class RunOpts(C.Structure):
         ("first_history", C.c_uint64), ("n_histories", C.c_uint64), ("stack_capacity", C.c_int64),
         ("stack_threshold", C.c_int64), ("stash_links", C.c_int32), ("arena_links", C.c_int32),
         ("waves_per_cu", C.c_int32), ("block_size", C.c_int32), ("hip_stream", C.c_void_p), ("digest", C.c_void_p),
-        ("time_kernels", C.c_int32), ("force_spill", C.c_int32), ("reserved", C.c_int32 * 6),
+        ("time_kernels", C.c_int32), ("force_spill", C.c_int32), ("consolidate", C.c_int32),
+        ("reserved", C.c_int32 * 5),
     ]
 
 
@@ -186,7 +187,7 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
 
 def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, first=0, n=0, stack_capacity=0,
              stack_threshold=0, stash_links=0, arena_links=0, waves_per_cu=0, block_size=0, stream=None,
-             digest=None, time_kernels=False, force_spill=0) -> RunOpts:
+             digest=None, time_kernels=False, force_spill=0, consolidate=0) -> RunOpts:
     o = RunOpts()
     o.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     o.decomp = DECOMP[decomp] if isinstance(decomp, str) else int(decomp)
@@ -204,6 +205,11 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
     o.digest = _ptr(digest)
     o.time_kernels = int(bool(time_kernels))
     o.force_spill = int(force_spill)
+    # async stash donation: None/"default" = library default, True/"on", False/"off"
+    if isinstance(consolidate, bool):
+        o.consolidate = 1 if consolidate else 2
+    else:
+        o.consolidate = {None: 0, "default": 0, "on": 1, "off": 2}.get(consolidate, consolidate)
     return o
 
 

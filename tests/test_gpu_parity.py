@@ -166,6 +166,28 @@ def test_async_spills(mcx, cfg2):
         assert c["spills"] == c["refills"] > 100, (decomp, k, c["spills"])
 
 
+@pytest.mark.parametrize("decomp", ["fused", "split"])
+def test_async_consolidate(mcx, cfg2, cfg1, decomp):
+    # drained wavefronts hand sparse stashes to the arena, where other
+    # wavefronts merge them into full links; results must not change
+    for d, ref in (cfg2, cfg1):
+        P = mcx.Problem(d)
+        dg = _digest(mcx, d["n_histories"])
+        P.run(sched="async", decomp=decomp, consolidate=True, digest=dg)
+        assert np.array_equal(P.tallies(), ref["tally"])
+        _check_counts(P.counters(), ref["counts"])
+        assert np.array_equal(_digest_np(dg, mcx), ref["digest"])
+        c = P.counters()
+        assert c["spills"] == c["refills"] > 0, c["spills"]
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    for k, wpc in ((1, 0), (3, 1)):
+        P.run(sched="async", decomp=decomp, consolidate=True, force_spill=k, waves_per_cu=wpc)
+        assert np.array_equal(P.tallies(), ref["tally"]), (k, wpc)
+        c = P.counters()
+        assert c["spills"] == c["refills"] > 100, (k, wpc, c["spills"])
+
+
 def test_max_steps(mcx, oracle):
     d = inputs.cfg2_lattice(3000)
     d["max_steps"] = 4
