@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--decomp", default="fused")
     ap.add_argument("--no-extras", action="store_true", help="time only the headline configuration")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="finish with one device-to-device copy of this many MiB (a kernel of known traffic "
+                         "against which profiler byte counters are scaled)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (histories would shard "
@@ -166,6 +169,14 @@ def main():
         out["cpu_baseline"] = {"value": N_HIST / cpu_s, "unit": "histories/s", "cores": threads, "kind": "oracle",
                                "sample": f"all {N_HIST} histories of the benchmark workload ({cpu_s:.1f} s)"}
         out["oracle_match"] = bool(np.array_equal(ref["tally"], tally))
+    if args.copy_mib > 0:
+        n = args.copy_mib * (1 << 20) // 8
+        src = torch.arange(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration"] = {"bytes_read": n * 8, "bytes_written": n * 8}
     print(json.dumps(out))
 
 

@@ -165,7 +165,14 @@ typedef struct {
                                  few particles hands them to the arena, where
                                  other wavefronts merge them into full links:
                                  0 = library default, 1 = on, 2 = off           */
-    int32_t reserved[5];
+    int32_t stack_tail_events;/* stack: when the live particles no longer fill
+                                 the resident wavefronts, a popped particle
+                                 runs up to this many events before it is
+                                 pushed (0 = default 16, 1 = one per round)   */
+    int32_t stack_min_events; /* stack: events a popped particle runs before it
+                                 is pushed again, at least (0 = default 1:
+                                 remap after every event)                     */
+    int32_t reserved[3];
 } mcx_run_opts;
 
 /* one record per history, written by runs that pass opts.digest */

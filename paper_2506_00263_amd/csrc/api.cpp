@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -314,14 +315,36 @@ static mcx_status upload(mcx_problem_t h)
         size_t xpl, ypl, cxs, cys, cmat, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, hlo, hhi, mx, my, mz, ee;
     };
     std::vector<Offs> off(h->n);
+    std::vector<size_t> tl_base(h->n), tl_bytes(h->n);
+    std::vector<std::array<int32_t, 11>> tl_off(h->n);
     for (int k = 0; k < h->n; ++k) {
         HostProblem &p = h->hp[k];
         Offs &o = off[k];
-        o.xpl = bb.add(p.xpl); o.ypl = bb.add(p.ypl); o.cxs = bb.add(p.cxs); o.cys = bb.add(p.cys);
-        o.cmat = bb.add(p.cmat); o.sig_t = bb.add(p.sig_t); o.sig_s = bb.add(p.sig_s); o.cdf = bb.add(p.cdf);
+        // the small per-event tables, packed: doubles, then the int32 materials
+        const std::vector<double> *dt[10] = {&p.sig_t, &p.sig_s, &p.cdf, &p.xpl, &p.ypl,
+                                             &p.cxs,   &p.cys,   &p.mx,  &p.my,  &p.mz};
+        std::vector<double> packed;
+        for (int t = 0; t < 10; ++t) {
+            tl_off[k][t] = (int32_t)packed.size();
+            packed.insert(packed.end(), dt[t]->begin(), dt[t]->end());
+        }
+        tl_off[k][TL_CMAT] = (int32_t)(2 * packed.size());
+        size_t nd = packed.size();
+        packed.resize(nd + (p.cmat.size() + 1) / 2);
+        if (!p.cmat.empty()) std::memcpy(packed.data() + nd, p.cmat.data(), p.cmat.size() * 4);
+        if (packed.size() % 2) packed.push_back(0.0);   // 16-byte multiple
+        tl_base[k] = bb.add(packed);
+        tl_bytes[k] = packed.size() * 8;
+        size_t b = tl_base[k];
+        o.sig_t = b + 8 * (size_t)tl_off[k][TL_SIG_T]; o.sig_s = b + 8 * (size_t)tl_off[k][TL_SIG_S];
+        o.cdf = b + 8 * (size_t)tl_off[k][TL_CDF]; o.xpl = b + 8 * (size_t)tl_off[k][TL_XPL];
+        o.ypl = b + 8 * (size_t)tl_off[k][TL_YPL]; o.cxs = b + 8 * (size_t)tl_off[k][TL_CXS];
+        o.cys = b + 8 * (size_t)tl_off[k][TL_CYS]; o.mx = b + 8 * (size_t)tl_off[k][TL_MX];
+        o.my = b + 8 * (size_t)tl_off[k][TL_MY]; o.mz = b + 8 * (size_t)tl_off[k][TL_MZ];
+        o.cmat = b + 4 * (size_t)tl_off[k][TL_CMAT];
         o.egrid = bb.add(p.egrid); o.siga = bb.add(p.siga); o.sigs = bb.add(p.sigs); o.awr = bb.add(p.awr);
         o.dens = bb.add(p.dens); o.hlo = bb.add(p.hash_lo); o.hhi = bb.add(p.hash_hi);
-        o.mx = bb.add(p.mx); o.my = bb.add(p.my); o.mz = bb.add(p.mz); o.ee = bb.add(p.eedges);
+        o.ee = bb.add(p.eedges);
     }
     HIP_TRY(h, hipMalloc(&h->blob, std::max<size_t>(bb.bytes.size(), 256)));
     HIP_TRY(h, hipMemcpy(h->blob, bb.bytes.data(), bb.bytes.size(), hipMemcpyHostToDevice));
@@ -435,6 +458,9 @@ static mcx_status upload(mcx_problem_t h)
         P.SL = ga + 1;
         P.SA = ga + 1 + mg;
         P.SS = ga + 1 + 2 * mg;
+        P.tl_src = (const double *)(base + tl_base[k]);
+        P.tl_bytes = (int32_t)std::min<size_t>(tl_bytes[k], 1u << 30);
+        for (int t = 0; t < 11; ++t) P.tl_off[t] = tl_off[k][t];
     }
     return MCX_OK;
 }
@@ -540,7 +566,8 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
     if (o.sched == MCX_SCHED_NAIVE && o.decomp == MCX_DECOMP_SPLIT)
         return fail(h, MCX_E_INVALID_ARG, "the naive scheduler runs whole histories (fused only)");
     if (o.stack_capacity < 0 || o.stack_threshold < 0 || o.stash_links < 0 || o.arena_links < 0 ||
-        o.waves_per_cu < 0 || o.block_size < 0 || o.force_spill < 0)
+        o.waves_per_cu < 0 || o.block_size < 0 || o.force_spill < 0 || o.stack_tail_events < 0 ||
+        o.stack_min_events < 0)
         return fail(h, MCX_E_INVALID_ARG, "negative tuning value");
     if (o.consolidate < 0 || o.consolidate > 2) return fail(h, MCX_E_INVALID_ARG, "bad consolidate");
     return MCX_OK;
@@ -581,6 +608,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.mode = mode;
     a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
     a.lacc_words = (mode == MODE_REPLAY_B && h->n == 1) ? 3 * h->pd[0].n_mat * h->pd[0].n_grp : 0;
+    a.tl_bytes = (h->n == 1 && h->pd[0].tl_bytes <= TL_MAX_BYTES) ? h->pd[0].tl_bytes : 0;
     a.stream = stream;
     a.num_cus = h->num_cus;
     a.block_size = o.block_size;
@@ -591,6 +619,8 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.arena_links = o.arena_links;
     a.force_spill = o.force_spill;
     a.consolidate = o.consolidate;
+    a.stack_tail_events = o.stack_tail_events;
+    a.stack_min_events = o.stack_min_events;
 
     LaunchStats st;
     LaunchTimer tm;

@@ -55,6 +55,7 @@ struct LaunchArgs {
     void *digest;                          // device Digest array or null
     int geom, emode, mode, split;
     int lacc_words;                        // pass B per-block sums in LDS (single problem), 0 = none
+    int tl_bytes;                          // single problem: packed tables copied to LDS; 0 = read globally
     hipStream_t stream;
     int num_cus;
     // tuning (0 = default)
@@ -64,6 +65,8 @@ struct LaunchArgs {
     int stash_links, arena_links;
     int force_spill;                       // async, testing
     int consolidate;                       // async: 0 default, 1 on, 2 off
+    int stack_tail_events;                 // stack: events per pop in the tail (0 = default)
+    int stack_min_events;                  // stack: events per pop at least (0 = default 1)
 };
 
 struct LaunchStats {

@@ -56,7 +56,17 @@ struct ProbDev {
     unsigned long long *U;           // pass A bound (uint64)
     unsigned long long *SL, *SA, *SS;  // pass B sums [n_mat*n_grp] (int64 bits)
     int32_t acc_off, pad;            // offset of this problem in per-wave LDS sums
+    // The small tables every event reads (Sigma_t, Sigma_s, transfer CDF,
+    // planes, pin centres, mesh edges, then the int32 cell materials) sit
+    // packed at tl_src; single-problem launches copy them into LDS.
+    // tl_off[t]: offset of table t in 8-byte words (TL_CMAT: in 4-byte words).
+    const double *tl_src;
+    int32_t tl_bytes;                // packed size, a multiple of 16
+    int32_t tl_off[11];
 };
+
+enum : int { TL_SIG_T = 0, TL_SIG_S, TL_CDF, TL_XPL, TL_YPL, TL_CXS, TL_CYS, TL_MX, TL_MY, TL_MZ, TL_CMAT };
+constexpr int TL_MAX_BYTES = 32768;   // larger tables stay in global memory
 
 enum Counter : int {
     C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,

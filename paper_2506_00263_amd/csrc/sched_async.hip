@@ -48,6 +48,7 @@ struct AsyncArgs {
     int spin_limit;
     int force_spill;             // testing: spill every k-th filled link
     int consolidate;             // drained sparse stashes are handed to the arena and merged
+    int tl_bytes;                // packed tables copied to LDS (single problem)
 };
 
 constexpr uint32_t NIL = 0xFFFFFFFFu;
@@ -326,7 +327,7 @@ struct AsyncWave {
 };
 
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) async_kernel(AsyncArgs A)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) async_kernel(AsyncArgs A)
 {
     using LAY = Layout<EMODE, MODE, SPLIT>;
     constexpr int E = SPLIT ? 4 : 1;
@@ -334,6 +335,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
     const bool dig = A.digest != nullptr;
     const int L = A.links;
     unsigned long long *lacc = (unsigned long long *)(lds + (long)L * A.link_bytes);
+    char *tl = lds + tabs_lds_offset((size_t)L * A.link_bytes + (size_t)A.lacc_words * 8);
+    if constexpr (!BATCH) tabs_to_lds(A.probs[0], tl);
     EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
     if (cx.lacc) {
         lacc_zero(lacc, A.lacc_words);
@@ -381,7 +384,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
             if (act) {
                 int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
                 const ProbDev &P = A.probs[pi];
-                source<GEOM, MODE>(P, p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+                source<GEOM, MODE>(P, tabs_for<BATCH>(P, tl), p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
             }
             wc.outcomes(act, O_SOURCE);
             wc.c[C_MAKE_WORK] += 1;
@@ -457,7 +460,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) as
         uint32_t out = 0;
         if (act) {
             const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
-            ne = run_event<GEOM, EMODE, MODE, SPLIT>(ev, P, cx, ln, p, out);
+            ne = run_event<GEOM, EMODE, MODE, SPLIT>(ev, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
         }
         wc.dispatch(act);
         wc.outcomes(act, out);
@@ -501,7 +504,8 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     if (L < E + 1) L = E + 1;
     if (L > 16) L = 16;
     int link_bytes = 64 * LAY::bytes(dig);
-    size_t lds = (size_t)L * link_bytes + (size_t)a.lacc_words * 8;
+    const int tl_bytes = BATCH ? 0 : a.tl_bytes;
+    size_t lds = tabs_lds_offset((size_t)L * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
     auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds);
@@ -537,6 +541,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.spin_limit = 1 << 20;
     A.force_spill = a.force_spill;
     A.consolidate = a.consolidate == 1 ? 1 : 0;   // off unless asked for
+    A.tl_bytes = tl_bytes;
     int ib = (std::max(n_arena, Q) + 255) / 256;
     hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A, (unsigned int)blocks);
     st.grid_blocks = (int)blocks;
@@ -553,8 +558,8 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
 template <int GEOM, int EMODE, int MODE, int SPLIT>
 static hipError_t async_b(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
-    return a.n_probs > 1 ? async_t<GEOM, EMODE, MODE, SPLIT, true>(a, ws, st, tm)
-                         : async_t<GEOM, EMODE, MODE, SPLIT, false>(a, ws, st, tm);
+    return (a.n_probs > 1 || a.tl_bytes == 0) ? async_t<GEOM, EMODE, MODE, SPLIT, true>(a, ws, st, tm)
+                                              : async_t<GEOM, EMODE, MODE, SPLIT, false>(a, ws, st, tm);
 }
 
 template <int GEOM, int EMODE, int MODE>

@@ -14,7 +14,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
                                                     unsigned long long total, RunCtl *ctl, Digest *digest,
                                                     int lacc_words)
 {
-    extern __shared__ unsigned long long lacc[];
+    extern __shared__ __attribute__((aligned(16))) unsigned long long lacc[];
+    char *tl = (char *)lacc + tabs_lds_offset((size_t)lacc_words * 8);
+    if constexpr (!BATCH) tabs_to_lds(probs[0], tl);
     EvCtx cx{probs, digest, (MODE == MODE_REPLAY_B && lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
     if (cx.lacc) {
         lacc_zero(lacc, lacc_words);
@@ -32,7 +34,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
         if (act) {
             int pi = BATCH ? find_problem(prefix, n_probs, gid) : 0;
             const ProbDev &P = probs[pi];
-            source<GEOM, MODE>(P, p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+            source<GEOM, MODE>(P, tabs_for<BATCH>(P, tl), p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
             ev = EV_STEP;
         }
         wc.outcomes(act, O_SOURCE);
@@ -41,7 +43,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
             uint32_t out = 0;
             if (alive) {
                 const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
-                ev = ev_step<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+                ev = ev_step<GEOM, EMODE, MODE>(P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
             }
             wc.dispatch(alive);
             wc.outcomes(alive, out);
@@ -64,7 +66,7 @@ static hipError_t launch_naive_t(const LaunchArgs &a, LaunchStats &st, LaunchTim
     unsigned long long cap = (unsigned long long)a.num_cus * 64;   // grid-stride beyond this
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
-    size_t lds = (size_t)a.lacc_words * sizeof(unsigned long long);
+    size_t lds = tabs_lds_offset((size_t)a.lacc_words * 8) + (BATCH ? 0 : (size_t)a.tl_bytes);
     st.grid_blocks = (int)blocks;
     st.block_threads = bs;
     st.lds_bytes = (int)lds;
@@ -79,8 +81,8 @@ static hipError_t launch_naive_t(const LaunchArgs &a, LaunchStats &st, LaunchTim
 template <int GEOM, int EMODE, int MODE>
 static hipError_t naive_b(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
 {
-    return a.n_probs > 1 ? launch_naive_t<GEOM, EMODE, MODE, true>(a, st, tm)
-                         : launch_naive_t<GEOM, EMODE, MODE, false>(a, st, tm);
+    return (a.n_probs > 1 || a.tl_bytes == 0) ? launch_naive_t<GEOM, EMODE, MODE, true>(a, st, tm)
+                                              : launch_naive_t<GEOM, EMODE, MODE, false>(a, st, tm);
 }
 
 hipError_t launch_naive(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)

@@ -49,6 +49,9 @@ struct StackArgs {
     unsigned int *sizes;        // [3][E][NSTRIPE] counters, CTR_STRIDE apart
     unsigned long long threshold;
     int lacc_words;
+    int tail_events;            // most events a popped particle runs in place in the tail
+    int min_events;             // events a popped particle runs at least
+    int tl_bytes;               // packed tables copied to LDS (single problem)
 };
 
 __device__ __forceinline__ unsigned int *stripe_ctr(const StackArgs &A, int set, int E, int e, int s)
@@ -125,12 +128,25 @@ __device__ __forceinline__ StripeView stripe_view(const StackArgs &A, int set, i
     return v;
 }
 
+// total 64-particle input chunks of one event (wave-uniform)
+__device__ __forceinline__ unsigned int event_chunks(const StackArgs &A, int set, int E, int e)
+{
+    const int lane = __lane_id();
+    unsigned int n = __hip_atomic_load(stripe_ctr(A, set, E, e, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned int cap = (lane == NSTRIPE - 1) ? (unsigned int)A.ocap : (unsigned int)A.scap;
+    n = n < cap ? n : cap;
+    unsigned int c = (n + 63u) >> 6;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    return c;
+}
+
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) stack_round(StackArgs A, int round)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) stack_round(StackArgs A, int round)
 {
     using LAY = Layout<EMODE, MODE, SPLIT>;
     constexpr int E = SPLIT ? 4 : 1;
-    extern __shared__ unsigned long long lacc[];
+    extern __shared__ __attribute__((aligned(16))) unsigned long long lacc[];
+    char *tl = (char *)lacc + tabs_lds_offset((size_t)A.lacc_words * 8);
     const bool dig = A.digest != nullptr;
     const int set_in = round % 3, set_out = (round + 1) % 3;
     char *bin = A.bank[round & 1];
@@ -152,6 +168,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
         if (blockIdx.x == 0 && threadIdx.x == 0 && A.ctl->done_round == 0) A.ctl->done_round = (unsigned)round + 1;
         return;
     }
+    // (a wavefront that returned above no longer takes part in block barriers)
+    if constexpr (!BATCH) tabs_to_lds(A.probs[0], tl);
     EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
     if (cx.lacc) {
         lacc_zero(lacc, A.lacc_words);
@@ -160,6 +178,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
     Lane ln{0, 0, 0, 0};
     WaveCount wc;
     wc.zero();
+    // A popped particle runs K events in place before it is pushed: at least
+    // min_events (1: remap after every event).  Tail: when the round's input
+    // chunks no longer give every wavefront one, remapping cannot fill the
+    // device and each round costs a launch plus one event's latency, so K
+    // grows as the population shrinks (up to tail_events).  Every history
+    // draws from its own keyed streams, so results do not change.
+    int K = A.min_events;
+    {
+        unsigned int all = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) all += event_chunks(A, set_in, E, e);
+        if (all < n_waves) {
+            unsigned int q = n_waves / (all ? all : 1u);
+            int kt = (int)(q < (unsigned int)A.tail_events ? q : (unsigned int)A.tail_events);
+            K = kt > K ? kt : K;
+        }
+    }
     // pop: the input stacks are read-only during a round, so the 64-particle
     // chunks are dealt to wavefronts in a fixed order (no pop atomics)
 #pragma unroll 1
@@ -173,15 +208,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
             unsigned int base = (c - excl) * 64u;
             bool act = base + (unsigned int)lane < ns;
             Part p;
-            int ne = EV_DEAD;
-            uint32_t out = 0;
-            if (act) {
-                get<LAY>(stripe_soa(A, bin, e, s, LAY::nd(dig)), (long)(base + lane), p, dig);
-                const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
-                ne = run_event<GEOM, EMODE, MODE, SPLIT>(e, P, cx, ln, p, out);
+            if (act) get<LAY>(stripe_soa(A, bin, e, s, LAY::nd(dig)), (long)(base + lane), p, dig);
+            int ne = EV_DEAD, cur = e;
+            bool live = act;
+            for (int i = 0;;) {
+                uint32_t out = 0;
+                if (live) {
+                    const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
+                    ne = run_event<GEOM, EMODE, MODE, SPLIT>(cur, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
+                }
+                wc.dispatch(live);
+                wc.outcomes(live, out);
+                if (++i >= K) break;
+                live = live && ne != EV_DEAD;
+                if (__ballot(live) == 0) break;
+                cur = ne;
             }
-            wc.dispatch(act);
-            wc.outcomes(act, out);
             push<LAY, E>(A, bout, set_out, home, act, ne, p, dig, ln.err);
         }
     }
@@ -211,7 +253,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) s
             if (act) {
                 int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
                 const ProbDev &P = A.probs[pi];
-                source<GEOM, MODE>(P, p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+                source<GEOM, MODE>(P, tabs_for<BATCH>(P, tl), p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
             }
             wc.outcomes(act, O_SOURCE);
             wc.c[C_MAKE_WORK] += 1;
@@ -232,7 +274,16 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     constexpr int E = SPLIT ? 4 : 1;
     const bool dig = a.digest != nullptr;
     const int block = 256;
-    int wpc = a.waves_per_cu > 0 ? a.waves_per_cu : 16;
+    // every block of a round is resident at once: the grid is the resident
+    // capacity (or the requested waves per CU, if fewer)
+    auto kern = stack_round<GEOM, EMODE, MODE, SPLIT, BATCH>;
+    const size_t lds_need = tabs_lds_offset((size_t)a.lacc_words * 8) + (size_t)(BATCH ? 0 : a.tl_bytes);
+    int per_cu = 0;
+    hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds_need);
+    if (oe != hipSuccess) return oe;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int wpc = per_cu * (block / 64);
+    if (a.waves_per_cu > 0 && a.waves_per_cu < wpc) wpc = a.waves_per_cu;
     long blocks = std::max(1L, (long)a.num_cus * wpc / (block / 64));
     long waves = blocks * (block / 64);
     long slack = 2 * (waves * 256 + 64);          // particles sourced past the threshold
@@ -269,49 +320,78 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.sizes = (unsigned int *)((char *)ws.ptr + (size_t)event_bytes * E * 2);
     A.threshold = (unsigned long long)thr;
     A.lacc_words = a.lacc_words;
+    A.tail_events = a.stack_tail_events > 0 ? a.stack_tail_events : 16;
+    A.min_events = a.stack_min_events > 0 ? a.stack_min_events : 1;
+    A.tl_bytes = BATCH ? 0 : a.tl_bytes;
     e = hipMemsetAsync(A.sizes, 0, ctr_bytes, a.stream);
     if (e != hipSuccess) return e;
-    size_t lds = (size_t)a.lacc_words * 8;
+    size_t lds = lds_need;
     st.grid_blocks = (int)blocks;
     st.block_threads = block;
     st.lds_bytes = (int)lds;
+    // Rounds are queued in batches.  After each batch the control block's
+    // error and done words are copied to pinned host memory behind an
+    // event; the host queues the next batch before it waits for the
+    // previous batch's words, so the device never idles on a poll.  A batch
+    // queued past the last round costs only its early exits.
+    hipEvent_t polled[2];
+    e = hipEventCreateWithFlags(&polled[0], hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    e = hipEventCreateWithFlags(&polled[1], hipEventDisableTiming);
+    if (e != hipSuccess) {
+        hipEventDestroy(polled[0]);
+        return e;
+    }
     int round = 0;
-    int batch = 4;
-    for (;;) {
+    const int batch = 8;
+    auto queue_batch = [&](int slot) -> hipError_t {
         for (int i = 0; i < batch; ++i) {
             tm.begin();
-            hipLaunchKernelGGL((stack_round<GEOM, EMODE, MODE, SPLIT, BATCH>), dim3((unsigned)blocks), dim3(block), lds,
-                               a.stream, A, round);
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(block), lds, a.stream, A, round);
             tm.end();
             ++round;
             st.launches += 1;
         }
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        hipError_t r = hipGetLastError();
+        if (r != hipSuccess) return r;
         // error and done_round are adjacent words of the control block
-        e = hipMemcpyAsync(flag, &a.ctl->error, 8, hipMemcpyDeviceToHost, a.stream);
-        if (e != hipSuccess) return e;
-        e = hipStreamSynchronize(a.stream);
-        if (e != hipSuccess) return e;
-        if (flag[1] != 0) {
-            st.rounds = flag[1];
+        r = hipMemcpyAsync(flag + 2 * slot, &a.ctl->error, 8, hipMemcpyDeviceToHost, a.stream);
+        if (r != hipSuccess) return r;
+        return hipEventRecord(polled[slot], a.stream);
+    };
+    e = queue_batch(0);
+    for (int b = 0; e == hipSuccess; ++b) {
+        if (round > (1 << 26)) {
+            e = hipErrorLaunchTimeOut;
             break;
         }
-        if (flag[0] & ERR_CAPACITY) {
+        e = queue_batch((b + 1) & 1);
+        if (e != hipSuccess) break;
+        e = hipEventSynchronize(polled[b & 1]);
+        if (e != hipSuccess) break;
+        const unsigned int *f = flag + 2 * (b & 1);
+        if (f[1] != 0) {
+            st.rounds = f[1];
+            break;
+        }
+        if (f[0] & ERR_CAPACITY) {
             st.rounds = (unsigned long long)round;
             break;
         }
-        if (batch < 64) batch *= 2;
-        if (round > (1 << 26)) return hipErrorLaunchTimeOut;
     }
+    hipError_t e2 = hipStreamSynchronize(a.stream);
+    hipEventDestroy(polled[0]);
+    hipEventDestroy(polled[1]);
+    if (e != hipSuccess) return e;
+    if (e2 != hipSuccess) return e2;
     return hipSuccess;
 }
 
 template <int GEOM, int EMODE, int MODE, int SPLIT>
 static hipError_t stack_b(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm, unsigned int *flag)
 {
-    return a.n_probs > 1 ? stack_t<GEOM, EMODE, MODE, SPLIT, true>(a, ws, st, tm, flag)
-                         : stack_t<GEOM, EMODE, MODE, SPLIT, false>(a, ws, st, tm, flag);
+    return (a.n_probs > 1 || a.tl_bytes == 0) ? stack_t<GEOM, EMODE, MODE, SPLIT, true>(a, ws, st, tm, flag)
+                                              : stack_t<GEOM, EMODE, MODE, SPLIT, false>(a, ws, st, tm, flag);
 }
 
 template <int GEOM, int EMODE, int MODE>

@@ -80,6 +80,65 @@ struct EvCtx {
     int single;                      // one problem in the run
 };
 
+// The small tables an event reads.  TabsG reads them from the problem's
+// arrays in global memory (batched launches, where the problem differs per
+// lane); TabsL holds pointers into this block's LDS copy (single-problem
+// launches).  LDS reads are waited for on their own counter, so they never
+// wait behind the wavefront's outstanding tally atomics, which go to memory.
+struct TabsG {
+    const ProbDev &P;
+    __device__ __forceinline__ const double *sig_t() const { return P.sig_t; }
+    __device__ __forceinline__ const double *sig_s() const { return P.sig_s; }
+    __device__ __forceinline__ const double *cdf() const { return P.cdf; }
+    __device__ __forceinline__ const double *xpl() const { return P.xpl; }
+    __device__ __forceinline__ const double *ypl() const { return P.ypl; }
+    __device__ __forceinline__ const double *cxs() const { return P.cxs; }
+    __device__ __forceinline__ const double *cys() const { return P.cys; }
+    __device__ __forceinline__ const double *mx() const { return P.mx; }
+    __device__ __forceinline__ const double *my() const { return P.my; }
+    __device__ __forceinline__ const double *mz() const { return P.mz; }
+    __device__ __forceinline__ const int32_t *cmat() const { return P.cmat; }
+};
+
+struct TabsL {
+    const double *d;                 // LDS copy of the packed tables
+    const ProbDev &P;
+    __device__ __forceinline__ const double *sig_t() const { return d + P.tl_off[TL_SIG_T]; }
+    __device__ __forceinline__ const double *sig_s() const { return d + P.tl_off[TL_SIG_S]; }
+    __device__ __forceinline__ const double *cdf() const { return d + P.tl_off[TL_CDF]; }
+    __device__ __forceinline__ const double *xpl() const { return d + P.tl_off[TL_XPL]; }
+    __device__ __forceinline__ const double *ypl() const { return d + P.tl_off[TL_YPL]; }
+    __device__ __forceinline__ const double *cxs() const { return d + P.tl_off[TL_CXS]; }
+    __device__ __forceinline__ const double *cys() const { return d + P.tl_off[TL_CYS]; }
+    __device__ __forceinline__ const double *mx() const { return d + P.tl_off[TL_MX]; }
+    __device__ __forceinline__ const double *my() const { return d + P.tl_off[TL_MY]; }
+    __device__ __forceinline__ const double *mz() const { return d + P.tl_off[TL_MZ]; }
+    __device__ __forceinline__ const int32_t *cmat() const { return (const int32_t *)d + P.tl_off[TL_CMAT]; }
+};
+
+// Copy problem P's packed tables into LDS at dst (every thread of the block
+// takes part; ends with a block barrier).
+__device__ __forceinline__ void tabs_to_lds(const ProbDev &P, char *dst)
+{
+    const uint4 *src = (const uint4 *)P.tl_src;
+    uint4 *d = (uint4 *)dst;
+    const int n = P.tl_bytes >> 4;
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) d[i] = src[i];
+    __syncthreads();
+}
+
+// Table accessor of a launch: per-lane problem tables in batched launches,
+// the block's LDS copy otherwise.
+template <bool BATCH>
+__device__ __forceinline__ auto tabs_for(const ProbDev &P, const char *lds)
+{
+    if constexpr (BATCH) return TabsG{P};
+    else return TabsL{(const double *)lds, P};
+}
+
+// LDS bytes in front of the table copy (16-byte aligned)
+__host__ __device__ __forceinline__ size_t tabs_lds_offset(size_t before) { return (before + 15) / 16 * 16; }
+
 __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
 
 // largest i in [0, n-1] with e[i] <= x; a point on edge i moving in the
@@ -134,40 +193,43 @@ __device__ __forceinline__ double plane_dist(double lo, double hi, double x, dou
     return d;
 }
 
-template <int GEOM>
-__device__ __forceinline__ int material(const ProbDev &P, uint32_t gc)
+template <int GEOM, class TB>
+__device__ __forceinline__ int material(const ProbDev &P, const TB &T, uint32_t gc)
 {
-    if (GEOM == GEOM_BOX) return P.cmat[gc_c0(gc)];
-    if (gc_in(gc)) return P.cmat[gc_c1(gc) * P.nx + gc_c0(gc)];
-    return P.mod_mat;
+    if (GEOM == GEOM_BOX) return T.cmat()[gc_c0(gc)];
+    // read the pin's material unconditionally (the index is always valid) and
+    // select afterwards: a load through a pointer chosen between LDS and the
+    // problem record would have to be a flat load
+    int pin = T.cmat()[gc_c1(gc) * P.nx + gc_c0(gc)];
+    return gc_in(gc) ? pin : P.mod_mat;
 }
 
-template <int GEOM>
-__device__ __forceinline__ uint32_t locate(const ProbDev &P, double x, double y, double u, double v, int g)
+template <int GEOM, class TB>
+__device__ __forceinline__ uint32_t locate(const ProbDev &P, const TB &T, double x, double y, double u, double v, int g)
 {
-    if (GEOM == GEOM_BOX) return gc_pack(g, edge_index(P.xpl, P.n_slabs, x, u), 0, 0, 0);
-    int i = edge_index(P.xpl, P.nx, x, u);
-    int j = edge_index(P.ypl, P.ny, y, v);
-    double ddx = x - P.cxs[i], ddy = y - P.cys[j];
+    if (GEOM == GEOM_BOX) return gc_pack(g, edge_index(T.xpl(), P.n_slabs, x, u), 0, 0, 0);
+    int i = edge_index(T.xpl(), P.nx, x, u);
+    int j = edge_index(T.ypl(), P.ny, y, v);
+    double ddx = x - T.cxs()[i], ddy = y - T.cys()[j];
     int in = (((ddx * ddx) + (ddy * ddy)) < P.r2) ? 1 : 0;
     return gc_pack(g, i, j, in, 0);
 }
 
 // Distance to the nearest bounding surface of the particle's cell; surf:
 // 0 x-plane, 1 y-plane, 2 z-plane, 3 cylinder; ties go to the lower number.
-template <int GEOM>
-__device__ __forceinline__ double surface_distance(const ProbDev &P, const Part &p, int &surf)
+template <int GEOM, class TB>
+__device__ __forceinline__ double surface_distance(const ProbDev &P, const TB &T, const Part &p, int &surf)
 {
     double dx = inf(), dy = inf(), dz, dc = inf();
     int c0 = gc_c0(p.gc);
     if (GEOM == GEOM_BOX) {
-        dx = plane_dist(P.xpl[c0], P.xpl[c0 + 1], p.x, p.u);
+        dx = plane_dist(T.xpl()[c0], T.xpl()[c0 + 1], p.x, p.u);
         dy = plane_dist(P.box_lo[1], P.box_hi[1], p.y, p.v);
         dz = plane_dist(P.box_lo[2], P.box_hi[2], p.z, p.w);
     } else {
         int c1 = gc_c1(p.gc);
         dz = plane_dist(P.box_lo[2], P.box_hi[2], p.z, p.w);
-        double ddx = p.x - P.cxs[c0], ddy = p.y - P.cys[c1];
+        double ddx = p.x - T.cxs()[c0], ddy = p.y - T.cys()[c1];
         double a = (p.u * p.u) + (p.v * p.v);
         double k = (ddx * p.u) + (ddy * p.v);
         double c = ((ddx * ddx) + (ddy * ddy)) - P.r2;
@@ -178,8 +240,8 @@ __device__ __forceinline__ double surface_distance(const ProbDev &P, const Part 
                 dc = (root(disc) - k) / a;
             }
         } else {
-            dx = plane_dist(P.xpl[c0], P.xpl[c0 + 1], p.x, p.u);
-            dy = plane_dist(P.ypl[c1], P.ypl[c1 + 1], p.y, p.v);
+            dx = plane_dist(T.xpl()[c0], T.xpl()[c0 + 1], p.x, p.u);
+            dy = plane_dist(T.ypl()[c1], T.ypl()[c1 + 1], p.y, p.v);
             if (a > 0.0 && k < 0.0 && disc >= 0.0) dc = c / (root(disc) - k);
         }
         if (dc < 0.0) dc = 0.0;
@@ -333,16 +395,17 @@ __device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, do
 // Track-length mesh tally of one flight of length d from the current
 // position: visit the mesh cells the segment crosses; every crossing
 // parameter is measured from the flight start; ties go x, y, z.
-template <int MODE>
-__device__ __forceinline__ void walk_mesh(const ProbDev &P, Lane &ln, Part &p, double d, int g)
+template <int MODE, class TB>
+__device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &ln, Part &p, double d, int g)
 {
     const int n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2];
-    int i0 = edge_index_guess(P.mx, n0, p.x, p.u, P.mesh_lo[0], P.mesh_inv[0]);
-    int i1 = edge_index_guess(P.my, n1, p.y, p.v, P.mesh_lo[1], P.mesh_inv[1]);
-    int i2 = edge_index_guess(P.mz, n2, p.z, p.w, P.mesh_lo[2], P.mesh_inv[2]);
-    double t0 = axis_t(P.mx, i0, p.x, p.u);
-    double t1 = axis_t(P.my, i1, p.y, p.v);
-    double t2 = axis_t(P.mz, i2, p.z, p.w);
+    const double *mx = T.mx(), *my = T.my(), *mz = T.mz();
+    int i0 = edge_index_guess(mx, n0, p.x, p.u, P.mesh_lo[0], P.mesh_inv[0]);
+    int i1 = edge_index_guess(my, n1, p.y, p.v, P.mesh_lo[1], P.mesh_inv[1]);
+    int i2 = edge_index_guess(mz, n2, p.z, p.w, P.mesh_lo[2], P.mesh_inv[2]);
+    double t0 = axis_t(mx, i0, p.x, p.u);
+    double t1 = axis_t(my, i1, p.y, p.v);
+    double t2 = axis_t(mz, i2, p.z, p.w);
     double tprev = 0.0;
     for (;;) {
         int a = 0;
@@ -356,17 +419,17 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, Lane &ln, Part &p, d
         if (a == 0) {
             i0 += (p.u > 0.0) ? 1 : -1;
             if (i0 < 0 || i0 >= n0) break;
-            t0 = (P.mx[i0 + ((p.u > 0.0) ? 1 : 0)] - p.x) / p.u;
+            t0 = (mx[i0 + ((p.u > 0.0) ? 1 : 0)] - p.x) / p.u;
             if (t0 < 0.0) t0 = 0.0;
         } else if (a == 1) {
             i1 += (p.v > 0.0) ? 1 : -1;
             if (i1 < 0 || i1 >= n1) break;
-            t1 = (P.my[i1 + ((p.v > 0.0) ? 1 : 0)] - p.y) / p.v;
+            t1 = (my[i1 + ((p.v > 0.0) ? 1 : 0)] - p.y) / p.v;
             if (t1 < 0.0) t1 = 0.0;
         } else {
             i2 += (p.w > 0.0) ? 1 : -1;
             if (i2 < 0 || i2 >= n2) break;
-            t2 = (P.mz[i2 + ((p.w > 0.0) ? 1 : 0)] - p.z) / p.w;
+            t2 = (mz[i2 + ((p.w > 0.0) ? 1 : 0)] - p.z) / p.w;
             if (t2 < 0.0) t2 = 0.0;
         }
         tprev = tend;
@@ -386,8 +449,9 @@ __device__ __forceinline__ void pass_b_add(const ProbDev &P, const EvCtx &cx, in
 }
 
 // Score a flight of length d that started at the particle's position.
-template <int EMODE, int MODE>
-__device__ __forceinline__ void score_flight(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, double d, int m)
+template <int EMODE, int MODE, class TB>
+__device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, double d,
+                                             int m)
 {
     int g = gc_group(p.gc);
     if (MODE == MODE_REPLAY_B) {
@@ -395,7 +459,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const EvCtx &cx, 
         return;
     }
     if (P.tally_kind == 0) {
-        walk_mesh<MODE>(P, ln, p, d, g);
+        walk_mesh<MODE>(P, T, ln, p, d, g);
     } else {
         int k;
         if (P.ebin_inv != 0.0) {
@@ -446,8 +510,8 @@ __device__ __forceinline__ void finish(const ProbDev &P, const EvCtx &cx, Lane &
 }
 
 // Source event ("make_work" output): the history's start state.
-template <int GEOM, int MODE>
-__device__ __forceinline__ void source(const ProbDev &P, Part &p, uint32_t hid, uint32_t prob)
+template <int GEOM, int MODE, class TB>
+__device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, uint32_t hid, uint32_t prob)
 {
     Key k{P.key0, P.key1};
     double x0, x1, x2, x3, x4, x5;
@@ -474,7 +538,7 @@ __device__ __forceinline__ void source(const ProbDev &P, Part &p, uint32_t hid, 
         p.u = P.src_dir[0]; p.v = P.src_dir[1]; p.w = P.src_dir[2];
     }
     p.e = P.e_src;
-    p.gc = locate<GEOM>(P, p.x, p.y, p.u, p.v, P.src_group);
+    p.gc = locate<GEOM>(P, T, p.x, p.y, p.u, p.v, P.src_group);
     p.hid = hid;
     p.prob = prob;
     p.step = 1;
@@ -498,13 +562,13 @@ __device__ __forceinline__ bool kill_check(const ProbDev &P, const EvCtx &cx, La
     return false;
 }
 
-template <int GEOM, int EMODE, int MODE>
-__device__ __forceinline__ int ev_lookup(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+template <int GEOM, int EMODE, int MODE, class TB>
+__device__ __forceinline__ int ev_lookup(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
     if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
-    int m = material<GEOM>(P, p.gc);
+    int m = material<GEOM>(P, T, p.gc);
     if (EMODE == EMODE_MG) {
-        p.sigt = P.sig_t[m * P.n_grp + gc_group(p.gc)];
+        p.sigt = T.sig_t()[m * P.n_grp + gc_group(p.gc)];
     } else {
         CEXS X;
         p.sigt = ce_lookup(P, m, p.e, X);
@@ -513,15 +577,15 @@ __device__ __forceinline__ int ev_lookup(const ProbDev &P, const EvCtx &cx, Lane
 }
 
 // Move to the next collision site or surface, scoring the track on the way.
-template <int GEOM, int EMODE, int MODE>
-__device__ __forceinline__ bool fly(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, double sigt, double xi0,
-                                    int m, int &surf)
+template <int GEOM, int EMODE, int MODE, class TB>
+__device__ __forceinline__ bool fly(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, double sigt,
+                                    double xi0, int m, int &surf)
 {
     double dcol = neg_log(xi0) / sigt;
-    double dsurf = surface_distance<GEOM>(P, p, surf);
+    double dsurf = surface_distance<GEOM>(P, T, p, surf);
     bool collide = dcol < dsurf;
     double d = collide ? dcol : dsurf;
-    score_flight<EMODE, MODE>(P, cx, ln, p, d, m);
+    score_flight<EMODE, MODE>(P, T, cx, ln, p, d, m);
     p.x = p.x + (d * p.u);
     p.y = p.y + (d * p.v);
     p.z = p.z + (d * p.w);
@@ -530,8 +594,8 @@ __device__ __forceinline__ bool fly(const ProbDev &P, const EvCtx &cx, Lane &ln,
 
 // Cross the surface `surf`: snap to the plane, then leak, reflect or enter
 // the neighbouring cell.  Returns false if the particle leaked.
-template <int GEOM>
-__device__ __forceinline__ bool cross(const ProbDev &P, Part &p, int surf, uint32_t &out)
+template <int GEOM, class TB>
+__device__ __forceinline__ bool cross(const ProbDev &P, const TB &T, Part &p, int surf, uint32_t &out)
 {
     // new values are formed in scalars and stored unconditionally, so no
     // field of the particle is ever addressed through a computed index
@@ -544,10 +608,10 @@ __device__ __forceinline__ bool cross(const ProbDev &P, Part &p, int surf, uint3
     } else if (surf == 0) {
         int n = (GEOM == GEOM_BOX) ? P.n_slabs : P.nx;
         if (p.u > 0.0) {
-            x = P.xpl[c0 + 1];
+            x = T.xpl()[c0 + 1];
             if (c0 + 1 == n) face = 1; else c0 = c0 + 1;
         } else {
-            x = P.xpl[c0];
+            x = T.xpl()[c0];
             if (c0 == 0) face = 0; else c0 = c0 - 1;
         }
     } else if (surf == 1) {
@@ -555,10 +619,10 @@ __device__ __forceinline__ bool cross(const ProbDev &P, Part &p, int surf, uint3
             y = (p.v > 0.0) ? P.box_hi[1] : P.box_lo[1];
             face = (p.v > 0.0) ? 3 : 2;
         } else if (p.v > 0.0) {
-            y = P.ypl[c1 + 1];
+            y = T.ypl()[c1 + 1];
             if (c1 + 1 == P.ny) face = 3; else c1 = c1 + 1;
         } else {
-            y = P.ypl[c1];
+            y = T.ypl()[c1];
             if (c1 == 0) face = 2; else c1 = c1 - 1;
         }
     } else {
@@ -586,16 +650,17 @@ __device__ __forceinline__ bool cross(const ProbDev &P, Part &p, int surf, uint3
 
 // Collision at the current site with the flight's random numbers xi1..xi4.
 // Returns false if the history ends (absorption or energy cutoff).
-template <int EMODE, int MODE>
-__device__ __forceinline__ bool collide(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, int m, double sigt,
-                                        const CEXS &X, double xi1, double xi2, double xi3, double xi4, uint32_t &out)
+template <int EMODE, int MODE, class TB>
+__device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, int m,
+                                        double sigt, const CEXS &X, double xi1, double xi2, double xi3, double xi4,
+                                        uint32_t &out)
 {
     out |= O_COLL;
     p.ncoll += 1;
     if (EMODE == EMODE_MG) {
         int g = gc_group(p.gc);
         int mg = m * P.n_grp + g;
-        double ss = P.sig_s[mg];
+        double ss = T.sig_s()[mg];
         if (!((xi1 * sigt) < ss)) {
             out |= O_ABS;
             if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 1, mg, (long long)to_fixed(p.G, P.gscale));
@@ -604,7 +669,7 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const EvCtx &cx, Lane 
         }
         out |= O_SCAT;
         if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 2, mg, (long long)to_fixed(p.G, P.gscale));
-        const double *row = P.cdf + (long)mg * P.n_grp;
+        const double *row = T.cdf() + (long)mg * P.n_grp;
         int gn = P.n_grp - 1;
         for (int k = 0; k < P.n_grp; ++k) {
             if (xi2 < row[k]) {
@@ -643,28 +708,28 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const EvCtx &cx, Lane 
 }
 
 // Monolithic event: one whole flight (lookup, move with tally, collide or cross).
-template <int GEOM, int EMODE, int MODE>
-__device__ __forceinline__ int ev_step(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+template <int GEOM, int EMODE, int MODE, class TB>
+__device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
     if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
-    int m = material<GEOM>(P, p.gc);
+    int m = material<GEOM>(P, T, p.gc);
     CEXS X;
     double sigt;
-    if (EMODE == EMODE_MG) sigt = P.sig_t[m * P.n_grp + gc_group(p.gc)];
+    if (EMODE == EMODE_MG) sigt = T.sig_t()[m * P.n_grp + gc_group(p.gc)];
     else sigt = ce_lookup(P, m, p.e, X);
     Key k{P.key0, P.key1};
     double xi0, xi1;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
     int surf;
-    bool coll = fly<GEOM, EMODE, MODE>(P, cx, ln, p, sigt, xi0, m, surf);
+    bool coll = fly<GEOM, EMODE, MODE>(P, T, cx, ln, p, sigt, xi0, m, surf);
     out |= O_FLIGHT;
     if (coll) {
         double xi2, xi3, xi4, xi5;
         uniform_pair(k, p.hid, p.step, 1, xi2, xi3);
         uniform_pair(k, p.hid, p.step, 2, xi4, xi5);
-        if (!collide<EMODE, MODE>(P, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
+        if (!collide<EMODE, MODE>(P, T, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
     } else {
-        if (!cross<GEOM>(P, p, surf, out)) {
+        if (!cross<GEOM>(P, T, p, surf, out)) {
             finish<MODE>(P, cx, ln, p, FATE_LEAK);
             return EV_DEAD;
         }
@@ -675,24 +740,25 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const EvCtx &cx, Lane &
 
 // Decomposed events ------------------------------------------------------
 
-template <int GEOM, int EMODE, int MODE>
-__device__ __forceinline__ int ev_move(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+template <int GEOM, int EMODE, int MODE, class TB>
+__device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
-    int m = material<GEOM>(P, p.gc);
+    int m = material<GEOM>(P, T, p.gc);
     Key k{P.key0, P.key1};
     double xi0, xi1;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
     int surf;
-    bool coll = fly<GEOM, EMODE, MODE>(P, cx, ln, p, p.sigt, xi0, m, surf);
+    bool coll = fly<GEOM, EMODE, MODE>(P, T, cx, ln, p, p.sigt, xi0, m, surf);
     out |= O_FLIGHT;
     p.gc = (p.gc & ~(3u << 29)) | ((uint32_t)surf << 29);
     return coll ? EV_COLLIDE : EV_SURFACE;
 }
 
-template <int GEOM, int EMODE, int MODE>
-__device__ __forceinline__ int ev_surface(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+template <int GEOM, int EMODE, int MODE, class TB>
+__device__ __forceinline__ int ev_surface(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
+                                          uint32_t &out)
 {
-    if (!cross<GEOM>(P, p, gc_surf(p.gc), out)) {
+    if (!cross<GEOM>(P, T, p, gc_surf(p.gc), out)) {
         finish<MODE>(P, cx, ln, p, FATE_LEAK);
         return EV_DEAD;
     }
@@ -700,10 +766,11 @@ __device__ __forceinline__ int ev_surface(const ProbDev &P, const EvCtx &cx, Lan
     return EV_LOOKUP;
 }
 
-template <int GEOM, int EMODE, int MODE>
-__device__ __forceinline__ int ev_collide(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+template <int GEOM, int EMODE, int MODE, class TB>
+__device__ __forceinline__ int ev_collide(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
+                                          uint32_t &out)
 {
-    int m = material<GEOM>(P, p.gc);
+    int m = material<GEOM>(P, T, p.gc);
     CEXS X;
     if (EMODE == EMODE_CE) ce_lookup(P, m, p.e, X);
     Key k{P.key0, P.key1};
@@ -711,19 +778,20 @@ __device__ __forceinline__ int ev_collide(const ProbDev &P, const EvCtx &cx, Lan
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
     uniform_pair(k, p.hid, p.step, 1, xi2, xi3);
     uniform_pair(k, p.hid, p.step, 2, xi4, xi5);
-    if (!collide<EMODE, MODE>(P, cx, ln, p, m, p.sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
+    if (!collide<EMODE, MODE>(P, T, cx, ln, p, m, p.sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
     p.step += 1;
     return EV_LOOKUP;
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT>
-__device__ __forceinline__ int run_event(int ev, const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+template <int GEOM, int EMODE, int MODE, int SPLIT, class TB>
+__device__ __forceinline__ int run_event(int ev, const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
+                                         uint32_t &out)
 {
-    if (!SPLIT) return ev_step<GEOM, EMODE, MODE>(P, cx, ln, p, out);
-    if (ev == EV_LOOKUP) return ev_lookup<GEOM, EMODE, MODE>(P, cx, ln, p, out);
-    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE>(P, cx, ln, p, out);
-    if (ev == EV_SURFACE) return ev_surface<GEOM, EMODE, MODE>(P, cx, ln, p, out);
-    return ev_collide<GEOM, EMODE, MODE>(P, cx, ln, p, out);
+    if (!SPLIT) return ev_step<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
+    if (ev == EV_LOOKUP) return ev_lookup<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
+    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
+    if (ev == EV_SURFACE) return ev_surface<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
+    return ev_collide<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
 }
 
 // ------------------------------------------------------- wavefront helpers

@@ -57,7 +57,7 @@ class RunOpts(C.Structure):
         ("stack_threshold", C.c_int64), ("stash_links", C.c_int32), ("arena_links", C.c_int32),
         ("waves_per_cu", C.c_int32), ("block_size", C.c_int32), ("hip_stream", C.c_void_p), ("digest", C.c_void_p),
         ("time_kernels", C.c_int32), ("force_spill", C.c_int32), ("consolidate", C.c_int32),
-        ("reserved", C.c_int32 * 5),
+        ("stack_tail_events", C.c_int32), ("stack_min_events", C.c_int32), ("reserved", C.c_int32 * 3),
     ]
 
 
@@ -187,7 +187,8 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
 
 def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, first=0, n=0, stack_capacity=0,
              stack_threshold=0, stash_links=0, arena_links=0, waves_per_cu=0, block_size=0, stream=None,
-             digest=None, time_kernels=False, force_spill=0, consolidate=0) -> RunOpts:
+             digest=None, time_kernels=False, force_spill=0, consolidate=0, stack_tail_events=0,
+             stack_min_events=0) -> RunOpts:
     o = RunOpts()
     o.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     o.decomp = DECOMP[decomp] if isinstance(decomp, str) else int(decomp)
@@ -205,6 +206,8 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
     o.digest = _ptr(digest)
     o.time_kernels = int(bool(time_kernels))
     o.force_spill = int(force_spill)
+    o.stack_tail_events = int(stack_tail_events)
+    o.stack_min_events = int(stack_min_events)
     # async stash donation: None/"default" = library default, True/"on", False/"off"
     if isinstance(consolidate, bool):
         o.consolidate = 1 if consolidate else 2

@@ -149,6 +149,38 @@ def test_stack_small_capacity_many_rounds(mcx, cfg2):
         assert P.counters()["rounds"] > 20
 
 
+@pytest.mark.parametrize("decomp", ["fused", "split"])
+def test_stack_events_per_pop(mcx, cfg2, decomp):
+    # a popped particle may run several events before it is pushed again
+    # (at least stack_min_events; more in the tail); results must not change
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    dg = _digest(mcx, d["n_histories"])
+    for kw in (dict(stack_min_events=1, stack_tail_events=1), dict(stack_min_events=3, stack_tail_events=64),
+               dict(stack_min_events=1, stack_tail_events=100000), dict(stack_min_events=7, waves_per_cu=2)):
+        dg.zero_()
+        P.run(sched="stack", decomp=decomp, digest=dg, **kw)
+        assert np.array_equal(P.tallies(), ref["tally"]), kw
+        _check_counts(P.counters(), ref["counts"])
+        assert np.array_equal(_digest_np(dg, mcx), ref["digest"]), kw
+
+
+def test_tables_too_large_for_lds(mcx, oracle):
+    # a single problem whose small tables exceed the LDS budget runs with
+    # tables read from global memory; results must not change
+    rng = np.random.default_rng(1007)
+    n_mat, n_grp = 8, 40                       # transfer CDF alone: 8*40*40 doubles = 100 KB
+    st, ss = inputs._mg_tables(rng, n_mat, n_grp, 0.3, 0.95)
+    cdf = inputs._transfer_cdf(rng, n_mat, n_grp)
+    d = inputs.box_slabs_mg(planes_x=np.linspace(0.0, 10.0, n_mat + 1), sigma_t=st, sigma_s=ss, cdf=cdf,
+                            mesh_n=(6, 6, 6), n_histories=3000)
+    ref = oracle.run(d)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        P.run(sched=sched, decomp=decomp)
+        assert np.array_equal(P.tallies(), ref["tally"]), (sched, decomp)
+
+
 def test_async_spills(mcx, cfg2):
     # the smallest stash (one partial link per event plus one) forces links
     # through the global arena; results must not change
