@@ -46,6 +46,8 @@ struct mcx_problem_s {
     ProbDev *d_probs = nullptr;
     unsigned long long *d_prefix = nullptr;
     unsigned long long *d_tally = nullptr;
+    unsigned long long *d_trep = nullptr;  // replicas of a large energy-bin tally
+    size_t trep_words = 0;
     RunCtl *d_ctl = nullptr;
     // backward buffers
     double *d_G = nullptr;
@@ -506,6 +508,7 @@ extern "C" void mcx_destroy_problem(mcx_problem_t h)
     if (h->d_probs) hipFree(h->d_probs);
     if (h->d_prefix) hipFree(h->d_prefix);
     if (h->d_tally) hipFree(h->d_tally);
+    if (h->d_trep) hipFree(h->d_trep);
     if (h->d_ctl) hipFree(h->d_ctl);
     if (h->d_G) hipFree(h->d_G);
     if (h->d_w) hipFree(h->d_w);
@@ -573,6 +576,16 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
     return MCX_OK;
 }
 
+// tally[b] += sum over replicas r of rep[r][b] (exact: int64 bits, wrapping)
+__global__ void trep_reduce(unsigned long long *tally, const unsigned long long *rep, int n, int nrep)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n) return;
+    unsigned long long v = 0;
+    for (int r = 0; r < nrep; ++r) v += rep[(size_t)r * n + b];
+    tally[b] += v;
+}
+
 // One pass over the run's histories with the given mode.
 static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, const std::vector<uint64_t> &first,
                            const std::vector<uint64_t> &count, void *digest, unsigned int *err_out)
@@ -585,9 +598,26 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
         P.count = count[k];
         P.gbase = prefix[k];
         P.lookup_hash = o.lookup == MCX_LOOKUP_HASH ? 1 : 0;
+        P.trep = nullptr;
         prefix[k + 1] = prefix[k] + count[k];
     }
     unsigned long long total = prefix[h->n];
+    // a single problem's energy-bin tally too large for LDS: adds go to
+    // replicas, summed into the tally after the launch
+    const bool use_trep = h->n == 1 && mode == MODE_FWD && h->pd[0].tally_kind == MCX_TALLY_ENERGY &&
+                          h->pd[0].n_ebins > LT_MAX_BINS;
+    if (use_trep) {
+        size_t words = (size_t)TREP * h->pd[0].n_ebins;
+        if (h->trep_words < words) {
+            if (h->d_trep) HIP_TRY(h, hipFree(h->d_trep));
+            h->d_trep = nullptr;
+            h->trep_words = 0;
+            HIP_TRY(h, hipMalloc(&h->d_trep, words * 8));
+            h->trep_words = words;
+        }
+        HIP_TRY(h, hipMemsetAsync(h->d_trep, 0, words * 8, stream));
+        h->pd[0].trep = h->d_trep;
+    }
     HIP_TRY(h, hipMemcpyAsync(h->d_probs, h->pd.data(), sizeof(ProbDev) * h->n, hipMemcpyHostToDevice, stream));
     HIP_TRY(h, hipMemcpyAsync(h->d_prefix, prefix.data(), sizeof(unsigned long long) * (h->n + 1),
                               hipMemcpyHostToDevice, stream));
@@ -607,7 +637,11 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.emode = h->emode;
     a.mode = mode;
     a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
-    a.lacc_words = (mode == MODE_REPLAY_B && h->n == 1) ? 3 * h->pd[0].n_mat * h->pd[0].n_grp : 0;
+    a.lacc_words = 0;
+    if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
+    // a small energy-bin tally is summed per block in LDS, then added once
+    if (h->n == 1 && mode == MODE_FWD && h->pd[0].tally_kind == MCX_TALLY_ENERGY && h->pd[0].n_ebins <= LT_MAX_BINS)
+        a.lacc_words = h->pd[0].n_ebins;
     a.tl_bytes = (h->n == 1 && h->pd[0].tl_bytes <= TL_MAX_BYTES) ? h->pd[0].tl_bytes : 0;
     a.stream = stream;
     a.num_cus = h->num_cus;
@@ -631,6 +665,12 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
         if (o.sched == MCX_SCHED_NAIVE) e = launch_naive(a, st, tm);
         else if (o.sched == MCX_SCHED_STACK) e = launch_stack(a, h->ws, st, tm, h->h_flag);
         else e = launch_async(a, h->ws, st, tm);
+        if (e == hipSuccess && use_trep) {
+            int n = h->pd[0].n_ebins;
+            hipLaunchKernelGGL(trep_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
+                               h->pd[0].tally, (const unsigned long long *)h->d_trep, n, TREP);
+            e = hipGetLastError();
+        }
     }
     if (e != hipSuccess) {
         tm.total_ms();

@@ -44,6 +44,8 @@ struct ProbDev {
     double ebin_lnlo, ebin_inv;      // energy bins uniform in ln E
     double tscale;                   // 2^tally_scale_log2
     unsigned long long *tally;       // this problem's bins
+    unsigned long long *trep;        // [TREP][n_ebins] replicas of a large energy-bin tally
+                                     // (summed into tally after the run), or null
     // random numbers and histories of the current run
     uint32_t key0, key1;
     uint64_t first, count;           // histories [first, first + count)
@@ -67,6 +69,8 @@ struct ProbDev {
 
 enum : int { TL_SIG_T = 0, TL_SIG_S, TL_CDF, TL_XPL, TL_YPL, TL_CXS, TL_CYS, TL_MX, TL_MY, TL_MZ, TL_CMAT };
 constexpr int TL_MAX_BYTES = 32768;   // larger tables stay in global memory
+constexpr int LT_MAX_BINS = 4096;     // energy-bin tallies up to this size are summed in LDS per block
+constexpr int TREP = 16;              // larger ones go to TREP replicas chosen by wavefront
 
 enum Counter : int {
     C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,

@@ -91,7 +91,7 @@ __device__ __forceinline__ void lane0_store(uint32_t *p, uint32_t v)
 
 // Pop one link from one of the 64 queues in `slots` (one queue per lane, so a
 // single vector load inspects all of them).  Returns NIL if none had a link.
-__device__ uint32_t arena_pop(const AsyncArgs &A, unsigned long long *slots, uint32_t start)
+__device__ __forceinline__ uint32_t arena_pop(const AsyncArgs &A, unsigned long long *slots, uint32_t start)
 {
     const int lane = __lane_id();
     unsigned long long mine = __hip_atomic_load(&slots[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -121,7 +121,7 @@ __device__ uint32_t arena_pop(const AsyncArgs &A, unsigned long long *slots, uin
 
 // Append link a to one of the 64 queues of `slots`; bounded retries while
 // all are claimed.
-__device__ bool arena_push(const AsyncArgs &A, unsigned long long *slots, uint32_t start, uint32_t a)
+__device__ __forceinline__ bool arena_push(const AsyncArgs &A, unsigned long long *slots, uint32_t start, uint32_t a)
 {
     lane0_store(&A.next[a], NIL);
     for (int spin = 0; spin < A.spin_limit; ++spin) {
@@ -159,23 +159,23 @@ struct Stash {
     unsigned long long clo, chi;   // 8-bit counts of links 0-7 and 8-15
     uint32_t evw;                  // 2-bit event of each link
     uint32_t part;                 // 8-bit partial link per event (0xff none)
-    __device__ int cnt(int l) const
+    __device__ __forceinline__ int cnt(int l) const
     {
         return (int)(((l < 8) ? (clo >> (8 * l)) : (chi >> (8 * (l - 8)))) & 0xffull);
     }
-    __device__ void set_cnt(int l, int c)
+    __device__ __forceinline__ void set_cnt(int l, int c)
     {
         if (l < 8) clo = (clo & ~(0xffull << (8 * l))) | ((unsigned long long)c << (8 * l));
         else chi = (chi & ~(0xffull << (8 * (l - 8)))) | ((unsigned long long)c << (8 * (l - 8)));
     }
-    __device__ int ev(int l) const { return (int)((evw >> (2 * l)) & 3u); }
-    __device__ void set_ev(int l, int e) { evw = (evw & ~(3u << (2 * l))) | ((uint32_t)e << (2 * l)); }
-    __device__ int partial(int k) const
+    __device__ __forceinline__ int ev(int l) const { return (int)((evw >> (2 * l)) & 3u); }
+    __device__ __forceinline__ void set_ev(int l, int e) { evw = (evw & ~(3u << (2 * l))) | ((uint32_t)e << (2 * l)); }
+    __device__ __forceinline__ int partial(int k) const
     {
         int v = (int)((part >> (8 * k)) & 0xffu);
         return v == 0xff ? -1 : v;
     }
-    __device__ void set_partial(int k, int l) { part = (part & ~(0xffu << (8 * k))) | ((uint32_t)(l & 0xff) << (8 * k)); }
+    __device__ __forceinline__ void set_partial(int k, int l) { part = (part & ~(0xffu << (8 * k))) | ((uint32_t)(l & 0xff) << (8 * k)); }
 };
 
 struct AsyncWave {
@@ -189,7 +189,7 @@ struct AsyncWave {
     __device__ SoA alink(uint32_t a) const { return SoA{A.arena + (long)a * A.link_bytes, 64, nd}; }
 
     // move ready link v to the global arena
-    __device__ bool spill(int v)
+    __device__ __forceinline__ bool spill(int v)
     {
         uint32_t a = NIL;
         for (int spin = 0; spin < A.spin_limit && a == NIL; ++spin) {
@@ -206,7 +206,7 @@ struct AsyncWave {
     }
 
     // a free stash link, spilling a ready one if none is free; -1 on failure
-    __device__ int alloc(WaveCount &wc, uint32_t &err)
+    __device__ __forceinline__ int alloc(WaveCount &wc, uint32_t &err)
     {
         if (S.freem == 0) {
             if (S.readym == 0) {
@@ -229,7 +229,7 @@ struct AsyncWave {
 
     // pack this wavefront's particles into the partial links of their next events
     template <class LAY, int E>
-    __device__ void deposit(bool act, int ne, const Part &p, bool dig, WaveCount &wc, uint32_t &err)
+    __device__ __forceinline__ void deposit(bool act, int ne, const Part &p, bool dig, WaveCount &wc, uint32_t &err)
     {
 #pragma unroll
         for (int k = 0; k < E; ++k) {
@@ -283,7 +283,7 @@ struct AsyncWave {
     // (a donated remnant) is packed into the partial link of its event, so
     // remnants of many wavefronts merge into full links.
     template <class LAY, int E>
-    __device__ bool refill(bool dig, WaveCount &wc, uint32_t &err)
+    __device__ __forceinline__ bool refill(bool dig, WaveCount &wc, uint32_t &err)
     {
         if (S.freem == 0 || arena_fill(A) == 0) return false;
         uint32_t a = arena_pop(A, A.qfull, qstart);
@@ -314,7 +314,7 @@ struct AsyncWave {
     // they count themselves out, so when the last one finds the arena
     // non-empty those links are all visible; it stays (returns true) and
     // counts itself back in.
-    __device__ bool last_with_work(RunCtl *ctl)
+    __device__ __forceinline__ bool last_with_work(RunCtl *ctl)
     {
         unsigned int old = 0;
         if (__lane_id() == 0) old = __hip_atomic_fetch_sub(&ctl->active, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -327,7 +327,7 @@ struct AsyncWave {
 };
 
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) async_kernel(AsyncArgs A)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2))) async_kernel(AsyncArgs A)
 {
     using LAY = Layout<EMODE, MODE, SPLIT>;
     constexpr int E = SPLIT ? 4 : 1;
@@ -337,12 +337,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) as
     unsigned long long *lacc = (unsigned long long *)(lds + (long)L * A.link_bytes);
     char *tl = lds + tabs_lds_offset((size_t)L * A.link_bytes + (size_t)A.lacc_words * 8);
     if constexpr (!BATCH) tabs_to_lds(A.probs[0], tl);
-    EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
-    if (cx.lacc) {
+    // LDS block sums: pass B's per-(material, group) sums, or the bins of a small
+    // energy-bin tally (single-problem launches)
+    EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
+             (MODE == MODE_FWD && A.lacc_words > 0) ? lacc : nullptr};
+    if (A.lacc_words > 0) {
         lacc_zero(lacc, A.lacc_words);
         __syncthreads();
     }
-    Lane ln{0, 0, 0, 0};
+    Lane ln{0, 0, 0, 0, (uint32_t)(blockIdx.x % TREP)};
     WaveCount wc;
     wc.zero();
     const int lane = __lane_id();
@@ -467,9 +470,10 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) as
         W.template deposit<LAY, E>(act, ne, p, dig, wc, ln.err);
     }
     flush_wave(A.ctl, wc, ln, A.probs, BATCH ? 0 : 1, MODE);
-    if (cx.lacc) {
+    if (A.lacc_words > 0) {
         __syncthreads();
-        lacc_flush(lacc, A.probs[0]);
+        if (cx.lacc) lacc_flush(lacc, A.probs[0]);
+        if (cx.ltally) ltally_flush(lacc, A.probs[0], A.lacc_words);
     }
 }
 

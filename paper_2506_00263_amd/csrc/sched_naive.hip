@@ -17,12 +17,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
     extern __shared__ __attribute__((aligned(16))) unsigned long long lacc[];
     char *tl = (char *)lacc + tabs_lds_offset((size_t)lacc_words * 8);
     if constexpr (!BATCH) tabs_to_lds(probs[0], tl);
-    EvCtx cx{probs, digest, (MODE == MODE_REPLAY_B && lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
-    if (cx.lacc) {
+    // LDS block sums: pass B's per-(material, group) sums, or the bins of a small
+    // energy-bin tally (single-problem launches)
+    EvCtx cx{probs, digest, (MODE == MODE_REPLAY_B && lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
+             (MODE == MODE_FWD && lacc_words > 0) ? lacc : nullptr};
+    if (lacc_words > 0) {
         lacc_zero(lacc, lacc_words);
         __syncthreads();
     }
-    Lane ln{0, 0, 0, 0};
+    Lane ln{0, 0, 0, 0, (uint32_t)(((blockIdx.x * blockDim.x + threadIdx.x) >> 6) % TREP)};
     WaveCount wc;
     wc.zero();
     const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
@@ -50,9 +53,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
         }
     }
     flush_wave(ctl, wc, ln, probs, BATCH ? 0 : 1, MODE);
-    if (cx.lacc) {
+    if (lacc_words > 0) {
         __syncthreads();
-        lacc_flush(lacc, probs[0]);
+        if (cx.lacc) lacc_flush(lacc, probs[0]);
+        if (cx.ltally) ltally_flush(lacc, probs[0], lacc_words);
     }
 }
 

@@ -141,7 +141,7 @@ __device__ __forceinline__ unsigned int event_chunks(const StackArgs &A, int set
 }
 
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) stack_round(StackArgs A, int round)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? 3 : 2))) stack_round(StackArgs A, int round)
 {
     using LAY = Layout<EMODE, MODE, SPLIT>;
     constexpr int E = SPLIT ? 4 : 1;
@@ -170,12 +170,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) s
     }
     // (a wavefront that returned above no longer takes part in block barriers)
     if constexpr (!BATCH) tabs_to_lds(A.probs[0], tl);
-    EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1};
-    if (cx.lacc) {
+    // LDS block sums: pass B's per-(material, group) sums, or the bins of a small
+    // energy-bin tally (single-problem launches)
+    EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
+             (MODE == MODE_FWD && A.lacc_words > 0) ? lacc : nullptr};
+    if (A.lacc_words > 0) {
         lacc_zero(lacc, A.lacc_words);
         __syncthreads();
     }
-    Lane ln{0, 0, 0, 0};
+    Lane ln{0, 0, 0, 0, (uint32_t)(wave % TREP)};
     WaveCount wc;
     wc.zero();
     // A popped particle runs K events in place before it is pushed: at least
@@ -261,9 +264,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) s
         }
     }
     flush_wave(A.ctl, wc, ln, A.probs, BATCH ? 0 : 1, MODE);
-    if (cx.lacc) {
+    if (A.lacc_words > 0) {
         __syncthreads();
-        lacc_flush(lacc, A.probs[0]);
+        if (cx.lacc) lacc_flush(lacc, A.probs[0]);
+        if (cx.ltally) ltally_flush(lacc, A.probs[0], A.lacc_words);
     }
 }
 

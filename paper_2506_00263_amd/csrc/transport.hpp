@@ -70,6 +70,7 @@ struct Lane {
     unsigned long long u;    // pass A bound (single-problem runs)
     uint32_t pieces;
     uint32_t err;
+    uint32_t rep;            // this wavefront's tally replica (wavefront id mod TREP)
 };
 
 // Everything an event needs besides the particle.
@@ -78,6 +79,7 @@ struct EvCtx {
     Digest *digest;                  // optional per-history records
     unsigned long long *lacc;        // pass B per-block sums (LDS) or null
     int single;                      // one problem in the run
+    unsigned long long *ltally;      // energy-bin tally per-block sums (LDS) or null
 };
 
 // The small tables an event reads.  TabsG reads them from the problem's
@@ -365,13 +367,25 @@ __device__ __forceinline__ void isotropic(double xi_mu, double xi_phi, Part &p)
 
 // ---------------------------------------------------------------- tallies
 
+// lt: this block's LDS copy of the bins (few bins: every flight would hit the
+// same few global words, and the device serialises atomics per address), or
+// null to add into the global tally directly
 template <int MODE>
-__device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long bin, double len)
+__device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long bin, double len,
+                                      unsigned long long *lt = nullptr)
 {
     if (MODE == MODE_FWD) {
         long long q = (long long)to_fixed(len, P.tscale);
         if (q != 0) {
-            __hip_atomic_fetch_add(P.tally + bin, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lt) {
+                __hip_atomic_fetch_add(lt + bin, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            } else {
+                // a large energy-bin tally: particles of a round or wavefront
+                // have similar energies and hit the same few bins, so the adds
+                // are spread over replicas
+                unsigned long long *dst = P.trep ? P.trep + (size_t)ln.rep * (size_t)P.n_ebins : P.tally;
+                __hip_atomic_fetch_add(dst + bin, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
             p.hq += q;
             unsigned long long before = ln.q;
             ln.q = before + (unsigned long long)q;
@@ -470,7 +484,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         } else {
             k = edge_index(P.eedges, P.n_ebins, p.e, 1.0);
         }
-        score<MODE>(P, ln, p, k, d);
+        score<MODE>(P, ln, p, k, d, cx.ltally);
     }
     if (MODE == MODE_REPLAY_A) p.L = p.L + d;
 }
@@ -907,6 +921,15 @@ __device__ __forceinline__ int find_problem(const unsigned long long *__restrict
 __device__ __forceinline__ void lacc_zero(unsigned long long *lacc, int n)
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) lacc[i] = 0;
+}
+
+// add a block's LDS energy-bin sums into the problem's tally
+__device__ __forceinline__ void ltally_flush(const unsigned long long *lt, const ProbDev &P, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        unsigned long long v = lt[i];
+        if (v) __hip_atomic_fetch_add(P.tally + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 __device__ __forceinline__ void lacc_flush(unsigned long long *lacc, const ProbDev &P)
