@@ -35,17 +35,35 @@ def algorithmic_bytes(c: dict) -> int:
     return 8 * c["pieces"] + 8 * c["flights"] + 16 * c["collisions"]
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (profiles/traffic.json), or None if those counters were taken
+    from a different build of the device code."""
+    from paper_2506_00263_amd import build
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic.json")) as f:
+            rec = json.load(f).get(kernel)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != build.source_hash():
+        return None
+    return rec["bytes_per_launch"]
+
+
 def timed_runs(P, reps, **kw):
+    """Wall times of `reps` runs (no per-launch events: they cost host time
+    between the stack scheduler's launches), then the kernel time of one
+    more run timed with HIP events."""
     import torch
-    times, kms = [], []
+    times = []
     for _ in range(reps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        P.run(time_kernels=True, **kw)
+        P.run(**kw)
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-        kms.append(P.counters()["kernel_ms"])
-    return times, kms
+    P.run(time_kernels=True, **kw)
+    return times, [P.counters()["kernel_ms"]]
 
 
 def main():
@@ -98,10 +116,10 @@ def main():
     per_launch_bytes = algorithmic_bytes(c) / max(1, launches // args.steps)
     mean_launch_ms = kernel_ms / max(1, launches)
     achieved = per_launch_bytes / (mean_launch_ms * 1e-3) / 1e9
+    kern = {"async": "async_kernel", "stack": "stack_round", "naive": "naive_kernel"}[args.sched]
     roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "kernel": {"async": "async_kernel", "stack": "stack_round", "naive": "naive_kernel"}[args.sched],
-                "mean_launch_ms": mean_launch_ms, "bytes_per_launch": per_launch_bytes}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kern),
+                "kernel": kern, "mean_launch_ms": mean_launch_ms, "bytes_per_launch": per_launch_bytes}
 
     out = {
         "metric": "particle histories/sec on 1 GPU (stack vs async TDR); backward/forward time ratio",
@@ -119,18 +137,23 @@ def main():
     }
 
     if not args.no_extras:
+        from paper_2506_00263_amd import autotune
         sched = {}
-        for s, dc in (("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"),
-                      ("async", "split")):
-            P.run(sched=s, decomp=dc)
-            ts, kms = timed_runs(P, 5, sched=s, decomp=dc)
-            cc = P.counters()
-            sched[f"{s}_{dc}"] = {"hist_per_s": N_HIST / float(np.median(ts)), "ms": 1e3 * float(np.median(ts)),
-                                  "kernel_ms": float(np.median(kms)),
-                                  "active_lane_frac": cc["events"] / max(1, cc["lane_slots"]),
-                                  "launches": cc["launches"]}
-            if not np.array_equal(P.tallies(), tally):
-                raise SystemExit(f"tally mismatch between schedulers: {s}/{dc}")
+        for s, dc in (("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"), ("async", "split")):
+            rec = {}
+            for label, knobs in (("default", {}), ("tuned", None)):
+                if knobs is None:
+                    knobs = autotune.tune(P, sched=s, decomp=dc, use_cache=False, reps=1)
+                P.run(sched=s, decomp=dc, **knobs)
+                ts, kms = timed_runs(P, 5, sched=s, decomp=dc, **knobs)
+                cc = P.counters()
+                rec[label] = {"hist_per_s": N_HIST / float(np.median(ts)), "ms": 1e3 * float(np.median(ts)),
+                              "kernel_ms": float(np.median(kms)),
+                              "active_lane_frac": cc["events"] / max(1, cc["lane_slots"]),
+                              "launches": cc["launches"], "knobs": knobs}
+                if not np.array_equal(P.tallies(), tally):
+                    raise SystemExit(f"tally mismatch between schedulers: {s}/{dc} {knobs}")
+            sched[f"{s}_{dc}"] = rec
         out["schedulers"] = sched
         # backward: two replays (pass A, pass B) of the same histories
         w = np.random.default_rng(4).normal(size=inputs.n_bins(d))
@@ -154,20 +177,46 @@ def main():
         B = mcx.Problem(probs)
         nb = sum(p["n_histories"] for p in probs)
         bres = {}
+        bref = None
         for s in ("async", "stack", "naive"):
-            B.run(sched=s)
-            ts, kms = timed_runs(B, 3, sched=s)
-            bres[s] = {"hist_per_s": nb / float(np.median(ts)), "ms": 1e3 * float(np.median(ts))}
+            rec = {}
+            for label, knobs in (("default", {}), ("tuned", None)):
+                if knobs is None:
+                    knobs = autotune.tune(B, sched=s, decomp="fused", use_cache=False, reps=1)
+                B.run(sched=s, **knobs)
+                ts, kms = timed_runs(B, 3, sched=s, **knobs)
+                rec[label] = {"hist_per_s": nb / float(np.median(ts)), "ms": 1e3 * float(np.median(ts)),
+                              "knobs": knobs}
+                t = [B.tallies(k) for k in range(len(probs))]
+                if bref is None:
+                    bref = t
+                elif not all(np.array_equal(a, b) for a, b in zip(bref, t)):
+                    raise SystemExit(f"batched tally mismatch: {s} {knobs}")
+            bres[s] = rec
         out["batched"] = {"problems": len(probs), "histories": nb, **bres}
 
     if not args.no_cpu:
+        # the oracle as it stands, on the host cores: the whole workload,
+        # repeated until about 5 s have passed; and a 1e5-history prefix on one
+        # core (histories are independent and keyed, so a prefix is a fair sample)
         from oracle import oracle as O
         threads = min(16, os.cpu_count() or 1)
+        reps, cpu_s, ref = 0, 0.0, None
+        while cpu_s < 5.0 and reps < 50:
+            t1 = time.perf_counter()
+            ref = O.run(d, threads=threads)
+            cpu_s += time.perf_counter() - t1
+            reps += 1
+        n1 = 100_000
         t1 = time.perf_counter()
-        ref = O.run(d, threads=threads)
-        cpu_s = time.perf_counter() - t1
-        out["cpu_baseline"] = {"value": N_HIST / cpu_s, "unit": "histories/s", "cores": threads, "kind": "oracle",
-                               "sample": f"all {N_HIST} histories of the benchmark workload ({cpu_s:.1f} s)"}
+        O.run(d, 0, n1, threads=1)
+        one_s = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": reps * N_HIST / cpu_s, "unit": "histories/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"all {N_HIST} histories of the benchmark workload, {reps} times "
+                                         f"({cpu_s:.1f} s)",
+                               "single_core": {"value": n1 / one_s, "sample": f"histories [0, {n1}) on 1 core "
+                                                                               f"({one_s:.1f} s)"}}
         out["oracle_match"] = bool(np.array_equal(ref["tally"], tally))
     if args.copy_mib > 0:
         n = args.copy_mib * (1 << 20) // 8

@@ -1,10 +1,12 @@
 """Autotuner for the remapping schedulers.
 
-Grid search over the tuning knobs of a scheduler (resident wavefronts per
-CU, stash links, stack capacity/threshold) on a short calibration run, timed
-with HIP events inside the library.  Knobs never change results: every
-candidate's tally is checked against the first candidate's.  The best choice
-is cached per (problem class, scheduler, decomposition, device).
+Grid search over the tuning knobs of a scheduler (async: resident
+wavefronts per CU and stash links; stack: events a popped particle runs
+before it is pushed again, at least and in the tail; naive: block size) on a
+calibration run, timed with HIP events inside the library.  Knobs never
+change results: every candidate's tally is checked against the first
+candidate's.  The best choice is cached per (problem class, scheduler,
+decomposition, device).
 """
 from __future__ import annotations
 
@@ -20,15 +22,16 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_autotune_cach
 
 
 def candidates(sched: str, decomp: str) -> list:
+    """Knob settings tried for one scheduler (0 = library default)."""
     events = 4 if decomp == "split" else 1
     if sched == "async":
         out = []
-        for wpc in (0, 8, 12):
+        for wpc in (0, 4, 6):
             for links in sorted({events + 1, events + 2, events + 3}):
                 out.append(dict(waves_per_cu=wpc, stash_links=links))
         return out
     if sched == "stack":
-        return [dict(waves_per_cu=w) for w in (4, 8, 12, 16, 20)]
+        return [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 256)]
     return [dict(block_size=b) for b in (64, 128, 256)]
 
 

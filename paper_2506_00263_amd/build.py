@@ -19,6 +19,23 @@ SOURCES = ["api.cpp", "sched_naive.hip", "sched_stack.hip", "sched_async.hip"]
 ARCH = os.environ.get("MCX_OFFLOAD_ARCH", "gfx950")
 
 
+def source_hash() -> str:
+    """Hash of everything the device code is built from (sources, the C
+    header, compiler flags): profiler figures taken from one build apply to
+    another only if the hashes agree."""
+    import hashlib
+    h = hashlib.sha1()
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp", ".cpp")))
+    for f in files:
+        h.update(f.encode())
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    with open(os.path.join(os.path.dirname(HERE), "include", "mcx.h"), "rb") as fh:
+        h.update(fh.read())
+    h.update(" ".join(flags()).encode())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 

@@ -1,0 +1,168 @@
+"""Summaries of rocprofv3 runs of bench.py (kernel statistics and counters).
+
+Reads the CSV output of rocprofv3 runs made with
+
+    rocprofv3 --kernel-trace --stats -d <dir>/trace_<sched> -o run --output-format csv -- \
+        python3 bench.py --sched <sched> --steps S --warmup 1 --no-extras --no-cpu
+    rocprofv3 --pmc <counters> -d <dir>/<pass>_<sched> -o run --output-format csv -- \
+        python3 bench.py --sched <sched> --steps 1 --warmup 1 --no-extras --no-cpu --copy-mib 1024
+
+and writes, per scheduler kernel, a short markdown summary and the HBM
+traffic per launch used by bench.py's roofline record.  Byte counters are
+scaled by what the same counter reads for the final 1 GiB device-to-device
+copy of the run (a kernel of known traffic).
+
+Usage: python -m paper_2506_00263_amd.profsum <dir> <out_dir> [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+from collections import defaultdict
+
+from . import build
+
+KERNELS = {"naive": "naive_kernel", "stack": "stack_round", "async": "async_kernel"}
+PASSES = {
+    "fetch": ["FETCH_SIZE"],
+    "write": ["WRITE_SIZE", "TCC_HIT_sum", "TCC_MISS_sum"],
+    "sq1": ["SQ_WAVES", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU",
+            "SQ_THREAD_CYCLES_VALU", "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY", "GRBM_GUI_ACTIVE"],
+    "sq2": ["SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_FLAT",
+            "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_ACTIVE_INST_ANY"],
+}
+COPY_BYTES = 1 << 30
+XCDS = 8           # GRBM_GUI_ACTIVE is summed over the eight XCDs
+CUS = 256
+
+
+def _csv(path_glob):
+    files = glob.glob(path_glob, recursive=True)
+    rows = []
+    for f in files:
+        with open(f) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def counters(d: str, pass_name: str, sched: str):
+    """{kernel_short: {counter: per-dispatch mean}}, dispatch counts, copy values."""
+    rows = _csv(os.path.join(d, f"{pass_name}_{sched}", "**", "*counter_collection.csv"))
+    per = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    copy = {}
+    by_dispatch = defaultdict(dict)
+    for r in rows:
+        name = r["Kernel_Name"]
+        by_dispatch[(r["Dispatch_Id"], name)][r["Counter_Name"]] = float(r["Counter_Value"])
+    for (did, name), cs in by_dispatch.items():
+        short = next((v for v in KERNELS.values() if v in name), None)
+        if short is None:
+            if "copyBuffer" in name and cs.get("FETCH_SIZE", cs.get("WRITE_SIZE", 0.0)) * 1024 > COPY_BYTES / 4:
+                copy = cs
+            continue
+        for c, v in cs.items():
+            per[short][c] += v
+        disp[short].add(did)
+    out = {}
+    for k, cs in per.items():
+        n = len(disp[k])
+        out[k] = {c: v / n for c, v in cs.items()}
+        out[k]["_dispatches"] = n
+    return out, copy
+
+
+def kernel_stats(d: str, sched: str):
+    rows = _csv(os.path.join(d, f"trace_{sched}", "**", "*kernel_stats.csv"))
+    for r in rows:
+        if KERNELS[sched] in r["Name"]:
+            return {"calls": int(r["Calls"]), "total_ns": float(r["TotalDurationNs"]),
+                    "avg_ns": float(r["AverageNs"]), "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])}
+    return None
+
+
+def summarise(d: str, out_dir: str, workload: str) -> dict:
+    src = build.source_hash()
+    traffic = {}
+    for sched, kern in KERNELS.items():
+        st = kernel_stats(d, sched)
+        f, fcopy = counters(d, "fetch", sched)
+        w, wcopy = counters(d, "write", sched)
+        s1, _ = counters(d, "sq1", sched)
+        s2, _ = counters(d, "sq2", sched)
+        if kern not in f or kern not in w:
+            continue
+        rf = COPY_BYTES / (fcopy["FETCH_SIZE"] * 1024) if fcopy.get("FETCH_SIZE") else None
+        rw = COPY_BYTES / (wcopy["WRITE_SIZE"] * 1024) if wcopy.get("WRITE_SIZE") else None
+        rd = f[kern]["FETCH_SIZE"] * 1024 * rf if rf else None
+        wr = w[kern]["WRITE_SIZE"] * 1024 * rw if rw else None
+        lines = [f"# {kern} — {workload}", ""]
+        lines.append(f"Build source hash: `{src}`.  Commands (from the repository root):")
+        lines.append("")
+        lines.append("```")
+        lines.append(f"rocprofv3 --kernel-trace --stats -d <dir>/trace_{sched} -o run --output-format csv -- "
+                     f"python3 bench.py --sched {sched} --steps 5 --warmup 1 --no-extras --no-cpu")
+        for p, cs in PASSES.items():
+            lines.append(f"rocprofv3 --pmc {' '.join(cs)} -d <dir>/{p}_{sched} -o run --output-format csv -- "
+                         f"python3 bench.py --sched {sched} --steps 1 --warmup 1 --no-extras --no-cpu --copy-mib 1024")
+        lines.append(f"python3 -m paper_2506_00263_amd.profsum <dir> profiles")
+        lines.append("```")
+        lines.append("")
+        if st:
+            lines.append("| kernel-trace | value |")
+            lines.append("|---|---|")
+            lines.append(f"| dispatches | {st['calls']} |")
+            lines.append(f"| average duration | {st['avg_ns'] / 1e3:.1f} us |")
+            lines.append(f"| min / max | {st['min_ns'] / 1e3:.1f} / {st['max_ns'] / 1e3:.1f} us |")
+            lines.append(f"| total | {st['total_ns'] / 1e6:.3f} ms |")
+            lines.append("")
+        lines.append("| counters (mean per dispatch) | value |")
+        lines.append("|---|---|")
+        lines.append(f"| dispatches per pass | {f[kern]['_dispatches']} |")
+        if rf:
+            lines.append(f"| FETCH_SIZE scale (1 GiB copy reads {fcopy['FETCH_SIZE']:.0f} KiB) | x{rf:.3f} |")
+        if rw:
+            lines.append(f"| WRITE_SIZE scale (1 GiB copy writes {wcopy['WRITE_SIZE']:.0f} KiB) | x{rw:.3f} |")
+        if rd is not None:
+            lines.append(f"| HBM read per dispatch (scaled) | {rd / 1e6:.2f} MB |")
+        if wr is not None:
+            lines.append(f"| HBM write per dispatch (scaled) | {wr / 1e6:.2f} MB |")
+        lines.append(f"| L2 hit rate | {w[kern]['TCC_HIT_sum'] / max(1.0, w[kern]['TCC_HIT_sum'] + w[kern]['TCC_MISS_sum']):.3f} |")
+        if kern in s1:
+            a = s1[kern]
+            util = a["SQ_THREAD_CYCLES_VALU"] / max(1.0, 64.0 * a["SQ_ACTIVE_INST_VALU"])
+            occ = 4.0 * a["SQ_WAVE_CYCLES"] / max(1.0, a["GRBM_GUI_ACTIVE"] / XCDS) / CUS
+            lines.append(f"| active lanes per VALU instruction (THREAD_CYCLES_VALU / 64 ACTIVE_INST_VALU) | {util:.3f} |")
+            lines.append(f"| mean resident waves per CU (4 WAVE_CYCLES / GUI_ACTIVE per XCD / 256 CUs) | {occ:.2f} of 32 |")
+            lines.append(f"| wave time waiting (WAIT_ANY / WAVE_CYCLES) | {a['SQ_WAIT_ANY'] / max(1.0, a['SQ_WAVE_CYCLES']):.3f} |")
+            lines.append(f"| VALU instructions | {a['SQ_INSTS_VALU']:.4g} |")
+        if kern in s2:
+            b = s2[kern]
+            for c in PASSES["sq2"]:
+                lines.append(f"| {c} | {b[c]:.4g} |")
+        lines.append("")
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, f"{kern}_{workload.replace(' ', '_')}.md"), "w") as fh:
+            fh.write("\n".join(lines))
+        if rd is not None and wr is not None:
+            traffic[kern] = {"bytes_per_launch": rd + wr, "read": rd, "write": wr, "source_hash": src,
+                             "workload": workload, "read_scale": rf, "write_scale": rw}
+    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
+        json.dump(traffic, fh, indent=1, sort_keys=True)
+    return traffic
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("dir")
+    ap.add_argument("out")
+    ap.add_argument("--workload", default="lattice_1e6")
+    a = ap.parse_args()
+    print(json.dumps(summarise(a.dir, a.out, a.workload), indent=1))
+
+
+if __name__ == "__main__":
+    main()
