@@ -66,6 +66,80 @@ def timed_runs(P, reps, **kw):
     return times, [P.counters()["kernel_ms"]]
 
 
+def _wall(P, reps, **kw):
+    ts, _ = timed_runs(P, reps + 1, **kw)
+    return float(np.median(ts[1:]))
+
+
+def sweep() -> dict:
+    """Measurement sweep (tuned knobs from the autotuner next to the defaults)."""
+    from paper_2506_00263_amd import autotune, inputs, mcx
+    out = {"lattice": [], "pincell_ce": [], "backward": [], "batch": {}}
+    scheds = (("naive", "fused"), ("async", "fused"), ("async", "split"), ("stack", "fused"), ("stack", "split"))
+    for n in (100_000, 1_000_000, 10_000_000):
+        P = mcx.Problem(inputs.cfg2_lattice(n))
+        reps = 3 if n < 10_000_000 else 2
+        for s, dc in scheds:
+            t = _wall(P, reps, sched=s, decomp=dc)
+            knobs = autotune.tune(P, sched=s, decomp=dc, use_cache=False, reps=1)
+            tt = _wall(P, reps, sched=s, decomp=dc, **knobs)
+            out["lattice"].append({"histories": n, "sched": s, "decomp": dc, "ms": 1e3 * t, "hist_per_s": n / t,
+                                   "tuned_ms": 1e3 * tt, "tuned_hist_per_s": n / tt, "knobs": knobs})
+            print("sweep lattice", out["lattice"][-1], file=sys.stderr, flush=True)
+        del P
+    for nb in (100, 1000, 10000):
+        for lookup in ("binary", "hash"):
+            P = mcx.Problem(inputs.cfg3_pincell(n_ebins=nb, n_histories=1_000_000))
+            for s, dc in scheds:
+                t = _wall(P, 2, sched=s, decomp=dc, lookup=lookup)
+                out["pincell_ce"].append({"bins": nb, "lookup": lookup, "sched": s, "decomp": dc, "ms": 1e3 * t,
+                                          "hist_per_s": 1e6 / t})
+                print("sweep pincell", out["pincell_ce"][-1], file=sys.stderr, flush=True)
+            del P
+    d = inputs.cfg4_lattice_grad(1_000_000)
+    P = mcx.Problem(d)
+    w = np.random.default_rng(4).normal(size=inputs.n_bins(d))
+    import torch
+    for s, dc in (("naive", "fused"), ("async", "fused"), ("stack", "fused")):
+        tf = _wall(P, 3, sched=s, decomp=dc)
+        tb = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            P.backward(w, sched=s, decomp=dc)
+            torch.cuda.synchronize()
+            tb.append(time.perf_counter() - t1)
+        out["backward"].append({"sched": s, "decomp": dc, "fwd_ms": 1e3 * tf, "bwd_ms": 1e3 * float(np.median(tb)),
+                                "ratio": float(np.median(tb)) / tf})
+        print("sweep backward", out["backward"][-1], file=sys.stderr, flush=True)
+    probs = inputs.cfg5_batch()
+    nb = sum(p["n_histories"] for p in probs)
+    B = mcx.Problem(probs)
+    singles = [mcx.Problem(p) for p in probs]
+    for s in ("async", "stack", "naive"):
+        t_one = _wall(B, 2, sched=s)
+        t_seq = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for Q in singles:
+                Q.run(sched=s)
+            torch.cuda.synchronize()
+            t_seq.append(time.perf_counter() - t1)
+        wb = np.concatenate([np.random.default_rng(k).normal(size=inputs.n_bins(p)) for k, p in enumerate(probs)])
+        B.run(sched=s)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.backward(wb, problem=-1, sched=s)
+        torch.cuda.synchronize()
+        tbw = time.perf_counter() - t1
+        out["batch"][s] = {"one_launch_ms": 1e3 * t_one, "hist_per_s": nb / t_one,
+                           "sequential_ms": 1e3 * float(np.median(t_seq)), "backward_ms": 1e3 * tbw}
+        print("sweep batch", s, out["batch"][s], file=sys.stderr, flush=True)
+    out["batch"]["histories"] = nb
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +149,11 @@ def main():
     ap.add_argument("--decomp", default="fused")
     ap.add_argument("--no-extras", action="store_true", help="time only the headline configuration")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the benchmark line, print one JSON object with the measurement sweep: "
+                         "lattice histories 1e5..1e7, the continuous-energy pin cell over bins, lookups and "
+                         "event decompositions, backward/forward per scheduler and the batch as one launch "
+                         "vs one launch per problem")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (a kernel of known traffic "
                          "against which profiler byte counters are scaled)")
@@ -88,6 +167,9 @@ def main():
     from paper_2506_00263_amd import inputs, mcx
 
     torch.cuda.set_device(0)
+    if args.sweep:
+        print(json.dumps(sweep()))
+        return
     d = inputs.cfg2_lattice(N_HIST)
     P = mcx.Problem(d)
     stream = torch.cuda.current_stream()

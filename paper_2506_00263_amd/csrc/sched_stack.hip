@@ -141,7 +141,7 @@ __device__ __forceinline__ unsigned int event_chunks(const StackArgs &A, int set
 }
 
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? 3 : 2))) stack_round(StackArgs A, int round)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH || EMODE == EMODE_CE) ? 3 : 2))) stack_round(StackArgs A, int round)
 {
     using LAY = Layout<EMODE, MODE, SPLIT>;
     constexpr int E = SPLIT ? 4 : 1;
