@@ -40,52 +40,75 @@ __device__ __forceinline__ uint32_t *ufield(const SoA &s, int f)
 {
     return (uint32_t *)(s.base + (long)s.nd * s.cap * 8) + (long)f * s.cap;
 }
+__device__ __forceinline__ double *dptr(const SoA &s, long i, int f) { return dfield(s, f) + i; }
+__device__ __forceinline__ uint32_t *uptr(const SoA &s, long i, int f) { return ufield(s, f) + i; }
 
-template <class LAY>
-__device__ __forceinline__ void put(const SoA &s, long i, const Part &p, bool dig)
+// 64-particle tiles (the event stacks): particle i lives in tile i/64 at
+// lane i%64; in a tile the 8-byte fields take 512 bytes each, then the 4-byte
+// fields 256 bytes each.  A wavefront touching 64 consecutive particles makes
+// one contiguous access per field, and every field's address is the lane's
+// tile address plus a constant, so no per-field base pointers are kept.
+struct Tiles {
+    char *base;
+    long tile_bytes;
+    int nd;
+};
+
+__device__ __forceinline__ char *tile_of(const Tiles &t, long i) { return t.base + (i >> 6) * t.tile_bytes; }
+__device__ __forceinline__ double *dptr(const Tiles &t, long i, int f)
 {
-    dfield(s, 0)[i] = p.x;
-    dfield(s, 1)[i] = p.y;
-    dfield(s, 2)[i] = p.z;
-    dfield(s, 3)[i] = p.u;
-    dfield(s, 4)[i] = p.v;
-    dfield(s, 5)[i] = p.w;
-    if (LAY::CE) dfield(s, LAY::D_E)[i] = p.e;
-    if (LAY::SIG) dfield(s, LAY::D_SIG)[i] = p.sigt;
-    if (LAY::GG) dfield(s, LAY::D_G)[i] = p.G;
-    if (LAY::LL) dfield(s, LAY::D_L)[i] = p.L;
-    ufield(s, 0)[i] = p.hid;
-    ufield(s, 1)[i] = p.step;
-    ufield(s, 2)[i] = p.gc;
-    ufield(s, 3)[i] = p.prob;
+    return (double *)(tile_of(t, i) + f * 512) + (i & 63);
+}
+__device__ __forceinline__ uint32_t *uptr(const Tiles &t, long i, int f)
+{
+    return (uint32_t *)(tile_of(t, i) + t.nd * 512 + f * 256) + (i & 63);
+}
+
+template <class LAY, class R>
+__device__ __forceinline__ void put(const R &s, long i, const Part &p, bool dig)
+{
+    *dptr(s, i, 0) = p.x;
+    *dptr(s, i, 1) = p.y;
+    *dptr(s, i, 2) = p.z;
+    *dptr(s, i, 3) = p.u;
+    *dptr(s, i, 4) = p.v;
+    *dptr(s, i, 5) = p.w;
+    if (LAY::CE) *dptr(s, i, LAY::D_E) = p.e;
+    if (LAY::SIG) *dptr(s, i, LAY::D_SIG) = p.sigt;
+    if (LAY::GG) *dptr(s, i, LAY::D_G) = p.G;
+    if (LAY::LL) *dptr(s, i, LAY::D_L) = p.L;
+    *uptr(s, i, 0) = p.hid;
+    *uptr(s, i, 1) = p.step;
+    *uptr(s, i, 2) = p.gc;
+    *uptr(s, i, 3) = p.prob;
     if (LAY::DIGEST && dig) {
-        ((long long *)dfield(s, LAY::D_HQ))[i] = p.hq;
-        ufield(s, 4)[i] = p.ncoll;
+        *(long long *)dptr(s, i, LAY::D_HQ) = p.hq;
+        *uptr(s, i, 4) = p.ncoll;
     }
 }
 
-template <class LAY>
-__device__ __forceinline__ void get(const SoA &s, long i, Part &p, bool dig)
+template <class LAY, class R>
+__device__ __forceinline__ void get(const R &s, long i, Part &p, bool dig)
 {
-    p.x = dfield(s, 0)[i];
-    p.y = dfield(s, 1)[i];
-    p.z = dfield(s, 2)[i];
-    p.u = dfield(s, 3)[i];
-    p.v = dfield(s, 4)[i];
-    p.w = dfield(s, 5)[i];
-    p.e = LAY::CE ? dfield(s, LAY::D_E)[i] : 0.0;
-    p.sigt = LAY::SIG ? dfield(s, LAY::D_SIG)[i] : 0.0;
-    p.G = LAY::GG ? dfield(s, LAY::D_G)[i] : 0.0;
-    p.L = LAY::LL ? dfield(s, LAY::D_L)[i] : 0.0;
-    p.hid = ufield(s, 0)[i];
-    p.step = ufield(s, 1)[i];
-    p.gc = ufield(s, 2)[i];
-    p.prob = ufield(s, 3)[i];
+    p.x = *dptr(s, i, 0);
+    p.y = *dptr(s, i, 1);
+    p.z = *dptr(s, i, 2);
+    p.u = *dptr(s, i, 3);
+    p.v = *dptr(s, i, 4);
+    p.w = *dptr(s, i, 5);
+    p.e = LAY::CE ? *dptr(s, i, LAY::D_E) : 0.0;
+    p.sigt = LAY::SIG ? *dptr(s, i, LAY::D_SIG) : 0.0;
+    p.G = LAY::GG ? *dptr(s, i, LAY::D_G) : 0.0;
+    p.L = LAY::LL ? *dptr(s, i, LAY::D_L) : 0.0;
+    p.hid = *uptr(s, i, 0);
+    p.step = *uptr(s, i, 1);
+    p.gc = *uptr(s, i, 2);
+    p.prob = *uptr(s, i, 3);
     p.hq = 0;
     p.ncoll = 0;
     if (LAY::DIGEST && dig) {
-        p.hq = ((const long long *)dfield(s, LAY::D_HQ))[i];
-        p.ncoll = ufield(s, 4)[i];
+        p.hq = *(const long long *)dptr(s, i, LAY::D_HQ);
+        p.ncoll = *uptr(s, i, 4);
     }
 }
 

@@ -45,6 +45,7 @@ struct StackArgs {
     long scap;                  // particles per ordinary stripe
     long ocap;                  // particles in the overflow stripe
     long stripe_bytes;          // bytes of one ordinary stripe region
+    long tile_bytes;            // bytes of one 64-particle tile
     long event_bytes;           // bytes of one event (all stripes)
     unsigned int *sizes;        // [3][E][NSTRIPE] counters, CTR_STRIDE apart
     unsigned long long threshold;
@@ -59,10 +60,10 @@ __device__ __forceinline__ unsigned int *stripe_ctr(const StackArgs &A, int set,
     return A.sizes + ((long)(set * E + e) * NSTRIPE + s) * CTR_STRIDE;
 }
 
-__device__ __forceinline__ SoA stripe_soa(const StackArgs &A, char *bank, int e, int s, int nd)
+// stripe s of event e's stack: a run of 64-particle tiles
+__device__ __forceinline__ Tiles stripe_soa(const StackArgs &A, char *bank, int e, int s, int nd)
 {
-    long cap = (s == NSTRIPE - 1) ? A.ocap : A.scap;
-    return SoA{bank + (long)e * A.event_bytes + (long)s * A.stripe_bytes, cap, nd};
+    return Tiles{bank + (long)e * A.event_bytes + (long)s * A.stripe_bytes, A.tile_bytes, nd};
 }
 
 // push the wavefront's survivors onto the output stacks of their next
@@ -302,8 +303,10 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     long scap = ((2 * cap) / (NSTRIPE - 1) + 63) / 64 * 64 + 64;
     long ocap = cap;
     long bytes = LAY::bytes(dig);
-    long stripe_bytes = (scap * bytes + 255) / 256 * 256;
-    long event_bytes = stripe_bytes * (NSTRIPE - 1) + (ocap * bytes + 255) / 256 * 256;
+    // scap and ocap are multiples of 64: stripes are whole tiles
+    long tile_bytes = 64 * bytes;
+    long stripe_bytes = scap / 64 * tile_bytes;
+    long event_bytes = stripe_bytes * (NSTRIPE - 1) + ocap / 64 * tile_bytes;
     size_t ctr_bytes = (size_t)3 * E * NSTRIPE * CTR_STRIDE * 4;
     size_t need = (size_t)event_bytes * E * 2 + ctr_bytes;
     hipError_t e = ws_reserve(ws, need);
@@ -320,6 +323,7 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.scap = scap;
     A.ocap = ocap;
     A.stripe_bytes = stripe_bytes;
+    A.tile_bytes = tile_bytes;
     A.event_bytes = event_bytes;
     A.sizes = (unsigned int *)((char *)ws.ptr + (size_t)event_bytes * E * 2);
     A.threshold = (unsigned long long)thr;
