@@ -74,8 +74,15 @@ def _wall(P, reps, **kw):
 def sweep() -> dict:
     """Measurement sweep (tuned knobs from the autotuner next to the defaults)."""
     from paper_2506_00263_amd import autotune, inputs, mcx
-    out = {"lattice": [], "pincell_ce": [], "backward": [], "batch": {}}
+    out = {"box": [], "lattice": [], "pincell_ce": [], "backward": [], "batch": {}}
     scheds = (("naive", "fused"), ("async", "fused"), ("async", "split"), ("stack", "fused"), ("stack", "split"))
+    for n in (10_000, 100_000, 1_000_000, 10_000_000):
+        P = mcx.Problem(inputs.cfg1_box(n))
+        for s, dc in scheds:
+            t = _wall(P, 3, sched=s, decomp=dc)
+            out["box"].append({"histories": n, "sched": s, "decomp": dc, "ms": 1e3 * t, "hist_per_s": n / t})
+            print("sweep box", out["box"][-1], file=sys.stderr, flush=True)
+        del P
     for n in (100_000, 1_000_000, 10_000_000):
         P = mcx.Problem(inputs.cfg2_lattice(n))
         reps = 3 if n < 10_000_000 else 2
@@ -143,15 +150,15 @@ def sweep() -> dict:
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sched", default="async")
     ap.add_argument("--decomp", default="fused")
     ap.add_argument("--no-extras", action="store_true", help="time only the headline configuration")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print one JSON object with the measurement sweep: "
-                         "lattice histories 1e5..1e7, the continuous-energy pin cell over bins, lookups and "
+                         "box histories 1e4..1e7, lattice histories 1e5..1e7, the continuous-energy pin cell over bins, lookups and "
                          "event decompositions, backward/forward per scheduler and the batch as one launch "
                          "vs one launch per problem")
     ap.add_argument("--copy-mib", type=int, default=0,

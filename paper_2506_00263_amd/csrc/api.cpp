@@ -60,6 +60,7 @@ struct mcx_problem_s {
     unsigned int *h_flag = nullptr;       // pinned
     RunCtl *h_ctl = nullptr;              // pinned
     Workspace ws;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;   // reused by LaunchTimer
     // state
     bool tallies_valid = false;
     bool have_forward = false;
@@ -509,6 +510,10 @@ extern "C" void mcx_destroy_problem(mcx_problem_t h)
     if (h->d_prefix) hipFree(h->d_prefix);
     if (h->d_tally) hipFree(h->d_tally);
     if (h->d_trep) hipFree(h->d_trep);
+    for (auto &ev : h->timer_events) {
+        hipEventDestroy(ev.first);
+        hipEventDestroy(ev.second);
+    }
     if (h->d_ctl) hipFree(h->d_ctl);
     if (h->d_G) hipFree(h->d_G);
     if (h->d_w) hipFree(h->d_w);
@@ -639,9 +644,9 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
     a.lacc_words = 0;
     if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
-    // a small energy-bin tally is summed per block in LDS, then added once
-    if (h->n == 1 && mode == MODE_FWD && h->pd[0].tally_kind == MCX_TALLY_ENERGY && h->pd[0].n_ebins <= LT_MAX_BINS)
-        a.lacc_words = h->pd[0].n_ebins;
+    // a small tally (energy bins or mesh cells x groups) is summed per block
+    // in LDS, then added once per block
+    if (h->n == 1 && mode == MODE_FWD && h->hp[0].n_bins <= LT_MAX_BINS) a.lacc_words = (int)h->hp[0].n_bins;
     a.tl_bytes = (h->n == 1 && h->pd[0].tl_bytes <= TL_MAX_BYTES) ? h->pd[0].tl_bytes : 0;
     a.stream = stream;
     a.num_cus = h->num_cus;
@@ -660,6 +665,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     LaunchTimer tm;
     tm.on = o.time_kernels != 0;
     tm.stream = stream;
+    tm.pool = &h->timer_events;
     hipError_t e = hipSuccess;
     if (total > 0) {
         if (o.sched == MCX_SCHED_NAIVE) e = launch_naive(a, st, tm);

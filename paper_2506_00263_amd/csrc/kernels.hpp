@@ -11,36 +11,43 @@
 
 namespace mcx {
 
-// Per-launch HIP-event timing on the run's stream (optional).
+// Per-launch HIP-event timing on the run's stream (optional).  Events come
+// from a pool owned by the problem handle and are reused across runs, so
+// timing adds two event records per launch and no event creation.
 struct LaunchTimer {
     bool on = false;
     hipStream_t stream = nullptr;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> *pool = nullptr;
+    size_t used = 0;
     void begin()
     {
-        if (!on) return;
-        hipEvent_t a, b;
-        hipEventCreate(&a);
-        hipEventCreate(&b);
-        hipEventRecord(a, stream);
-        ev.emplace_back(a, b);
+        if (!on || !pool) return;
+        if (used == pool->size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                return;
+            }
+            pool->emplace_back(a, b);
+        }
+        (void)hipEventRecord((*pool)[used].first, stream);
     }
     void end()
     {
-        if (!on || ev.empty()) return;
-        hipEventRecord(ev.back().second, stream);
+        if (!on || !pool || used == pool->size()) return;
+        (void)hipEventRecord((*pool)[used].second, stream);
+        ++used;
     }
     // after the stream has been synchronised
     double total_ms()
     {
         double t = 0.0;
-        for (auto &p : ev) {
+        for (size_t i = 0; pool && i < used; ++i) {
             float ms = 0.f;
-            if (hipEventElapsedTime(&ms, p.first, p.second) == hipSuccess) t += ms;
-            hipEventDestroy(p.first);
-            hipEventDestroy(p.second);
+            if (hipEventElapsedTime(&ms, (*pool)[i].first, (*pool)[i].second) == hipSuccess) t += ms;
         }
-        ev.clear();
+        used = 0;
         return t;
     }
 };

@@ -367,9 +367,9 @@ __device__ __forceinline__ void isotropic(double xi_mu, double xi_phi, Part &p)
 
 // ---------------------------------------------------------------- tallies
 
-// lt: this block's LDS copy of the bins (few bins: every flight would hit the
-// same few global words, and the device serialises atomics per address), or
-// null to add into the global tally directly
+// lt: this block's LDS copy of the bins (a small tally: every flight would hit
+// the same few global words, and the device serialises atomics per address),
+// or null to add into the global tally directly
 template <int MODE>
 __device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long bin, double len,
                                       unsigned long long *lt = nullptr)
@@ -410,7 +410,8 @@ __device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, do
 // position: visit the mesh cells the segment crosses; every crossing
 // parameter is measured from the flight start; ties go x, y, z.
 template <int MODE, class TB>
-__device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &ln, Part &p, double d, int g)
+__device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &ln, Part &p, double d, int g,
+                                          unsigned long long *lt)
 {
     const int n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2];
     const double *mx = T.mx(), *my = T.my(), *mz = T.mz();
@@ -428,7 +429,7 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &l
         if (t2 < tm) { tm = t2; a = 2; }
         double tend = (tm < d) ? tm : d;
         long bin = (((long)g * n2 + i2) * n1 + i1) * n0 + i0;
-        score<MODE>(P, ln, p, bin, tend - tprev);
+        score<MODE>(P, ln, p, bin, tend - tprev, lt);
         if (tm >= d) break;
         if (a == 0) {
             i0 += (p.u > 0.0) ? 1 : -1;
@@ -473,7 +474,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         return;
     }
     if (P.tally_kind == 0) {
-        walk_mesh<MODE>(P, T, ln, p, d, g);
+        walk_mesh<MODE>(P, T, ln, p, d, g, cx.ltally);
     } else {
         int k;
         if (P.ebin_inv != 0.0) {
