@@ -346,9 +346,14 @@ typedef struct {
     orc_counts *cnt;
     uint64_t qsum_total;      /* running exact sum of q                         */
     int overflow;
+    /* time split of the current flight (n_tbins > 0): flight start time, speed,
+       bin width, current bin, bins without time */
+    double t0, v, tw;
+    int32_t tk;
+    int64_t nbase;
 } orc_acc;
 
-static void orc_score(const orc_problem *p, orc_acc *acc, int64_t bin, double len)
+static void orc_score_bin(const orc_problem *p, orc_acc *acc, int64_t bin, double len)
 {
     if (acc->mode == 1) {
         acc->G = acc->G + (acc->w[bin] * len);
@@ -367,6 +372,45 @@ static void orc_score(const orc_problem *p, orc_acc *acc, int64_t bin, double le
     uint64_t before = acc->qsum_total;
     acc->qsum_total = before + (uint64_t)q;
     if (acc->qsum_total < before || acc->qsum_total >= 0x8000000000000000ull) acc->overflow = 1;
+}
+
+/* Largest k in [0, n-1] with k dt <= t: a first guess from t / dt, then
+   corrected against the edges k dt (the edges are exactly these products). */
+static int32_t orc_time_bin(double t, double dt, int32_t n)
+{
+    double g = t / dt;
+    int32_t k = 0;
+    if (g > 0.0) k = (g < (double)n) ? (int32_t)g : n - 1;
+    while (k + 1 < n && ((double)(k + 1) * dt) <= t) k = k + 1;
+    while (k > 0 && ((double)k * dt) > t) k = k - 1;
+    return k;
+}
+
+/* Score the piece [a, b] of the current flight (lengths from its start) into
+   bin `bin` of the time-free tally.  With time bins the piece is cut where
+   the particle's time t0 + s / v crosses a bin edge: the edge after bin k
+   lies at length ((k+1) dt - t0) v; the last bin takes the rest. */
+static void orc_score_piece(const orc_problem *p, orc_acc *acc, int64_t bin, double a, double b)
+{
+    if (p->n_tbins <= 0) {
+        orc_score_bin(p, acc, bin, b - a);
+        return;
+    }
+    for (;;) {
+        int32_t k = acc->tk;
+        if (k + 1 >= p->n_tbins) {
+            orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, b - a);
+            return;
+        }
+        double se = (((double)(k + 1) * acc->tw) - acc->t0) * acc->v;
+        if (se >= b) {
+            orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, b - a);
+            return;
+        }
+        orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, se - a);
+        a = se;
+        acc->tk = k + 1;
+    }
 }
 
 /* Track-length mesh tally over one flight from pos (direction dir, length d):
@@ -395,7 +439,7 @@ static void orc_tally_mesh(const orc_problem *p, orc_acc *acc, const double pos[
         if (t[2] < tm) { tm = t[2]; a = 2; }
         double t1 = (tm < d) ? tm : d;
         int64_t bin = (((int64_t)g * n[2] + idx[2]) * n[1] + idx[1]) * n[0] + idx[0];
-        orc_score(p, acc, bin, t1 - t0);
+        orc_score_piece(p, acc, bin, t0, t1);
         if (tm >= d) break;
         idx[a] = idx[a] + ((dir[a] > 0.0) ? 1 : -1);
         if (idx[a] < 0 || idx[a] >= n[a]) break;
@@ -410,7 +454,7 @@ static void orc_tally_mesh(const orc_problem *p, orc_acc *acc, const double pos[
 static void orc_tally_energy(const orc_problem *p, orc_acc *acc, double e, double d)
 {
     int32_t k = orc_cell_index_fast(p->e_edges, p->n_ebins, e, 1.0);
-    orc_score(p, acc, k, d);
+    orc_score_piece(p, acc, k, 0.0, d);
 }
 
 /* ------------------------------------------------------ elastic kinematics */
@@ -508,6 +552,13 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
     cnt->sourced += 1;
 
     uint32_t flights = 0, collisions = 0, fate = ORC_FATE_LEAK;
+    double t = 0.0;                      /* particle time (time-binned tallies) */
+    if (p->n_tbins > 0) {
+        acc->tw = p->t_max / (double)p->n_tbins;
+        acc->nbase = (p->tally_kind == 0)
+                         ? (int64_t)p->mesh_n[0] * p->mesh_n[1] * p->mesh_n[2] * (p->energy_mode == 0 ? p->n_grp : 1)
+                         : (int64_t)p->n_ebins;
+    }
     acc->hq = 0;
     acc->G = 0.0;
     acc->L = 0.0;
@@ -533,6 +584,22 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
         double dsurf = orc_distance(p, pos, dir, cell, &surf);
         int collide = dcol < dsurf;
         double d = collide ? dcol : dsurf;
+        /* time: a flight that would reach t_max ends there (ties go to the
+           time boundary); the tally pieces are split at time-bin edges */
+        int timecut = 0;
+        double v = 0.0;
+        if (p->n_tbins > 0) {
+            v = (p->energy_mode == 0) ? p->speed[g] : p->speed_coef * orc_sqrt(e);
+            double dtime = (p->t_max - t) * v;
+            if (!(d < dtime)) {
+                d = dtime;
+                timecut = 1;
+                collide = 0;
+            }
+            acc->t0 = t;
+            acc->v = v;
+            acc->tk = orc_time_bin(t, acc->tw, p->n_tbins);
+        }
         /* track-length tally along the flight */
         if (acc->mode != 2) {
             if (p->tally_kind == 0) orc_tally_mesh(p, acc, pos, dir, d, g);
@@ -548,6 +615,12 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
         pos[2] = pos[2] + (d * dir[2]);
         flights += 1;
         cnt->flights += 1;
+        if (timecut) {
+            fate = ORC_FATE_CUTOFF;
+            cnt->cutoffs += 1;
+            break;
+        }
+        if (p->n_tbins > 0) t = t + (d / v);
         if (collide) {
             collisions += 1;
             cnt->collisions += 1;
@@ -721,7 +794,9 @@ void orc_tally_segment(const orc_problem *p, const double pos[3], const double d
     acc.mode = 3;
     acc.dtally = out;
     acc.cnt = &local;
-    orc_tally_mesh(p, &acc, pos, dir, d, g);
+    orc_problem q = *p;           /* the mesh walk alone, without time bins */
+    q.n_tbins = 0;
+    orc_tally_mesh(&q, &acc, pos, dir, d, g);
 }
 
 double orc_ce_xs_hook(const orc_problem *p, int32_t m, double e, double *sa, double *ss)

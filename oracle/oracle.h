@@ -57,6 +57,16 @@ typedef struct {
     uint32_t problem_id;
     uint64_t seed;
     int64_t max_steps;
+    /* time-binned tallies (0 bins: no time dimension).  A particle starts at
+       time 0 and moves at speed v: speed[g] (multigroup) or
+       speed_coef * sqrt(E) (continuous energy).  A flight that would reach
+       t_max ends there and the history ends (a cutoff).  Bins are
+       [k dt, (k+1) dt), dt = t_max / n_tbins; the tally is laid out
+       [time bin][bins without time]. */
+    int32_t n_tbins;
+    double t_max;
+    const double *speed;       /* [G], multigroup                            */
+    double speed_coef;         /* continuous energy                          */
 } orc_problem;
 
 /* what a history ended with */

@@ -47,7 +47,8 @@ class OrcProblem(C.Structure):
         ("src_radius", C.c_double), ("mesh_n", C.c_int32 * 3), ("mesh_x", C.c_void_p),
         ("mesh_y", C.c_void_p), ("mesh_z", C.c_void_p), ("n_ebins", C.c_int32), ("e_edges", C.c_void_p),
         ("tally_scale_log2", C.c_int32), ("problem_id", C.c_uint32), ("seed", C.c_uint64),
-        ("max_steps", C.c_int64),
+        ("max_steps", C.c_int64), ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p),
+        ("speed_coef", C.c_double),
     ]
 
 
@@ -175,6 +176,11 @@ class Problem:
         s.problem_id = d["problem_id"]
         s.seed = d["seed"]
         s.max_steps = d["max_steps"]
+        s.n_tbins = int(d.get("n_tbins", 0))
+        s.t_max = float(d.get("t_max", 0.0))
+        if s.n_tbins > 0 and d["energy_mode"] == 0:
+            s.speed = arr("speed", np.float64)
+        s.speed_coef = float(d.get("speed_coef", 0.0))
         self.s = s
         self._keep = keep
 
@@ -182,8 +188,10 @@ class Problem:
     def n_bins(self) -> int:
         d = self.d
         if d["tally_kind"] == 0:
-            return int(np.prod(d["mesh_n"])) * int(d["n_grp"])
-        return int(d["n_ebins"])
+            nb = int(np.prod(d["mesh_n"])) * (int(d["n_grp"]) if d["energy_mode"] == 0 else 1)
+        else:
+            nb = int(d["n_ebins"])
+        return nb * max(1, int(d.get("n_tbins", 0)))
 
 
 def _ranges(h0: int, h1: int, threads: int):

@@ -100,6 +100,7 @@ def _base(n_histories: int, seed: int, problem_id: int) -> dict:
         src_radius=0.0, src_isotropic=1, src_dir=_f64([0, 0, 1]), src_group=0,
         tally_kind=TALLY_MESH, mesh_n=_i32([1, 1, 1]), mesh_x=_f64([0, 1]), mesh_y=_f64([0, 1]),
         mesh_z=_f64([0, 1]), n_ebins=0, e_edges=_f64([0.0, 1.0]), tally_scale_log2=32,
+        n_tbins=0, t_max=0.0, speed=_f64([1.0]), speed_coef=0.0,
     )
 
 
@@ -306,10 +307,27 @@ def cfg5_batch(n_problems: int = 256, hist_scale: float = 1.0, data_seed: int = 
 
 
 def n_bins(d: dict) -> int:
-    """Number of tally bins of a problem description."""
+    """Number of tally bins of a problem description (times the time bins)."""
     if d["tally_kind"] == TALLY_MESH:
-        return int(np.prod(d["mesh_n"])) * int(d["n_grp"])
-    return int(d["n_ebins"])
+        nb = int(np.prod(d["mesh_n"])) * (int(d["n_grp"]) if d["energy_mode"] == ENERGY_MG else 1)
+    else:
+        nb = int(d["n_ebins"])
+    return nb * max(1, int(d.get("n_tbins", 0)))
+
+
+def with_time_bins(d: dict, n_tbins: int, t_max: float, speed=None, speed_coef: float = 0.0) -> dict:
+    """A copy of problem d with a time-binned tally: n_tbins equal bins over
+    [0, t_max); a flight that would reach t_max ends there.  Speeds: one per
+    group (multigroup, default 10^(-g/2)) or speed_coef * sqrt(E) (continuous
+    energy)."""
+    d = dict(d)
+    d["n_tbins"] = int(n_tbins)
+    d["t_max"] = float(t_max)
+    if d["energy_mode"] == ENERGY_MG:
+        g = np.arange(int(d["n_grp"]), dtype=np.float64)
+        d["speed"] = _f64(speed if speed is not None else 10.0 ** (-0.5 * g))
+    d["speed_coef"] = float(speed_coef)
+    return d
 
 
 def config(k: int, **kw):
