@@ -585,14 +585,16 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
         int collide = dcol < dsurf;
         double d = collide ? dcol : dsurf;
         /* time: a flight that would reach t_max ends there (ties go to the
-           time boundary); the tally pieces are split at time-bin edges */
+           time boundary); the tally pieces are split at time-bin edges.  The
+           sum t + d / v of an earlier flight can round to just past t_max:
+           the remaining length is then zero, never negative. */
         int timecut = 0;
         double v = 0.0;
         if (p->n_tbins > 0) {
             v = (p->energy_mode == 0) ? p->speed[g] : p->speed_coef * orc_sqrt(e);
             double dtime = (p->t_max - t) * v;
             if (!(d < dtime)) {
-                d = dtime;
+                d = (dtime > 0.0) ? dtime : 0.0;
                 timecut = 1;
                 collide = 0;
             }
