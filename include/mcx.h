@@ -138,6 +138,19 @@ typedef struct {
     uint64_t seed;
     uint64_t n_histories;
     int64_t max_steps;
+    /* Time-binned tally (the temporal tally resolution of Sec. 4 of the
+     * paper).  n_tbins > 0 adds a time dimension of n_tbins equal bins over
+     * [0, t_max): a particle starts at time 0 and moves at speed[g] (MG,
+     * n_grp entries, cm per unit time) or speed_coef * sqrt(E) (CE); a
+     * flight that would reach t_max stops there and its history ends (fate
+     * CUTOFF, counted in cutoffs); a track piece is split where the
+     * particle's time passes a bin edge.  Bins are laid out [time bin][bins
+     * without time].  n_tbins = 0: no time dimension (the other three
+     * fields are ignored).  Every problem of a handle has time bins or none. */
+    int32_t n_tbins;
+    double t_max;
+    const double *speed;
+    double speed_coef;
 } mcx_problem_desc;
 
 /* Options of one run.  Zero-initialise and set what you need; zero means the

@@ -24,10 +24,12 @@ namespace {
 struct HostProblem {
     mcx_problem_desc d;
     std::vector<double> xpl, ypl, cxs, cys, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, mx, my, mz, eedges;
+    std::vector<double> speed;            // group speeds (time bins, multigroup)
     std::vector<int32_t> cmat, hash_lo, hash_hi;
     double hash_ln_lo = 0.0, hash_inv = 0.0;
     int32_t hash_bins = 0;
-    int64_t n_bins = 0;
+    int64_t n_bins = 0;                   // all bins (time bins included)
+    int64_t nbase = 0;                    // bins without time
 };
 
 }  // namespace
@@ -288,7 +290,24 @@ static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int
     } else {
         return fail(h, MCX_E_INVALID_ARG, "problem %d: bad tally_kind", k);
     }
-    if (d.energy_mode == MCX_CE && d.tally_kind == MCX_TALLY_MESH && false) return MCX_E_INVALID_ARG;
+    hp.nbase = hp.n_bins;
+    hp.speed = {1.0};
+    if (d.n_tbins < 0 || d.n_tbins > (1 << 20))
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: n_tbins must be 0..%d", k, 1 << 20);
+    if (d.n_tbins > 0) {
+        if (!(d.t_max > 0.0) || !std::isfinite(d.t_max))
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: t_max must be finite and > 0", k);
+        if (d.energy_mode == MCX_MG) {
+            if (!d.speed) return fail(h, MCX_E_INVALID_ARG, "problem %d: time bins need group speeds", k);
+            hp.speed = copy_of(d.speed, d.n_grp);
+            for (double v : hp.speed)
+                if (!(v > 0.0) || !std::isfinite(v))
+                    return fail(h, MCX_E_INVALID_ARG, "problem %d: speeds must be finite and > 0", k);
+        } else if (!(d.speed_coef > 0.0) || !std::isfinite(d.speed_coef)) {
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: speed_coef must be finite and > 0", k);
+        }
+        hp.n_bins *= d.n_tbins;
+    }
     if (d.tally_scale_log2 < 0 || d.tally_scale_log2 > 62)
         return fail(h, MCX_E_INVALID_ARG, "problem %d: tally_scale_log2 must be 0..62", k);
     if (d.n_histories >= (1ull << 32)) return fail(h, MCX_E_INVALID_ARG, "problem %d: at most 2^32-1 histories", k);
@@ -316,18 +335,19 @@ static mcx_status upload(mcx_problem_t h)
     BlobBuilder bb;
     struct Offs {
         size_t xpl, ypl, cxs, cys, cmat, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, hlo, hhi, mx, my, mz, ee;
+        size_t speed;
     };
     std::vector<Offs> off(h->n);
     std::vector<size_t> tl_base(h->n), tl_bytes(h->n);
-    std::vector<std::array<int32_t, 11>> tl_off(h->n);
+    std::vector<std::array<int32_t, 12>> tl_off(h->n);
     for (int k = 0; k < h->n; ++k) {
         HostProblem &p = h->hp[k];
         Offs &o = off[k];
         // the small per-event tables, packed: doubles, then the int32 materials
-        const std::vector<double> *dt[10] = {&p.sig_t, &p.sig_s, &p.cdf, &p.xpl, &p.ypl,
-                                             &p.cxs,   &p.cys,   &p.mx,  &p.my,  &p.mz};
+        const std::vector<double> *dt[TL_NDBL] = {&p.sig_t, &p.sig_s, &p.cdf, &p.xpl, &p.ypl, &p.cxs,
+                                                  &p.cys,   &p.mx,    &p.my,  &p.mz,  &p.speed};
         std::vector<double> packed;
-        for (int t = 0; t < 10; ++t) {
+        for (int t = 0; t < TL_NDBL; ++t) {
             tl_off[k][t] = (int32_t)packed.size();
             packed.insert(packed.end(), dt[t]->begin(), dt[t]->end());
         }
@@ -344,6 +364,7 @@ static mcx_status upload(mcx_problem_t h)
         o.ypl = b + 8 * (size_t)tl_off[k][TL_YPL]; o.cxs = b + 8 * (size_t)tl_off[k][TL_CXS];
         o.cys = b + 8 * (size_t)tl_off[k][TL_CYS]; o.mx = b + 8 * (size_t)tl_off[k][TL_MX];
         o.my = b + 8 * (size_t)tl_off[k][TL_MY]; o.mz = b + 8 * (size_t)tl_off[k][TL_MZ];
+        o.speed = b + 8 * (size_t)tl_off[k][TL_SPEED];
         o.cmat = b + 4 * (size_t)tl_off[k][TL_CMAT];
         o.egrid = bb.add(p.egrid); o.siga = bb.add(p.siga); o.sigs = bb.add(p.sigs); o.awr = bb.add(p.awr);
         o.dens = bb.add(p.dens); o.hlo = bb.add(p.hash_lo); o.hhi = bb.add(p.hash_hi);
@@ -463,7 +484,14 @@ static mcx_status upload(mcx_problem_t h)
         P.SS = ga + 1 + 2 * mg;
         P.tl_src = (const double *)(base + tl_base[k]);
         P.tl_bytes = (int32_t)std::min<size_t>(tl_bytes[k], 1u << 30);
-        for (int t = 0; t < 11; ++t) P.tl_off[t] = tl_off[k][t];
+        for (int t = 0; t < 12; ++t) P.tl_off[t] = tl_off[k][t];
+        P.n_tbins = d.n_tbins;
+        P.t_max = d.n_tbins > 0 ? d.t_max : 0.0;
+        P.tw = d.n_tbins > 0 ? d.t_max / (double)d.n_tbins : 0.0;
+        P.speed_coef = d.speed_coef;
+        P.nbase = hp.nbase;
+        P.n_bins = hp.n_bins;
+        P.speed = (const double *)(base + o.speed);
     }
     return MCX_OK;
 }
@@ -485,6 +513,8 @@ extern "C" mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t 
         for (int k = 1; k < n_problems; ++k)
             if (descs[k].geometry != h->geom || descs[k].energy_mode != h->emode || descs[k].tally_kind != h->tally_kind)
                 s = fail(h, MCX_E_INVALID_ARG, "problems of one handle must share geometry, energy mode and tally kind");
+            else if ((descs[k].n_tbins > 0) != (descs[0].n_tbins > 0))
+                s = fail(h, MCX_E_INVALID_ARG, "problems of one handle must all have time bins or none");
     }
     if (s == MCX_OK) {
         hipError_t e = hipGetDevice(&h->device);
@@ -608,11 +638,12 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     }
     unsigned long long total = prefix[h->n];
     // a single problem's energy-bin tally too large for LDS: adds go to
-    // replicas, summed into the tally after the launch
+    // replicas, summed into the tally after the launch (up to 2^24 bins;
+    // larger tallies are spread enough to take the adds directly)
     const bool use_trep = h->n == 1 && mode == MODE_FWD && h->pd[0].tally_kind == MCX_TALLY_ENERGY &&
-                          h->pd[0].n_ebins > LT_MAX_BINS;
+                          h->hp[0].n_bins > LT_MAX_BINS && h->hp[0].n_bins <= (1 << 24);
     if (use_trep) {
-        size_t words = (size_t)TREP * h->pd[0].n_ebins;
+        size_t words = (size_t)TREP * (size_t)h->hp[0].n_bins;
         if (h->trep_words < words) {
             if (h->d_trep) HIP_TRY(h, hipFree(h->d_trep));
             h->d_trep = nullptr;
@@ -642,6 +673,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.emode = h->emode;
     a.mode = mode;
     a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
+    a.time = h->pd[0].n_tbins > 0 ? 1 : 0;
     a.lacc_words = 0;
     if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
     // a small tally (energy bins or mesh cells x groups) is summed per block
@@ -672,7 +704,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
         else if (o.sched == MCX_SCHED_STACK) e = launch_stack(a, h->ws, st, tm, h->h_flag);
         else e = launch_async(a, h->ws, st, tm);
         if (e == hipSuccess && use_trep) {
-            int n = h->pd[0].n_ebins;
+            int n = (int)h->hp[0].n_bins;
             hipLaunchKernelGGL(trep_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
                                h->pd[0].tally, (const unsigned long long *)h->d_trep, n, TREP);
             e = hipGetLastError();

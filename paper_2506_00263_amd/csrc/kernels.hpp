@@ -1,5 +1,7 @@
-// Host-visible launch interface of the scheduler kernels (implemented in
-// sched_naive.hip, sched_stack.hip and sched_async.hip).
+// Host-visible launch interface of the scheduler kernels (kernels in
+// sched_naive.hpp, sched_stack.hpp and sched_async.hpp; each is built once
+// for runs without time bins, sched_*.hip, and once for runs with them,
+// sched_*_time.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -61,6 +63,7 @@ struct LaunchArgs {
     RunCtl *ctl;                           // device control block
     void *digest;                          // device Digest array or null
     int geom, emode, mode, split;
+    int time;                              // 1: the problems have time-binned tallies
     int lacc_words;                        // pass B per-block sums in LDS (single problem), 0 = none
     int tl_bytes;                          // single problem: packed tables copied to LDS; 0 = read globally
     hipStream_t stream;
@@ -93,5 +96,9 @@ hipError_t launch_naive(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm);
 hipError_t launch_stack(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
                         unsigned int *host_flag_pinned);
 hipError_t launch_async(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm);
+hipError_t launch_naive_time(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm);
+hipError_t launch_stack_time(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
+                             unsigned int *host_flag_pinned);
+hipError_t launch_async_time(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm);
 
 }  // namespace mcx

@@ -44,7 +44,7 @@ struct ProbDev {
     double ebin_lnlo, ebin_inv;      // energy bins uniform in ln E
     double tscale;                   // 2^tally_scale_log2
     unsigned long long *tally;       // this problem's bins
-    unsigned long long *trep;        // [TREP][n_ebins] replicas of a large energy-bin tally
+    unsigned long long *trep;        // [TREP][n_bins] replicas of a large energy-bin tally
                                      // (summed into tally after the run), or null
     // random numbers and histories of the current run
     uint32_t key0, key1;
@@ -59,15 +59,26 @@ struct ProbDev {
     unsigned long long *SL, *SA, *SS;  // pass B sums [n_mat*n_grp] (int64 bits)
     int32_t acc_off, pad;            // offset of this problem in per-wave LDS sums
     // The small tables every event reads (Sigma_t, Sigma_s, transfer CDF,
-    // planes, pin centres, mesh edges, then the int32 cell materials) sit
-    // packed at tl_src; single-problem launches copy them into LDS.
+    // planes, pin centres, mesh edges, group speeds, then the int32 cell
+    // materials) sit packed at tl_src; single-problem launches copy them
+    // into LDS.
     // tl_off[t]: offset of table t in 8-byte words (TL_CMAT: in 4-byte words).
     const double *tl_src;
     int32_t tl_bytes;                // packed size, a multiple of 16
-    int32_t tl_off[11];
+    int32_t tl_off[12];
+    // time-binned tally (temporal tally resolution, paper Sec. 4): n_tbins
+    // equal bins of width tw = t_max / n_tbins; 0 = no time dimension.  A
+    // particle moves at speed[g] (multigroup, a packed table) or
+    // speed_coef * sqrt(E); bins are laid out [time bin][nbase bins].
+    int32_t n_tbins, pad1;
+    double t_max, tw, speed_coef;
+    long long nbase;                 // bins of the tally without time
+    long long n_bins;                // all bins of this problem's tally
+    const double *speed;
 };
 
-enum : int { TL_SIG_T = 0, TL_SIG_S, TL_CDF, TL_XPL, TL_YPL, TL_CXS, TL_CYS, TL_MX, TL_MY, TL_MZ, TL_CMAT };
+enum : int { TL_SIG_T = 0, TL_SIG_S, TL_CDF, TL_XPL, TL_YPL, TL_CXS, TL_CYS, TL_MX, TL_MY, TL_MZ, TL_SPEED, TL_CMAT };
+constexpr int TL_NDBL = TL_CMAT;      // tables of doubles in front of the int32 materials
 constexpr int TL_MAX_BYTES = 32768;   // larger tables stay in global memory
 constexpr int LT_MAX_BINS = 4096;     // energy-bin tallies up to this size are summed in LDS per block
 constexpr int TREP = 16;              // larger ones go to TREP replicas chosen by wavefront

@@ -21,6 +21,7 @@
 // release before the queue is put back and read after an acquire, so other
 // XCDs see it.  No wavefront ever waits for another block's progress except
 // for bounded retries when every queue is momentarily claimed.
+#pragma once
 #include <algorithm>
 
 #include "bank.hpp"
@@ -326,10 +327,10 @@ struct AsyncWave {
     }
 };
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int TIME>
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2))) async_kernel(AsyncArgs A)
 {
-    using LAY = Layout<EMODE, MODE, SPLIT>;
+    using LAY = Layout<EMODE, MODE, SPLIT, TIME>;
     constexpr int E = SPLIT ? 4 : 1;
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const bool dig = A.digest != nullptr;
@@ -463,7 +464,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BATCH ?
         uint32_t out = 0;
         if (act) {
             const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
-            ne = run_event<GEOM, EMODE, MODE, SPLIT>(ev, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
+            ne = run_event<GEOM, EMODE, MODE, SPLIT, TIME>(ev, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
         }
         wc.dispatch(act);
         wc.outcomes(act, out);
@@ -477,7 +478,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BATCH ?
     }
 }
 
-__global__ void arena_init(AsyncArgs A, unsigned int waves)
+static __global__ void arena_init(AsyncArgs A, unsigned int waves)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) A.ctl->active = waves;
@@ -495,10 +496,10 @@ __global__ void arena_init(AsyncArgs A, unsigned int waves)
     }
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH>
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int TIME>
 static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
-    using LAY = Layout<EMODE, MODE, SPLIT>;
+    using LAY = Layout<EMODE, MODE, SPLIT, TIME>;
     constexpr int E = SPLIT ? 4 : 1;
     const bool dig = a.digest != nullptr;
     // one partial link per event plus one: a stash with no free link then
@@ -510,7 +511,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     int link_bytes = 64 * LAY::bytes(dig);
     const int tl_bytes = BATCH ? 0 : a.tl_bytes;
     size_t lds = tabs_lds_offset((size_t)L * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
-    auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH>;
+    auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, TIME>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds);
     if (e != hipSuccess) return e;
@@ -559,33 +560,36 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     return hipGetLastError();
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT>
+template <int GEOM, int EMODE, int MODE, int SPLIT, int TIME>
 static hipError_t async_b(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
-    return (a.n_probs > 1 || a.tl_bytes == 0) ? async_t<GEOM, EMODE, MODE, SPLIT, true>(a, ws, st, tm)
-                                              : async_t<GEOM, EMODE, MODE, SPLIT, false>(a, ws, st, tm);
+    return (a.n_probs > 1 || a.tl_bytes == 0) ? async_t<GEOM, EMODE, MODE, SPLIT, true, TIME>(a, ws, st, tm)
+                                              : async_t<GEOM, EMODE, MODE, SPLIT, false, TIME>(a, ws, st, tm);
 }
 
-template <int GEOM, int EMODE, int MODE>
+template <int GEOM, int EMODE, int MODE, int TIME>
 static hipError_t async_s(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
-    return a.split ? async_b<GEOM, EMODE, MODE, 1>(a, ws, st, tm) : async_b<GEOM, EMODE, MODE, 0>(a, ws, st, tm);
+    return a.split ? async_b<GEOM, EMODE, MODE, 1, TIME>(a, ws, st, tm)
+                   : async_b<GEOM, EMODE, MODE, 0, TIME>(a, ws, st, tm);
 }
 
-hipError_t launch_async(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
+// every event program of one time mode (runs with or without time bins)
+template <int TIME>
+static hipError_t launch_async_tm(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
     if (a.emode == EMODE_CE) {
         if (a.geom != GEOM_LATTICE || a.mode != MODE_FWD) return hipErrorInvalidValue;
-        return async_s<GEOM_LATTICE, EMODE_CE, MODE_FWD>(a, ws, st, tm);
+        return async_s<GEOM_LATTICE, EMODE_CE, MODE_FWD, TIME>(a, ws, st, tm);
     }
     if (a.geom == GEOM_BOX) {
-        if (a.mode == MODE_FWD) return async_s<GEOM_BOX, EMODE_MG, MODE_FWD>(a, ws, st, tm);
-        if (a.mode == MODE_REPLAY_A) return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_A>(a, ws, st, tm);
-        return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_B>(a, ws, st, tm);
+        if (a.mode == MODE_FWD) return async_s<GEOM_BOX, EMODE_MG, MODE_FWD, TIME>(a, ws, st, tm);
+        if (a.mode == MODE_REPLAY_A) return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_A, TIME>(a, ws, st, tm);
+        return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_B, TIME>(a, ws, st, tm);
     }
-    if (a.mode == MODE_FWD) return async_s<GEOM_LATTICE, EMODE_MG, MODE_FWD>(a, ws, st, tm);
-    if (a.mode == MODE_REPLAY_A) return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A>(a, ws, st, tm);
-    return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B>(a, ws, st, tm);
+    if (a.mode == MODE_FWD) return async_s<GEOM_LATTICE, EMODE_MG, MODE_FWD, TIME>(a, ws, st, tm);
+    if (a.mode == MODE_REPLAY_A) return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A, TIME>(a, ws, st, tm);
+    return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B, TIME>(a, ws, st, tm);
 }
 
 }  // namespace mcx

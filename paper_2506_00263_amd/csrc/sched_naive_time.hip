@@ -1,0 +1,11 @@
+// History-based baseline: the event programs of runs with time-binned tallies.
+#include "sched_naive.hpp"
+
+namespace mcx {
+
+hipError_t launch_naive_time(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
+{
+    return launch_naive_tm<1>(a, st, tm);
+}
+
+}  // namespace mcx

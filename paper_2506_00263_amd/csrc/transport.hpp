@@ -44,6 +44,7 @@ struct Part {
     double e;         // energy (continuous energy)
     double sigt;      // total cross section of the current flight (split events)
     double G, L;      // backward accumulators
+    double t;         // particle time (time-binned tallies)
     long long hq;     // this history's tally sum (digest)
     uint32_t hid;     // history index within its problem
     uint32_t step;    // flight counter (0 = source)
@@ -99,6 +100,7 @@ struct TabsG {
     __device__ __forceinline__ const double *mx() const { return P.mx; }
     __device__ __forceinline__ const double *my() const { return P.my; }
     __device__ __forceinline__ const double *mz() const { return P.mz; }
+    __device__ __forceinline__ const double *speed() const { return P.speed; }
     __device__ __forceinline__ const int32_t *cmat() const { return P.cmat; }
 };
 
@@ -115,6 +117,7 @@ struct TabsL {
     __device__ __forceinline__ const double *mx() const { return d + P.tl_off[TL_MX]; }
     __device__ __forceinline__ const double *my() const { return d + P.tl_off[TL_MY]; }
     __device__ __forceinline__ const double *mz() const { return d + P.tl_off[TL_MZ]; }
+    __device__ __forceinline__ const double *speed() const { return d + P.tl_off[TL_SPEED]; }
     __device__ __forceinline__ const int32_t *cmat() const { return (const int32_t *)d + P.tl_off[TL_CMAT]; }
 };
 
@@ -383,7 +386,7 @@ __device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long 
                 // a large energy-bin tally: particles of a round or wavefront
                 // have similar energies and hit the same few bins, so the adds
                 // are spread over replicas
-                unsigned long long *dst = P.trep ? P.trep + (size_t)ln.rep * (size_t)P.n_ebins : P.tally;
+                unsigned long long *dst = P.trep ? P.trep + (size_t)ln.rep * (size_t)P.n_bins : P.tally;
                 __hip_atomic_fetch_add(dst + bin, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             p.hq += q;
@@ -394,6 +397,55 @@ __device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long 
         }
     } else if (MODE == MODE_REPLAY_A) {
         p.G = p.G + (P.w[bin] * len);
+    }
+}
+
+// Time split of the current flight (time-binned tallies): the flight starts
+// at time t0 in time bin k and moves at speed v.
+struct TSplit {
+    double t0, v;
+    int k;
+};
+
+// largest k in [0, n-1] with k dt <= t (0 if none): a guess from t / dt,
+// corrected against the edges k dt themselves
+__device__ __forceinline__ int time_bin(double t, double dt, int n)
+{
+    double g = t / dt;
+    int k = 0;
+    if (g > 0.0) k = (g < (double)n) ? (int)g : n - 1;
+    while (k + 1 < n && ((double)(k + 1) * dt) <= t) k = k + 1;
+    while (k > 0 && ((double)k * dt) > t) k = k - 1;
+    return k;
+}
+
+// Score the piece [a, b] of the current flight (distances from its start)
+// into bin `bin` of the tally without time.  With time bins the piece is cut
+// where the particle's time t0 + s / v passes a bin edge: the edge closing
+// bin k lies at s = ((k + 1) tw - t0) v; the last time bin takes the rest.
+template <int MODE, int TIME>
+__device__ __forceinline__ void score_piece(const ProbDev &P, Lane &ln, Part &p, TSplit &ts, long bin, double a,
+                                            double b, unsigned long long *lt)
+{
+    if (!TIME) {
+        score<MODE>(P, ln, p, bin, b - a, lt);
+        return;
+    }
+    for (;;) {
+        const int k = ts.k;
+        const long kb = (long)k * P.nbase + bin;
+        if (k + 1 >= P.n_tbins) {
+            score<MODE>(P, ln, p, kb, b - a, lt);
+            return;
+        }
+        double se = (((double)(k + 1) * P.tw) - ts.t0) * ts.v;
+        if (se >= b) {
+            score<MODE>(P, ln, p, kb, b - a, lt);
+            return;
+        }
+        score<MODE>(P, ln, p, kb, se - a, lt);
+        a = se;
+        ts.k = k + 1;
     }
 }
 
@@ -409,9 +461,9 @@ __device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, do
 // Track-length mesh tally of one flight of length d from the current
 // position: visit the mesh cells the segment crosses; every crossing
 // parameter is measured from the flight start; ties go x, y, z.
-template <int MODE, class TB>
+template <int MODE, int TIME, class TB>
 __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &ln, Part &p, double d, int g,
-                                          unsigned long long *lt)
+                                          TSplit &ts, unsigned long long *lt)
 {
     const int n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2];
     const double *mx = T.mx(), *my = T.my(), *mz = T.mz();
@@ -429,7 +481,7 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &l
         if (t2 < tm) { tm = t2; a = 2; }
         double tend = (tm < d) ? tm : d;
         long bin = (((long)g * n2 + i2) * n1 + i1) * n0 + i0;
-        score<MODE>(P, ln, p, bin, tend - tprev, lt);
+        score_piece<MODE, TIME>(P, ln, p, ts, bin, tprev, tend, lt);
         if (tm >= d) break;
         if (a == 0) {
             i0 += (p.u > 0.0) ? 1 : -1;
@@ -464,9 +516,9 @@ __device__ __forceinline__ void pass_b_add(const ProbDev &P, const EvCtx &cx, in
 }
 
 // Score a flight of length d that started at the particle's position.
-template <int EMODE, int MODE, class TB>
+template <int EMODE, int MODE, int TIME, class TB>
 __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, double d,
-                                             int m)
+                                             int m, TSplit &ts)
 {
     int g = gc_group(p.gc);
     if (MODE == MODE_REPLAY_B) {
@@ -474,7 +526,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         return;
     }
     if (P.tally_kind == 0) {
-        walk_mesh<MODE>(P, T, ln, p, d, g, cx.ltally);
+        walk_mesh<MODE, TIME>(P, T, ln, p, d, g, ts, cx.ltally);
     } else {
         int k;
         if (P.ebin_inv != 0.0) {
@@ -485,7 +537,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         } else {
             k = edge_index(P.eedges, P.n_ebins, p.e, 1.0);
         }
-        score<MODE>(P, ln, p, k, d, cx.ltally);
+        score_piece<MODE, TIME>(P, ln, p, ts, k, 0.0, d, cx.ltally);
     }
     if (MODE == MODE_REPLAY_A) p.L = p.L + d;
 }
@@ -562,6 +614,7 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
     p.sigt = 0.0;
     p.L = 0.0;
     p.G = 0.0;
+    p.t = 0.0;
     if (MODE == MODE_REPLAY_B) p.G = P.G[P.gbase + (uint64_t)(hid - P.first)];
 }
 
@@ -591,20 +644,39 @@ __device__ __forceinline__ int ev_lookup(const ProbDev &P, const TB &T, const Ev
     return EV_MOVE;
 }
 
+enum : int { FLY_SURFACE = 0, FLY_COLLIDE = 1, FLY_TIME = 2 };
+
 // Move to the next collision site or surface, scoring the track on the way.
-template <int GEOM, int EMODE, int MODE, class TB>
-__device__ __forceinline__ bool fly(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, double sigt,
-                                    double xi0, int m, int &surf)
+// With time bins a flight that would reach t_max stops there (a tie goes to
+// the time boundary) and the history ends; otherwise the particle's time
+// advances by d / v.  That sum can round to just past t_max; the remaining
+// length is then zero, never negative.
+template <int GEOM, int EMODE, int MODE, int TIME, class TB>
+__device__ __forceinline__ int fly(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, double sigt,
+                                   double xi0, int m, int &surf)
 {
     double dcol = neg_log(xi0) / sigt;
     double dsurf = surface_distance<GEOM>(P, T, p, surf);
-    bool collide = dcol < dsurf;
-    double d = collide ? dcol : dsurf;
-    score_flight<EMODE, MODE>(P, T, cx, ln, p, d, m);
+    int res = (dcol < dsurf) ? FLY_COLLIDE : FLY_SURFACE;
+    double d = (res == FLY_COLLIDE) ? dcol : dsurf;
+    TSplit ts{0.0, 0.0, 0};
+    if (TIME) {
+        const double v = (EMODE == EMODE_MG) ? T.speed()[gc_group(p.gc)] : P.speed_coef * root(p.e);
+        const double dtime = (P.t_max - p.t) * v;
+        if (!(d < dtime)) {
+            d = (dtime > 0.0) ? dtime : 0.0;
+            res = FLY_TIME;
+        }
+        ts.t0 = p.t;
+        ts.v = v;
+        ts.k = time_bin(p.t, P.tw, P.n_tbins);
+    }
+    score_flight<EMODE, MODE, TIME>(P, T, cx, ln, p, d, m, ts);
     p.x = p.x + (d * p.u);
     p.y = p.y + (d * p.v);
     p.z = p.z + (d * p.w);
-    return collide;
+    if (TIME && res != FLY_TIME) p.t = p.t + (d / ts.v);
+    return res;
 }
 
 // Cross the surface `surf`: snap to the plane, then leak, reflect or enter
@@ -723,7 +795,7 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
 }
 
 // Monolithic event: one whole flight (lookup, move with tally, collide or cross).
-template <int GEOM, int EMODE, int MODE, class TB>
+template <int GEOM, int EMODE, int MODE, int TIME, class TB>
 __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
     if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
@@ -736,9 +808,14 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
     double xi0, xi1;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
     int surf;
-    bool coll = fly<GEOM, EMODE, MODE>(P, T, cx, ln, p, sigt, xi0, m, surf);
+    const int res = fly<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, sigt, xi0, m, surf);
     out |= O_FLIGHT;
-    if (coll) {
+    if (TIME && res == FLY_TIME) {
+        out |= O_CUT;
+        finish<MODE>(P, cx, ln, p, FATE_CUTOFF);
+        return EV_DEAD;
+    }
+    if (res == FLY_COLLIDE) {
         double xi2, xi3, xi4, xi5;
         uniform_pair(k, p.hid, p.step, 1, xi2, xi3);
         uniform_pair(k, p.hid, p.step, 2, xi4, xi5);
@@ -755,7 +832,7 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
 
 // Decomposed events ------------------------------------------------------
 
-template <int GEOM, int EMODE, int MODE, class TB>
+template <int GEOM, int EMODE, int MODE, int TIME, class TB>
 __device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
     int m = material<GEOM>(P, T, p.gc);
@@ -763,10 +840,15 @@ __device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCt
     double xi0, xi1;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
     int surf;
-    bool coll = fly<GEOM, EMODE, MODE>(P, T, cx, ln, p, p.sigt, xi0, m, surf);
+    const int res = fly<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, p.sigt, xi0, m, surf);
     out |= O_FLIGHT;
+    if (TIME && res == FLY_TIME) {
+        out |= O_CUT;
+        finish<MODE>(P, cx, ln, p, FATE_CUTOFF);
+        return EV_DEAD;
+    }
     p.gc = (p.gc & ~(3u << 29)) | ((uint32_t)surf << 29);
-    return coll ? EV_COLLIDE : EV_SURFACE;
+    return (res == FLY_COLLIDE) ? EV_COLLIDE : EV_SURFACE;
 }
 
 template <int GEOM, int EMODE, int MODE, class TB>
@@ -798,13 +880,13 @@ __device__ __forceinline__ int ev_collide(const ProbDev &P, const TB &T, const E
     return EV_LOOKUP;
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, class TB>
+template <int GEOM, int EMODE, int MODE, int SPLIT, int TIME, class TB>
 __device__ __forceinline__ int run_event(int ev, const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
                                          uint32_t &out)
 {
-    if (!SPLIT) return ev_step<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
+    if (!SPLIT) return ev_step<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, out);
     if (ev == EV_LOOKUP) return ev_lookup<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
-    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
+    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, out);
     if (ev == EV_SURFACE) return ev_surface<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
     return ev_collide<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
 }

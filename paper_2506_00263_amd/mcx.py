@@ -47,6 +47,7 @@ class ProblemDesc(C.Structure):
         ("tally_kind", C.c_int32), ("mesh_n", C.c_int32 * 3), ("mesh_x", C.c_void_p), ("mesh_y", C.c_void_p),
         ("mesh_z", C.c_void_p), ("n_ebins", C.c_int32), ("e_edges", C.c_void_p), ("tally_scale_log2", C.c_int32),
         ("problem_id", C.c_uint32), ("seed", C.c_uint64), ("n_histories", C.c_uint64), ("max_steps", C.c_int64),
+        ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p), ("speed_coef", C.c_double),
     ]
 
 
@@ -182,6 +183,14 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
     s.seed = d["seed"]
     s.n_histories = d["n_histories"]
     s.max_steps = d["max_steps"]
+    s.n_tbins = int(d.get("n_tbins", 0))
+    s.t_max = float(d.get("t_max", 0.0))
+    s.speed = None
+    if s.n_tbins > 0 and d["energy_mode"] == 0:
+        if np.asarray(d["speed"]).size != d["n_grp"]:
+            raise ValueError("time bins need one speed per group")
+        s.speed = arr("speed", np.float64)
+    s.speed_coef = float(d.get("speed_coef", 0.0))
     return s
 
 

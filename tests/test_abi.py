@@ -37,8 +37,9 @@ def test_struct_sizes_match_header():
 #include <stddef.h>
 #include "mcx.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mcx_problem_desc), sizeof(mcx_run_opts), sizeof(mcx_counters_t),
-         sizeof(mcx_digest), offsetof(mcx_problem_desc, max_steps), offsetof(mcx_run_opts, time_kernels));
+  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mcx_problem_desc), sizeof(mcx_run_opts), sizeof(mcx_counters_t),
+         sizeof(mcx_digest), offsetof(mcx_problem_desc, max_steps), offsetof(mcx_run_opts, time_kernels),
+         offsetof(mcx_problem_desc, speed_coef));
   return 0;
 }
 '''
@@ -56,3 +57,4 @@ int main(void) {
     assert sizes[3] == mcx.DIGEST_DTYPE.itemsize
     assert sizes[4] == mcx.ProblemDesc.max_steps.offset
     assert sizes[5] == mcx.RunOpts.time_kernels.offset
+    assert sizes[6] == mcx.ProblemDesc.speed_coef.offset
