@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 N_HIST = 1_000_000
+NEUTRON_SPEED = 1.383e6        # cm/s per sqrt(eV)
 
 
 def algorithmic_bytes(c: dict) -> int:
@@ -71,19 +72,22 @@ def _wall(P, reps, **kw):
     return float(np.median(ts[1:]))
 
 
-def sweep() -> dict:
+SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "backward", "batch")
+
+
+def sweep(parts=SWEEP_PARTS) -> dict:
     """Measurement sweep (tuned knobs from the autotuner next to the defaults)."""
     from paper_2506_00263_amd import autotune, inputs, mcx
-    out = {"box": [], "lattice": [], "pincell_ce": [], "backward": [], "batch": {}}
+    out = {k: [] for k in parts}
     scheds = (("naive", "fused"), ("async", "fused"), ("async", "split"), ("stack", "fused"), ("stack", "split"))
-    for n in (10_000, 100_000, 1_000_000, 10_000_000):
+    for n in ((10_000, 100_000, 1_000_000, 10_000_000) if "box" in parts else ()):
         P = mcx.Problem(inputs.cfg1_box(n))
         for s, dc in scheds:
             t = _wall(P, 3, sched=s, decomp=dc)
             out["box"].append({"histories": n, "sched": s, "decomp": dc, "ms": 1e3 * t, "hist_per_s": n / t})
             print("sweep box", out["box"][-1], file=sys.stderr, flush=True)
         del P
-    for n in (100_000, 1_000_000, 10_000_000):
+    for n in ((100_000, 1_000_000, 10_000_000) if "lattice" in parts else ()):
         P = mcx.Problem(inputs.cfg2_lattice(n))
         reps = 3 if n < 10_000_000 else 2
         for s, dc in scheds:
@@ -94,7 +98,7 @@ def sweep() -> dict:
                                    "tuned_ms": 1e3 * tt, "tuned_hist_per_s": n / tt, "knobs": knobs})
             print("sweep lattice", out["lattice"][-1], file=sys.stderr, flush=True)
         del P
-    for nb in (100, 1000, 10000):
+    for nb in ((100, 1000, 10000) if "pincell_ce" in parts else ()):
         for lookup in ("binary", "hash"):
             P = mcx.Problem(inputs.cfg3_pincell(n_ebins=nb, n_histories=1_000_000))
             for s, dc in scheds:
@@ -103,11 +107,48 @@ def sweep() -> dict:
                                           "hist_per_s": 1e6 / t})
                 print("sweep pincell", out["pincell_ce"][-1], file=sys.stderr, flush=True)
             del P
-    d = inputs.cfg4_lattice_grad(1_000_000)
-    P = mcx.Problem(d)
-    w = np.random.default_rng(4).normal(size=inputs.n_bins(d))
+    # temporal tally resolution (paper Sec. 4): the continuous-energy pin cell
+    # with 100 energy bins times 1..128 time bins over [0, 5e-7 s), a window
+    # every history ends in (absorbed) at neutron speeds
+    for n in ((100_000, 1_000_000) if "pincell_time" in parts else ()):
+        for nt in (1, 2, 4, 8, 16, 32, 64, 128):
+            d = inputs.with_time_bins(inputs.cfg3_pincell(n_ebins=100, n_histories=n), nt, 5e-7,
+                                      speed_coef=NEUTRON_SPEED)
+            P = mcx.Problem(d)
+            for s, dc in scheds:
+                t = _wall(P, 2, sched=s, decomp=dc)
+                c = P.counters()
+                out["pincell_time"].append({"histories": n, "time_bins": nt, "sched": s, "decomp": dc,
+                                            "ms": 1e3 * t, "hist_per_s": n / t, "cutoffs": c["cutoffs"],
+                                            "pieces": c["pieces"]})
+                print("sweep pincell_time", out["pincell_time"][-1], file=sys.stderr, flush=True)
+            del P
+    # where the tally adds go (per-block LDS sums, 16 replicas, direct), per
+    # scheduler and tally size
+    if "tally_path" in parts:
+        cases = [("box, 2000 mesh bins", inputs.cfg1_box(1_000_000))]
+        for nt in (1, 8, 16, 32, 64):
+            cases.append((f"pin cell, 100 energy x {nt} time bins",
+                          inputs.with_time_bins(inputs.cfg3_pincell(n_ebins=100, n_histories=1_000_000), nt, 5e-7,
+                                                speed_coef=NEUTRON_SPEED)))
+        cases.append(("lattice, 364140 mesh bins", inputs.cfg2_lattice(1_000_000)))
+        for name, d in cases:
+            P = mcx.Problem(d)
+            nb = inputs.n_bins(d)
+            for s, dc in scheds:
+                for path in ("lds", "replicas", "direct"):
+                    if path == "lds" and nb > 4096:
+                        continue
+                    t = _wall(P, 2, sched=s, decomp=dc, tally_path=path)
+                    out["tally_path"].append({"case": name, "bins": nb, "sched": s, "decomp": dc, "path": path,
+                                              "ms": 1e3 * t, "hist_per_s": d["n_histories"] / t})
+                    print("sweep tally_path", out["tally_path"][-1], file=sys.stderr, flush=True)
+            del P
     import torch
-    for s, dc in (("naive", "fused"), ("async", "fused"), ("stack", "fused")):
+    d = inputs.cfg4_lattice_grad(1_000_000)
+    P = mcx.Problem(d) if "backward" in parts else None
+    w = np.random.default_rng(4).normal(size=inputs.n_bins(d))
+    for s, dc in ((("naive", "fused"), ("async", "fused"), ("stack", "fused")) if P else ()):
         tf = _wall(P, 3, sched=s, decomp=dc)
         tb = []
         for _ in range(3):
@@ -119,6 +160,9 @@ def sweep() -> dict:
         out["backward"].append({"sched": s, "decomp": dc, "fwd_ms": 1e3 * tf, "bwd_ms": 1e3 * float(np.median(tb)),
                                 "ratio": float(np.median(tb)) / tf})
         print("sweep backward", out["backward"][-1], file=sys.stderr, flush=True)
+    if "batch" not in parts:
+        return out
+    out["batch"] = {}
     probs = inputs.cfg5_batch()
     nb = sum(p["n_histories"] for p in probs)
     B = mcx.Problem(probs)
@@ -159,8 +203,10 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print one JSON object with the measurement sweep: "
                          "box histories 1e4..1e7, lattice histories 1e5..1e7, the continuous-energy pin cell over bins, lookups and "
-                         "event decompositions, backward/forward per scheduler and the batch as one launch "
-                         "vs one launch per problem")
+                         "event decompositions, the pin cell over 1..128 time bins, backward/forward per scheduler "
+                         "and the batch as one launch vs one launch per problem")
+    ap.add_argument("--sweep-parts", default=",".join(SWEEP_PARTS),
+                    help="comma-separated parts of the sweep to run (default: all)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="finish with one device-to-device copy of this many MiB (a kernel of known traffic "
                          "against which profiler byte counters are scaled)")
@@ -175,7 +221,11 @@ def main():
 
     torch.cuda.set_device(0)
     if args.sweep:
-        print(json.dumps(sweep()))
+        parts = tuple(p for p in args.sweep_parts.split(",") if p)
+        bad = [p for p in parts if p not in SWEEP_PARTS]
+        if bad:
+            ap.error(f"unknown sweep parts {bad}; known: {SWEEP_PARTS}")
+        print(json.dumps(sweep(parts)))
         return
     d = inputs.cfg2_lattice(N_HIST)
     P = mcx.Problem(d)

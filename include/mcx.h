@@ -185,8 +185,21 @@ typedef struct {
     int32_t stack_min_events; /* stack: events a popped particle runs before it
                                  is pushed again, at least (0 = default 1:
                                  remap after every event)                     */
-    int32_t reserved[3];
+    int32_t tally_path;       /* single-problem forward runs: where tally adds
+                                 go (mcx_tally_path; 0 = chosen by tally size
+                                 and scheduler).  Batches and backward passes
+                                 add into the tallies directly.               */
+    int32_t reserved[2];
 } mcx_run_opts;
+
+/* Tally paths (results are the same integers on every path):
+ *  MCX_TALLY_PATH_LDS       each block sums its adds in LDS and adds the
+ *                           sums once at its end (at most 4096 bins);
+ *  MCX_TALLY_PATH_REPLICAS  adds go to one of 16 copies of the tally,
+ *                           chosen by wavefront, summed after the launch
+ *                           (at most 2^24 bins);
+ *  MCX_TALLY_PATH_DIRECT    adds go to the tally itself. */
+enum { MCX_TALLY_PATH_AUTO = 0, MCX_TALLY_PATH_LDS = 1, MCX_TALLY_PATH_REPLICAS = 2, MCX_TALLY_PATH_DIRECT = 3 };
 
 /* one record per history, written by runs that pass opts.digest */
 typedef struct {

@@ -96,6 +96,17 @@ static mcx_status hip_fail(mcx_problem_t p, hipError_t e, const char *where)
         if (e_ != hipSuccess) return hip_fail(p, e_, #call); \
     } while (0)
 
+// Default tally paths, from measurements on MI355X (1e6 histories: box with
+// 2000 mesh bins, continuous-energy pin cell with 100 energy x 1..64 time
+// bins, lattice with 364140 mesh bins): LDS sums are fastest up to 4096 bins
+// except for the asynchronous scheduler, whose one-wavefront blocks each hold
+// a copy (fused: faster up to about 2048 bins, split, with its larger stash:
+// up to about 1024); replicas beat direct adds by 2-15x below 65536 bins and
+// tie at 364140.
+constexpr long long ASYNC_LDS_TALLY_BINS_FUSED = 2048;
+constexpr long long ASYNC_LDS_TALLY_BINS_SPLIT = 1024;
+constexpr long long AUTO_REPLICA_MAX_BINS = 1 << 16;
+
 static bool sorted_strict(const double *a, int64_t n)
 {
     for (int64_t i = 0; i + 1 < n; ++i)
@@ -608,6 +619,12 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
         o.stack_min_events < 0)
         return fail(h, MCX_E_INVALID_ARG, "negative tuning value");
     if (o.consolidate < 0 || o.consolidate > 2) return fail(h, MCX_E_INVALID_ARG, "bad consolidate");
+    if (o.tally_path < MCX_TALLY_PATH_AUTO || o.tally_path > MCX_TALLY_PATH_DIRECT)
+        return fail(h, MCX_E_INVALID_ARG, "bad tally_path");
+    if (o.tally_path == MCX_TALLY_PATH_LDS && h->hp[0].n_bins > LT_MAX_BINS)
+        return fail(h, MCX_E_INVALID_ARG, "tally_path LDS needs at most %d bins", LT_MAX_BINS);
+    if (o.tally_path == MCX_TALLY_PATH_REPLICAS && h->hp[0].n_bins > TREP_MAX_BINS)
+        return fail(h, MCX_E_INVALID_ARG, "tally_path REPLICAS needs at most %lld bins", TREP_MAX_BINS);
     return MCX_OK;
 }
 
@@ -619,6 +636,25 @@ __global__ void trep_reduce(unsigned long long *tally, const unsigned long long 
     unsigned long long v = 0;
     for (int r = 0; r < nrep; ++r) v += rep[(size_t)r * n + b];
     tally[b] += v;
+}
+
+// Where a run's tally adds go.  Single-problem forward runs: a small tally is
+// summed per block in LDS, a larger one spread over replicas (on MI355X every
+// device-scope atomic is carried out at the memory side, so the adds of all
+// wavefronts to a few hot words serialise there), a very large one, whose
+// adds are spread anyway, is added directly.  Batches and backward passes add
+// directly.
+static int tally_path(mcx_problem_t h, const mcx_run_opts &o, int mode)
+{
+    if (h->n != 1 || mode != MODE_FWD) return MCX_TALLY_PATH_DIRECT;
+    if (o.tally_path != MCX_TALLY_PATH_AUTO) return o.tally_path;
+    const long long nb = h->hp[0].n_bins;
+    long long lds_max = LT_MAX_BINS;
+    if (o.sched == MCX_SCHED_ASYNC)
+        lds_max = o.decomp == MCX_DECOMP_SPLIT ? ASYNC_LDS_TALLY_BINS_SPLIT : ASYNC_LDS_TALLY_BINS_FUSED;
+    if (nb <= lds_max) return MCX_TALLY_PATH_LDS;
+    if (nb <= AUTO_REPLICA_MAX_BINS) return MCX_TALLY_PATH_REPLICAS;
+    return MCX_TALLY_PATH_DIRECT;
 }
 
 // One pass over the run's histories with the given mode.
@@ -637,11 +673,8 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
         prefix[k + 1] = prefix[k] + count[k];
     }
     unsigned long long total = prefix[h->n];
-    // a single problem's energy-bin tally too large for LDS: adds go to
-    // replicas, summed into the tally after the launch (up to 2^24 bins;
-    // larger tallies are spread enough to take the adds directly)
-    const bool use_trep = h->n == 1 && mode == MODE_FWD && h->pd[0].tally_kind == MCX_TALLY_ENERGY &&
-                          h->hp[0].n_bins > LT_MAX_BINS && h->hp[0].n_bins <= (1 << 24);
+    const int path = tally_path(h, o, mode);
+    const bool use_trep = path == MCX_TALLY_PATH_REPLICAS;
     if (use_trep) {
         size_t words = (size_t)TREP * (size_t)h->hp[0].n_bins;
         if (h->trep_words < words) {
@@ -676,9 +709,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.time = h->pd[0].n_tbins > 0 ? 1 : 0;
     a.lacc_words = 0;
     if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
-    // a small tally (energy bins or mesh cells x groups) is summed per block
-    // in LDS, then added once per block
-    if (h->n == 1 && mode == MODE_FWD && h->hp[0].n_bins <= LT_MAX_BINS) a.lacc_words = (int)h->hp[0].n_bins;
+    if (path == MCX_TALLY_PATH_LDS) a.lacc_words = (int)h->hp[0].n_bins;
     a.tl_bytes = (h->n == 1 && h->pd[0].tl_bytes <= TL_MAX_BYTES) ? h->pd[0].tl_bytes : 0;
     a.stream = stream;
     a.num_cus = h->num_cus;

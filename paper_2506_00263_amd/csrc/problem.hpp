@@ -80,8 +80,9 @@ struct ProbDev {
 enum : int { TL_SIG_T = 0, TL_SIG_S, TL_CDF, TL_XPL, TL_YPL, TL_CXS, TL_CYS, TL_MX, TL_MY, TL_MZ, TL_SPEED, TL_CMAT };
 constexpr int TL_NDBL = TL_CMAT;      // tables of doubles in front of the int32 materials
 constexpr int TL_MAX_BYTES = 32768;   // larger tables stay in global memory
-constexpr int LT_MAX_BINS = 4096;     // energy-bin tallies up to this size are summed in LDS per block
-constexpr int TREP = 16;              // larger ones go to TREP replicas chosen by wavefront
+constexpr int LT_MAX_BINS = 4096;     // tallies up to this size can be summed in LDS per block
+constexpr int TREP = 16;              // or go to TREP replicas chosen by wavefront
+constexpr long long TREP_MAX_BINS = 1ll << 24;
 
 enum Counter : int {
     C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,

@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mcx.h")
 SCHED = {"naive": 0, "stack": 1, "async": 2}
 DECOMP = {"fused": 0, "split": 1}
 LOOKUP = {"binary": 0, "hash": 1}
+TALLY_PATH = {"auto": 0, "lds": 1, "replicas": 2, "direct": 3}
 STATUS = {0: "MCX_OK", 1: "MCX_E_INVALID_ARG", 2: "MCX_E_OOM", 3: "MCX_E_DEVICE", 4: "MCX_E_CAPACITY",
           5: "MCX_E_OVERFLOW", 6: "MCX_E_STATE"}
 HOST, DEVICE = 0, 1
@@ -58,7 +59,8 @@ class RunOpts(C.Structure):
         ("stack_threshold", C.c_int64), ("stash_links", C.c_int32), ("arena_links", C.c_int32),
         ("waves_per_cu", C.c_int32), ("block_size", C.c_int32), ("hip_stream", C.c_void_p), ("digest", C.c_void_p),
         ("time_kernels", C.c_int32), ("force_spill", C.c_int32), ("consolidate", C.c_int32),
-        ("stack_tail_events", C.c_int32), ("stack_min_events", C.c_int32), ("reserved", C.c_int32 * 3),
+        ("stack_tail_events", C.c_int32), ("stack_min_events", C.c_int32), ("tally_path", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 
@@ -197,7 +199,7 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
 def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, first=0, n=0, stack_capacity=0,
              stack_threshold=0, stash_links=0, arena_links=0, waves_per_cu=0, block_size=0, stream=None,
              digest=None, time_kernels=False, force_spill=0, consolidate=0, stack_tail_events=0,
-             stack_min_events=0) -> RunOpts:
+             stack_min_events=0, tally_path="auto") -> RunOpts:
     o = RunOpts()
     o.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     o.decomp = DECOMP[decomp] if isinstance(decomp, str) else int(decomp)
@@ -217,6 +219,7 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
     o.force_spill = int(force_spill)
     o.stack_tail_events = int(stack_tail_events)
     o.stack_min_events = int(stack_min_events)
+    o.tally_path = TALLY_PATH[tally_path] if isinstance(tally_path, str) else int(tally_path)
     # async stash donation: None/"default" = library default, True/"on", False/"off"
     if isinstance(consolidate, bool):
         o.consolidate = 1 if consolidate else 2

@@ -302,3 +302,28 @@ def test_full_size_lattice_sampled(mcx, oracle):
     for h in sample:
         ref = oracle.run(d, int(h), int(h) + 1, digest=True, threads=1)
         assert ref["digest"][0] == g[h], h
+
+
+@pytest.mark.parametrize("sched,decomp", SCHEDS)
+def test_tally_paths(mcx, oracle, cfg1, sched, decomp):
+    # LDS sums, replicas and direct adds give the same integers (mesh and
+    # energy tallies, with and without time bins)
+    d, ref = cfg1
+    P = mcx.Problem(d)
+    for path in ("lds", "replicas", "direct"):
+        P.run(sched=sched, decomp=decomp, tally_path=path)
+        assert np.array_equal(P.tallies(), ref["tally"]), path
+        _check_counts(P.counters(), ref["counts"])
+    dc = inputs.with_time_bins(inputs.pincell_ce(n_ebins=500, n_histories=400), 8, 3e-7, speed_coef=1.383e6)
+    refc = oracle.run(dc)
+    Q = mcx.Problem(dc)
+    for path in ("auto", "lds", "replicas", "direct"):
+        Q.run(sched=sched, decomp=decomp, tally_path=path)
+        assert np.array_equal(Q.tallies(), refc["tally"]), path
+    # more bins than the LDS sums hold: rejected, and no tallies until the next good run
+    R = mcx.Problem(inputs.with_time_bins(dc, 16, 3e-7, speed_coef=1.383e6))
+    with pytest.raises(mcx.McxError) as e:
+        R.run(sched=sched, decomp=decomp, tally_path="lds")
+    assert e.value.status == 1
+    with pytest.raises(mcx.McxError):
+        R.run(sched=sched, decomp=decomp, tally_path=7)
