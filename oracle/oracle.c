@@ -16,6 +16,7 @@
  */
 #include "oracle.h"
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------ RNG */
@@ -510,12 +511,22 @@ static void orc_isotropic(double xi_mu, double xi_phi, double dir[3])
     dir[2] = mu;
 }
 
+/* State of one k-eigenvalue cycle (NULL in fixed-source runs). */
+typedef struct {
+    uint32_t stream;          /* random-number stream: the cycle number      */
+    const double *bank;       /* source positions, 3 per history (NULL: the
+                                 problem's own source)                       */
+    uint32_t *fn;             /* out: neutrons banked by each history        */
+    double *fpos;             /* out: its fission site, 3 per history        */
+} orc_cycle;
+
 static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad *gr,
-                        orc_digest *dig)
+                        orc_digest *dig, const orc_cycle *cy)
 {
     orc_counts *cnt = acc->cnt;
     uint64_t seed = p->seed;
     uint32_t pid = p->problem_id;
+    uint32_t stream = cy ? cy->stream : 0;
     double pos[3], dir[3];
     int32_t cell[3];
     int32_t g = p->src_group;
@@ -524,12 +535,18 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
     if (acc->mode == 2) Gh = gr->G[h - gr->h0];
 
     /* source event: flight counter 0, slots 0-2 position, 3-4 direction */
-    double xi0 = orc_uniform(seed, pid, h, 0, 0, 0);
-    double xi1 = orc_uniform(seed, pid, h, 0, 1, 0);
-    double xi2 = orc_uniform(seed, pid, h, 0, 2, 0);
-    double xi3 = orc_uniform(seed, pid, h, 0, 3, 0);
-    double xi4 = orc_uniform(seed, pid, h, 0, 4, 0);
-    if (p->src_kind == 0) {
+    double xi0 = orc_uniform(seed, pid, h, 0, 0, stream);
+    double xi1 = orc_uniform(seed, pid, h, 0, 1, stream);
+    double xi2 = orc_uniform(seed, pid, h, 0, 2, stream);
+    double xi3 = orc_uniform(seed, pid, h, 0, 3, stream);
+    double xi4 = orc_uniform(seed, pid, h, 0, 4, stream);
+    if (cy && cy->bank) {
+        /* a banked fission neutron: its site, an isotropic direction, and a
+           group from the fission spectrum of the material found there */
+        pos[0] = cy->bank[3 * (uint64_t)h];
+        pos[1] = cy->bank[3 * (uint64_t)h + 1];
+        pos[2] = cy->bank[3 * (uint64_t)h + 2];
+    } else if (p->src_kind == 0) {
         pos[0] = p->src_pos[0]; pos[1] = p->src_pos[1]; pos[2] = p->src_pos[2];
     } else if (p->src_kind == 1) {
         pos[0] = p->src_lo[0] + (xi0 * (p->src_hi[0] - p->src_lo[0]));
@@ -543,12 +560,20 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
         pos[1] = p->src_pos[1] + (r * s);
         pos[2] = p->src_pos[2];
     }
-    if (p->src_isotropic) {
+    if (p->src_isotropic || (cy && cy->bank)) {
         orc_isotropic(xi3, xi4, dir);
     } else {
         dir[0] = p->src_dir[0]; dir[1] = p->src_dir[1]; dir[2] = p->src_dir[2];
     }
     orc_locate(p, pos, dir, cell);
+    if (cy && cy->bank) {
+        const double *row = p->chi + (int64_t)orc_material(p, cell) * p->n_grp;
+        g = p->n_grp - 1;
+        for (int32_t k = 0; k < p->n_grp; ++k) {
+            if (xi0 < row[k]) { g = k; break; }
+        }
+    }
+    if (cy && cy->fn) cy->fn[h] = 0;
     cnt->sourced += 1;
 
     uint32_t flights = 0, collisions = 0, fate = ORC_FATE_LEAK;
@@ -579,7 +604,7 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
         }
         /* flight: distance to collision, nearest surface, the shorter wins
            (a collision only if strictly shorter) */
-        double dcol = orc_nlog(orc_uniform(seed, pid, h, st32, 0, 0)) / sigma_t;
+        double dcol = orc_nlog(orc_uniform(seed, pid, h, st32, 0, stream)) / sigma_t;
         int32_t surf;
         double dsurf = orc_distance(p, pos, dir, cell, &surf);
         int collide = dcol < dsurf;
@@ -626,16 +651,28 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
         if (collide) {
             collisions += 1;
             cnt->collisions += 1;
-            double c1 = orc_uniform(seed, pid, h, st32, 1, 0);
-            double c2 = orc_uniform(seed, pid, h, st32, 2, 0);
-            double c3 = orc_uniform(seed, pid, h, st32, 3, 0);
-            double c4 = orc_uniform(seed, pid, h, st32, 4, 0);
+            double c1 = orc_uniform(seed, pid, h, st32, 1, stream);
+            double c2 = orc_uniform(seed, pid, h, st32, 2, stream);
+            double c3 = orc_uniform(seed, pid, h, st32, 3, stream);
+            double c4 = orc_uniform(seed, pid, h, st32, 4, stream);
             if (p->energy_mode == 0) {
                 double ss = p->sigma_s[m * p->n_grp + g];
                 if (!((c1 * sigma_t) < ss)) {
                     fate = ORC_FATE_ABSORB;
                     cnt->absorbs += 1;
                     if (acc->mode == 2) gr->SA[m * p->n_grp + g] += orc_qs(Gh, gr->scale);
+                    /* k-eigenvalue cycle: the absorption is a fission with
+                       probability Sigma_f / Sigma_a and banks floor(nu + xi)
+                       neutrons at the collision site */
+                    if (cy && cy->fn && ((c2 * (sigma_t - ss)) < p->sigma_f[m * p->n_grp + g])) {
+                        uint32_t n = (uint32_t)(p->nu[m * p->n_grp + g] + c3);
+                        cy->fn[h] = n;
+                        cy->fpos[3 * (uint64_t)h] = pos[0];
+                        cy->fpos[3 * (uint64_t)h + 1] = pos[1];
+                        cy->fpos[3 * (uint64_t)h + 2] = pos[2];
+                        cnt->fissions += 1;
+                        cnt->sites += n;
+                    }
                     break;
                 }
                 cnt->scatters += 1;
@@ -734,7 +771,7 @@ int orc_run(const orc_problem *p, uint64_t h0, uint64_t h1, int64_t *tally,
     acc.tally = tally;
     acc.cnt = &local;
     for (uint64_t h = h0; h < h1; ++h)
-        orc_history(p, (uint32_t)h, &acc, NULL, digest ? &digest[h - h0] : NULL);
+        orc_history(p, (uint32_t)h, &acc, NULL, digest ? &digest[h - h0] : NULL, NULL);
     local.qsum = acc.qsum_total;
     local.overflow = (uint64_t)acc.overflow;
     if (counts) *counts = local;
@@ -754,7 +791,7 @@ int orc_replay_a(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w
     uint64_t u = 0;
     int bad = 0;
     for (uint64_t h = h0; h < h1; ++h) {
-        orc_history(p, (uint32_t)h, &acc, NULL, NULL);
+        orc_history(p, (uint32_t)h, &acc, NULL, NULL, NULL);
         G[h - h0] = acc.G;
         double bound = ceil(fabs(acc.G) * (acc.L + (double)acc.nfl));
         if (!(bound < 0x1p63)) { bad = 1; continue; }
@@ -780,8 +817,102 @@ int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *G
     gr.h0 = h0;
     gr.scale = ldexp(1.0, s);
     gr.SL = SL; gr.SA = SA; gr.SS = SS;
-    for (uint64_t h = h0; h < h1; ++h) orc_history(p, (uint32_t)h, &acc, &gr, NULL);
+    for (uint64_t h = h0; h < h1; ++h) orc_history(p, (uint32_t)h, &acc, &gr, NULL, NULL);
     return 0;
+}
+
+/* ------------------------------------------------------------ k-eigenvalue */
+
+int orc_eigen(const orc_problem *p, uint64_t N, int32_t n_cycles, int32_t n_inactive, int64_t *tally,
+              double *k_cycle, uint64_t *n_source, orc_counts *counts, double *bank, uint64_t bank_cap,
+              uint64_t *bank_n)
+{
+    int64_t nbins = (p->tally_kind == 0)
+                        ? (int64_t)p->mesh_n[0] * p->mesh_n[1] * p->mesh_n[2] * (p->energy_mode == 0 ? p->n_grp : 1)
+                        : (int64_t)p->n_ebins;
+    if (p->n_tbins > 0) nbins *= p->n_tbins;
+    int64_t *scratch = calloc((size_t)nbins, sizeof(int64_t));   /* inactive cycles score here */
+    orc_counts total;
+    memset(&total, 0, sizeof total);
+    double *src = NULL;          /* source of the current cycle (NULL: cycle 0) */
+    uint64_t Nc = N;
+    int status = 0;
+    for (int32_t c = 0; c < n_cycles && status == 0; ++c) {
+        uint32_t *fn = malloc((size_t)(Nc ? Nc : 1) * sizeof(uint32_t));
+        double *fpos = malloc((size_t)(Nc ? Nc : 1) * 3 * sizeof(double));
+        orc_cycle cy = { (uint32_t)c, src, fn, fpos };
+        orc_counts local;
+        memset(&local, 0, sizeof local);
+        orc_acc acc;
+        memset(&acc, 0, sizeof acc);
+        acc.mode = 0;
+        acc.tally = (c >= n_inactive) ? tally : scratch;
+        acc.cnt = &local;
+        for (uint64_t h = 0; h < Nc; ++h) orc_history(p, (uint32_t)h, &acc, NULL, NULL, &cy);
+        /* totals over cycles; the overflow rule applies to the sum over all of them */
+        uint64_t q_before = total.qsum;
+        total.sourced += local.sourced; total.flights += local.flights;
+        total.collisions += local.collisions; total.scatters += local.scatters;
+        total.absorbs += local.absorbs; total.crossings += local.crossings; total.leaks += local.leaks;
+        total.reflections += local.reflections; total.cutoffs += local.cutoffs; total.killed += local.killed;
+        total.pieces += local.pieces; total.fissions += local.fissions; total.sites += local.sites;
+        total.qsum = q_before + acc.qsum_total;
+        if (acc.overflow || total.qsum < q_before || total.qsum >= 0x8000000000000000ull) total.overflow = 1;
+        /* the bank: each history's neutrons in history order */
+        uint64_t M = 0;
+        for (uint64_t h = 0; h < Nc; ++h) M += fn[h];
+        n_source[c] = Nc;
+        k_cycle[c] = (double)M / (double)Nc;
+        if (M == 0) {
+            status = 2;
+        } else {
+            double *sites = malloc((size_t)M * 3 * sizeof(double));
+            uint64_t s = 0;
+            for (uint64_t h = 0; h < Nc; ++h)
+                for (uint32_t j = 0; j < fn[h]; ++j, ++s) {
+                    sites[3 * s] = fpos[3 * h];
+                    sites[3 * s + 1] = fpos[3 * h + 1];
+                    sites[3 * s + 2] = fpos[3 * h + 2];
+                }
+            /* splitting-roulette back to about N particles */
+            double r = (double)N / (double)M;
+            double fl = floor(r);
+            double fr = r - fl;
+            uint64_t Nn = 0;
+            for (uint64_t j = 0; j < M; ++j) {
+                double u = orc_uniform(p->seed, p->problem_id, (uint32_t)j, 0xFFFFFFFFu, 0, (uint32_t)c);
+                Nn += (uint64_t)fl + ((u < fr) ? 1u : 0u);
+            }
+            double *next = malloc((size_t)(Nn ? Nn : 1) * 3 * sizeof(double));
+            uint64_t o = 0;
+            for (uint64_t j = 0; j < M; ++j) {
+                double u = orc_uniform(p->seed, p->problem_id, (uint32_t)j, 0xFFFFFFFFu, 0, (uint32_t)c);
+                uint64_t copies = (uint64_t)fl + ((u < fr) ? 1u : 0u);
+                for (uint64_t i = 0; i < copies; ++i, ++o) {
+                    next[3 * o] = sites[3 * j];
+                    next[3 * o + 1] = sites[3 * j + 1];
+                    next[3 * o + 2] = sites[3 * j + 2];
+                }
+            }
+            free(sites);
+            free(src);
+            src = next;
+            Nc = Nn;
+            if (Nc == 0) status = 2;
+        }
+        free(fn);
+        free(fpos);
+    }
+    if (bank_n) *bank_n = Nc;
+    if (bank && src) {
+        if (Nc > bank_cap) status = status ? status : 3;
+        else memcpy(bank, src, (size_t)Nc * 3 * sizeof(double));
+    }
+    free(src);
+    free(scratch);
+    if (counts) *counts = total;
+    if (status == 0 && total.overflow) status = 1;
+    return status;
 }
 
 /* ------------------------------------------------------------- test hooks */

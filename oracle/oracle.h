@@ -67,6 +67,12 @@ typedef struct {
     double t_max;
     const double *speed;       /* [G], multigroup                            */
     double speed_coef;         /* continuous energy                          */
+    /* fission (multigroup k-eigenvalue runs; NULL sigma_f: none).  An
+       absorption in (m, g) is a fission with probability
+       sigma_f / (sigma_t - sigma_s); it emits floor(nu + xi) neutrons at the
+       collision site.  chi [M*G]: cumulative fission spectrum per material.
+       Fixed-source runs ignore fission (it is one kind of absorption). */
+    const double *sigma_f, *nu, *chi;
 } orc_problem;
 
 /* what a history ended with */
@@ -84,6 +90,7 @@ typedef struct {              /* totals over a run (scheduler invariant)   */
     uint64_t sourced, flights, collisions, scatters, absorbs, crossings;
     uint64_t leaks, reflections, cutoffs, killed, pieces, qsum;
     uint64_t overflow;        /* 1 if the total of all q reached 2^63       */
+    uint64_t fissions, sites; /* k-eigenvalue runs: fissions, neutrons banked */
 } orc_counts;
 
 /* primitives, exposed for tests */
@@ -121,5 +128,23 @@ int orc_replay_a(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w
    SS per scatter, with q(x) = rint(x * 2^s) */
 int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *G, int32_t s,
                  int64_t *SL, int64_t *SA, int64_t *SS);
+
+/* k-eigenvalue power iteration (multigroup, fission data required).
+   Cycle c runs N_c histories with random-number stream c: cycle 0 from the
+   problem's source (N_0 = N), later cycles from the source bank.  Every
+   fission banks its neutrons at the collision site, in history order.
+   Splitting-roulette brings the M_c banked neutrons back to about N: with
+   r = N / M_c each site is copied floor(r) times plus once more when
+   u_j < r - floor(r), u_j = orc_uniform(seed, id, j, 0xFFFFFFFF, 0, c); the
+   copies in site order are the next source.  A banked neutron starts with
+   an isotropic direction (slots 3, 4) and a group drawn from chi of the
+   material at its site (slot 0).  k_c = M_c / N_c; n_source[c] = N_c.
+   Cycles c >= n_inactive add into tally; counts are totals over all cycles.
+   bank (optional, 3 doubles per particle, capacity bank_cap) receives the
+   source of the cycle after the last, *bank_n its size.
+   Returns 0, 1 (overflow), 2 (no neutron banked in a cycle), 3 (bank full). */
+int orc_eigen(const orc_problem *p, uint64_t N, int32_t n_cycles, int32_t n_inactive, int64_t *tally,
+              double *k_cycle, uint64_t *n_source, orc_counts *counts, double *bank, uint64_t bank_cap,
+              uint64_t *bank_n);
 
 #endif

@@ -48,7 +48,7 @@ class OrcProblem(C.Structure):
         ("mesh_y", C.c_void_p), ("mesh_z", C.c_void_p), ("n_ebins", C.c_int32), ("e_edges", C.c_void_p),
         ("tally_scale_log2", C.c_int32), ("problem_id", C.c_uint32), ("seed", C.c_uint64),
         ("max_steps", C.c_int64), ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p),
-        ("speed_coef", C.c_double),
+        ("speed_coef", C.c_double), ("sigma_f", C.c_void_p), ("nu", C.c_void_p), ("chi", C.c_void_p),
     ]
 
 
@@ -60,7 +60,7 @@ class OrcDigest(C.Structure):
 DIGEST_DTYPE = np.dtype([("qsum", "<i8"), ("flights", "<u4"), ("collisions", "<u4"),
                          ("fate", "<u4"), ("pad", "<u4")])
 COUNT_NAMES = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks",
-               "reflections", "cutoffs", "killed", "pieces", "qsum", "overflow"]
+               "reflections", "cutoffs", "killed", "pieces", "qsum", "overflow", "fissions", "sites"]
 
 
 class OrcCounts(C.Structure):
@@ -108,6 +108,8 @@ def lib():
                                        P(C.c_uint64)]
             L.orc_replay_b.argtypes = [P(OrcProblem), C.c_uint64, C.c_uint64, C.c_void_p, C.c_int32,
                                        C.c_void_p, C.c_void_p, C.c_void_p]
+            L.orc_eigen.argtypes = [P(OrcProblem), C.c_uint64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, P(OrcCounts), C.c_void_p, C.c_uint64, P(C.c_uint64)]
             _lib = L
     return _lib
 
@@ -181,6 +183,10 @@ class Problem:
         if s.n_tbins > 0 and d["energy_mode"] == 0:
             s.speed = arr("speed", np.float64)
         s.speed_coef = float(d.get("speed_coef", 0.0))
+        if d.get("sigma_f") is not None:
+            s.sigma_f = arr("sigma_f", np.float64)
+            s.nu = arr("nu", np.float64)
+            s.chi = arr("chi", np.float64)
         self.s = s
         self._keep = keep
 
@@ -315,6 +321,33 @@ def backward(d: dict, w: np.ndarray, threads: int | None = None):
     SL, SA, SS = replay_b(d, G, s, threads=threads)
     gt, gs = grads_from_sums(d, SL, SA, SS, s, d["n_histories"])
     return dict(grad_sigma_t=gt, grad_sigma_s=gs, G=G, U=U, s=s, SL=SL, SA=SA, SS=SS)
+
+
+def eigen(d: dict, n_particles: int, n_cycles: int, n_inactive: int, bank_cap: int | None = None):
+    """k-eigenvalue power iteration (multigroup problem with fission data):
+    the int64 tally summed over the active cycles, k and the source size of
+    every cycle, counters over all cycles and the source bank that would
+    start the next cycle (positions, [n, 3])."""
+    P = Problem(d)
+    if d.get("sigma_f") is None:
+        raise ValueError("k-eigenvalue runs need fission data")
+    L = lib()
+    tally = np.zeros(P.n_bins, dtype=np.int64)
+    k = np.zeros(n_cycles, dtype=np.float64)
+    ns = np.zeros(n_cycles, dtype=np.uint64)
+    cap = 2 * n_particles + 1024 if bank_cap is None else bank_cap
+    bank = np.zeros((cap, 3), dtype=np.float64)
+    bn = C.c_uint64(0)
+    cnt = OrcCounts()
+    rc = L.orc_eigen(C.byref(P.s), n_particles, n_cycles, n_inactive, _ptr(tally), _ptr(k), _ptr(ns),
+                     C.byref(cnt), _ptr(bank), cap, C.byref(bn))
+    if rc == 2:
+        raise RuntimeError("no neutron was banked in a cycle")
+    if rc == 3:
+        raise RuntimeError("source bank capacity exceeded")
+    counts = {n: int(getattr(cnt, n)) for n in COUNT_NAMES}
+    return dict(tally=tally, k=k, n_source=ns.astype(np.int64), counts=counts, bank=bank[:bn.value].copy(),
+                status=rc)
 
 
 def _parallel(fn, n):

@@ -330,6 +330,45 @@ def with_time_bins(d: dict, n_tbins: int, t_max: float, speed=None, speed_coef: 
     return d
 
 
+def with_fission(d: dict, fissile=None, sigma_f=None, nu=None, chi=None,
+                 data_seed: int = DATA_SEED_BASE + 6) -> dict:
+    """A copy of multigroup problem d with fission data for k-eigenvalue runs.
+
+    Defaults (a synthetic stand-in for fuel data): the `fissile` materials
+    (default: every material but the moderator of a lattice, every material of
+    a box) get Sigma_f = f Sigma_a with f ~ U[0.3, 0.7] per (material, group)
+    and nu ~ U[2.3, 2.7]; the others none.  chi (the cumulative fission
+    spectrum, per material) puts the neutrons into the fastest groups with
+    weights proportional to 0.6^g over the first min(3, G) groups."""
+    d = dict(d)
+    assert d["energy_mode"] == ENERGY_MG
+    n_mat, n_grp = int(d["n_mat"]), int(d["n_grp"])
+    rng = np.random.default_rng(data_seed)
+    st = np.asarray(d["sigma_t"], np.float64).reshape(n_mat, n_grp)
+    ss = np.asarray(d["sigma_s"], np.float64).reshape(n_mat, n_grp)
+    if fissile is None:
+        fissile = [m for m in range(n_mat) if not (d["geometry"] == GEOM_LATTICE and m == d["mod_mat"])]
+    if sigma_f is None:
+        sigma_f = np.zeros((n_mat, n_grp))
+        for m in fissile:
+            sigma_f[m] = rng.uniform(0.3, 0.7, n_grp) * (st[m] - ss[m])
+    if nu is None:
+        nu = np.zeros((n_mat, n_grp))
+        for m in fissile:
+            nu[m] = rng.uniform(2.3, 2.7, n_grp)
+    if chi is None:
+        w = np.zeros(n_grp)
+        k = min(3, n_grp)
+        w[:k] = 0.6 ** np.arange(k)
+        c = np.cumsum(w / w.sum())
+        c[-1] = 1.0
+        chi = np.tile(c, (n_mat, 1))
+    d["sigma_f"] = _f64(np.asarray(sigma_f, np.float64).reshape(n_mat * n_grp))
+    d["nu"] = _f64(np.asarray(nu, np.float64).reshape(n_mat * n_grp))
+    d["chi"] = _f64(np.asarray(chi, np.float64).reshape(n_mat * n_grp))
+    return d
+
+
 def config(k: int, **kw):
     """Workload k in 1..5 (see module docstring)."""
     return {1: cfg1_box, 2: cfg2_lattice, 3: cfg3_pincell, 4: cfg4_lattice_grad, 5: cfg5_batch}[k](**kw)
