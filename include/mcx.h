@@ -151,6 +151,14 @@ typedef struct {
     double t_max;
     const double *speed;
     double speed_coef;
+    /* Fission, for k-eigenvalue runs (mcx_run_eigen; multigroup).  sigma_f,
+     * nu [n_mat*n_grp]: an absorption in (m, g) is a fission with probability
+     * sigma_f / (sigma_t - sigma_s) and banks floor(nu + xi) neutrons at the
+     * collision site (0 <= sigma_f <= sigma_t - sigma_s, 0 <= nu < 15);
+     * chi [n_mat*n_grp]: cumulative fission spectrum of each material (rows
+     * non-decreasing, ending at 1.0).  NULL sigma_f: no fission data.  Other
+     * runs treat a fission as an absorption. */
+    const double *sigma_f, *nu, *chi;
 } mcx_problem_desc;
 
 /* Options of one run.  Zero-initialise and set what you need; zero means the
@@ -227,7 +235,31 @@ typedef struct {
     int32_t block_threads;    /* threads per block of the main launch           */
     int32_t lds_bytes;        /* dynamic LDS per block of the main launch       */
     int32_t pad;
+    uint64_t fissions;        /* k-eigenvalue runs: fissions (all cycles)       */
+    uint64_t sites;           /*   and neutrons banked                          */
 } mcx_counters_t;
+
+/* k-eigenvalue power iteration (the multigroup workload of Sec. 4 of the
+ * paper).  Cycle c runs N_c histories on random-number stream c (the fourth
+ * Philox counter word): cycle 0 from the problem's source (N_0 = N, the same
+ * histories as mcx_run), later cycles from the source bank.  Every fission
+ * banks its neutrons at its site; the bank is ordered by history.
+ * Splitting-roulette brings the M_c banked neutrons back to about N: with
+ * r = N / M_c each site is copied floor(r) times, plus once when
+ * u_j < r - floor(r), u_j the first deviate of counter (j, 0xFFFFFFFF, 0, c);
+ * the copies in site order are the next cycle's source.  A banked neutron
+ * starts isotropic with a group drawn from chi of the material at its site
+ * (slot 0).  Tallies are summed over cycles c >= n_inactive; counters over all
+ * cycles.  Single-problem multigroup handles with fission data and no time
+ * bins; the source bank holds at most 2 N + 1024 particles (MCX_E_CAPACITY
+ * beyond); a cycle that banks nothing fails with MCX_E_STATE. */
+typedef struct {
+    uint64_t n_particles;     /* N: source particles per cycle (1 .. 2^30)       */
+    int32_t n_cycles;         /* cycles (>= 1)                                   */
+    int32_t n_inactive;       /* first cycles not tallied (0 .. n_cycles)        */
+    double *k_cycle;          /* out, host [n_cycles]: M_c / N_c                 */
+    uint64_t *n_source;       /* out, host [n_cycles]: N_c                       */
+} mcx_eigen_opts;
 
 /* Create a handle for n_problems independent problems (a batch runs all of
  * them in one launch).  All problems of a batch must share geometry kind,
@@ -262,6 +294,12 @@ mcx_status mcx_tallies(mcx_problem_t p, int32_t problem, int64_t *out, int64_t n
  * and digest fields are ignored). */
 mcx_status mcx_backward(mcx_problem_t p, int32_t problem, const double *dL_dT, double *grad_sigma_t,
                         double *grad_sigma_s, int32_t where, const mcx_run_opts *opts);
+
+/* Run a k-eigenvalue calculation (see mcx_eigen_opts) through the scheduler
+ * and tuning of opts (its range, accumulate and digest fields are ignored).
+ * On success the tallies hold the active cycles' sum and k_cycle, n_source
+ * are filled; mcx_backward does not apply to it. */
+mcx_status mcx_run_eigen(mcx_problem_t p, const mcx_run_opts *opts, const mcx_eigen_opts *eig);
 
 mcx_status mcx_counters(mcx_problem_t p, mcx_counters_t *out);
 

@@ -25,6 +25,8 @@ struct HostProblem {
     mcx_problem_desc d;
     std::vector<double> xpl, ypl, cxs, cys, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, mx, my, mz, eedges;
     std::vector<double> speed;            // group speeds (time bins, multigroup)
+    std::vector<double> sigf, nu, chi;    // fission (k-eigenvalue runs)
+    bool fission = false;
     std::vector<int32_t> cmat, hash_lo, hash_hi;
     double hash_ln_lo = 0.0, hash_inv = 0.0;
     int32_t hash_bins = 0;
@@ -63,6 +65,20 @@ struct mcx_problem_s {
     RunCtl *h_ctl = nullptr;              // pinned
     Workspace ws;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;   // reused by LaunchTimer
+    // k-eigenvalue buffers (grown on demand): source banks (ping-pong), per
+    // history banked count and fission site, the cycle's sites, scan tiles,
+    // a tally for the inactive cycles, device and pinned host totals
+    double *d_sbank[2] = {nullptr, nullptr};
+    uint32_t *d_fn = nullptr;
+    double *d_fpos = nullptr;
+    size_t eig_cap = 0;                   // particles per source bank
+    double *d_sites = nullptr;
+    size_t sites_cap = 0;
+    uint64_t *d_tsum = nullptr;
+    size_t tsum_cap = 0;
+    unsigned long long *d_scratch = nullptr;
+    uint64_t *d_tot = nullptr;
+    uint64_t *h_tot = nullptr;            // pinned
     // state
     bool tallies_valid = false;
     bool have_forward = false;
@@ -301,6 +317,29 @@ static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int
     } else {
         return fail(h, MCX_E_INVALID_ARG, "problem %d: bad tally_kind", k);
     }
+    hp.sigf = hp.nu = hp.chi = {0.0};
+    if (d.sigma_f) {
+        if (d.energy_mode != MCX_MG)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: fission data needs a multigroup problem", k);
+        if (!d.nu || !d.chi) return fail(h, MCX_E_INVALID_ARG, "problem %d: fission needs nu and chi", k);
+        hp.sigf = copy_of(d.sigma_f, MG);
+        hp.nu = copy_of(d.nu, MG);
+        hp.chi = copy_of(d.chi, MG);
+        for (int64_t i = 0; i < MG; ++i) {
+            if (!(hp.sigf[i] >= 0.0 && hp.sigf[i] <= hp.sig_t[i] - hp.sig_s[i]))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: need 0 <= sigma_f <= sigma_t - sigma_s", k);
+            if (!(hp.nu[i] >= 0.0 && hp.nu[i] < 15.0))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: need 0 <= nu < 15", k);
+        }
+        for (int m = 0; m < d.n_mat; ++m) {
+            const double *row = hp.chi.data() + (int64_t)m * d.n_grp;
+            for (int g = 0; g < d.n_grp; ++g)
+                if (!(row[g] >= 0.0 && row[g] <= 1.0 && (g == 0 || row[g - 1] <= row[g])))
+                    return fail(h, MCX_E_INVALID_ARG, "problem %d: chi rows must be non-decreasing in [0, 1]", k);
+            if (row[d.n_grp - 1] != 1.0) return fail(h, MCX_E_INVALID_ARG, "problem %d: chi rows must end at 1.0", k);
+        }
+        hp.fission = true;
+    }
     hp.nbase = hp.n_bins;
     hp.speed = {1.0};
     if (d.n_tbins < 0 || d.n_tbins > (1 << 20))
@@ -346,17 +385,18 @@ static mcx_status upload(mcx_problem_t h)
     BlobBuilder bb;
     struct Offs {
         size_t xpl, ypl, cxs, cys, cmat, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, hlo, hhi, mx, my, mz, ee;
-        size_t speed;
+        size_t speed, sigf, nu, chi;
     };
     std::vector<Offs> off(h->n);
     std::vector<size_t> tl_base(h->n), tl_bytes(h->n);
-    std::vector<std::array<int32_t, 12>> tl_off(h->n);
+    std::vector<std::array<int32_t, 15>> tl_off(h->n);
     for (int k = 0; k < h->n; ++k) {
         HostProblem &p = h->hp[k];
         Offs &o = off[k];
         // the small per-event tables, packed: doubles, then the int32 materials
-        const std::vector<double> *dt[TL_NDBL] = {&p.sig_t, &p.sig_s, &p.cdf, &p.xpl, &p.ypl, &p.cxs,
-                                                  &p.cys,   &p.mx,    &p.my,  &p.mz,  &p.speed};
+        const std::vector<double> *dt[TL_NDBL] = {&p.sig_t, &p.sig_s, &p.cdf,   &p.xpl, &p.ypl,
+                                                  &p.cxs,   &p.cys,   &p.mx,    &p.my,  &p.mz,
+                                                  &p.speed, &p.sigf,  &p.nu,    &p.chi};
         std::vector<double> packed;
         for (int t = 0; t < TL_NDBL; ++t) {
             tl_off[k][t] = (int32_t)packed.size();
@@ -376,6 +416,9 @@ static mcx_status upload(mcx_problem_t h)
         o.cys = b + 8 * (size_t)tl_off[k][TL_CYS]; o.mx = b + 8 * (size_t)tl_off[k][TL_MX];
         o.my = b + 8 * (size_t)tl_off[k][TL_MY]; o.mz = b + 8 * (size_t)tl_off[k][TL_MZ];
         o.speed = b + 8 * (size_t)tl_off[k][TL_SPEED];
+        o.sigf = b + 8 * (size_t)tl_off[k][TL_SIGF];
+        o.nu = b + 8 * (size_t)tl_off[k][TL_NU];
+        o.chi = b + 8 * (size_t)tl_off[k][TL_CHI];
         o.cmat = b + 4 * (size_t)tl_off[k][TL_CMAT];
         o.egrid = bb.add(p.egrid); o.siga = bb.add(p.siga); o.sigs = bb.add(p.sigs); o.awr = bb.add(p.awr);
         o.dens = bb.add(p.dens); o.hlo = bb.add(p.hash_lo); o.hhi = bb.add(p.hash_hi);
@@ -495,7 +538,10 @@ static mcx_status upload(mcx_problem_t h)
         P.SS = ga + 1 + 2 * mg;
         P.tl_src = (const double *)(base + tl_base[k]);
         P.tl_bytes = (int32_t)std::min<size_t>(tl_bytes[k], 1u << 30);
-        for (int t = 0; t < 12; ++t) P.tl_off[t] = tl_off[k][t];
+        for (int t = 0; t < 15; ++t) P.tl_off[t] = tl_off[k][t];
+        P.sigf = (const double *)(base + o.sigf);
+        P.nu = (const double *)(base + o.nu);
+        P.chi = (const double *)(base + o.chi);
         P.n_tbins = d.n_tbins;
         P.t_max = d.n_tbins > 0 ? d.t_max : 0.0;
         P.tw = d.n_tbins > 0 ? d.t_max / (double)d.n_tbins : 0.0;
@@ -562,6 +608,15 @@ extern "C" void mcx_destroy_problem(mcx_problem_t h)
     if (h->h_flag) hipHostFree(h->h_flag);
     if (h->h_ctl) hipHostFree(h->h_ctl);
     if (h->ws.ptr) hipFree(h->ws.ptr);
+    for (double *b : h->d_sbank)
+        if (b) hipFree(b);
+    if (h->d_fn) hipFree(h->d_fn);
+    if (h->d_fpos) hipFree(h->d_fpos);
+    if (h->d_sites) hipFree(h->d_sites);
+    if (h->d_tsum) hipFree(h->d_tsum);
+    if (h->d_scratch) hipFree(h->d_scratch);
+    if (h->d_tot) hipFree(h->d_tot);
+    if (h->h_tot) hipHostFree(h->h_tot);
     delete h;
 }
 
@@ -585,6 +640,10 @@ extern "C" mcx_status mcx_set_xs(mcx_problem_t h, int32_t problem, const double 
     for (size_t i = 0; i < mg; ++i)
         if (!(st[i] > 0.0 && ss[i] >= 0.0 && ss[i] <= st[i] && std::isfinite(st[i])))
             return fail(h, MCX_E_INVALID_ARG, "need 0 <= sigma_s <= sigma_t, sigma_t > 0");
+    if (hp.fission)
+        for (size_t i = 0; i < mg; ++i)
+            if (!(hp.sigf[i] <= st[i] - ss[i]))
+                return fail(h, MCX_E_INVALID_ARG, "need sigma_f <= sigma_t - sigma_s");
     HIP_TRY(h, hipMemcpy((void *)h->pd[problem].sig_t, st.data(), mg * 8, hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy((void *)h->pd[problem].sig_s, ss.data(), mg * 8, hipMemcpyHostToDevice));
     hp.sig_t = st;
@@ -776,6 +835,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     c.spills = tot[C_SPILLS];
     c.refills = tot[C_REFILLS];
     c.make_work = tot[C_MAKE_WORK];
+    c.fissions = tot[C_FISSIONS];
     c.rounds = st.rounds;
     c.launches = st.launches;
     c.kernel_ms = tm.total_ms();
@@ -824,6 +884,149 @@ extern "C" mcx_status mcx_run(mcx_problem_t h, const mcx_run_opts *opts)
     h->have_forward = true;
     h->last_first = first;
     h->last_count = count;
+    return MCX_OK;
+}
+
+// grow a device buffer to at least `count` elements (contents not kept)
+template <class T>
+static hipError_t grow(T *&ptr, size_t &cap, size_t count)
+{
+    if (cap >= count && ptr) return hipSuccess;
+    if (ptr) {
+        hipError_t e = hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc((void **)&ptr, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) cap = count;
+    return e;
+}
+
+// device total -> host (on the run's stream)
+static mcx_status read_total(mcx_problem_t h, hipStream_t stream, uint64_t &out)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->h_tot, h->d_tot, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(h, hipStreamSynchronize(stream));
+    out = *h->h_tot;
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, const mcx_eigen_opts *eig)
+{
+    if (!h || !opts || !eig) return MCX_E_INVALID_ARG;
+    mcx_run_opts o = *opts;
+    mcx_status s = check_opts(h, o);
+    if (s != MCX_OK) return s;
+    if (h->n != 1) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs take a single problem");
+    const HostProblem &hp = h->hp[0];
+    if (!hp.fission) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs need fission data");
+    if (hp.d.n_tbins > 0) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs take no time bins");
+    const uint64_t N = eig->n_particles;
+    if (N < 1 || N > (1ull << 30)) return fail(h, MCX_E_INVALID_ARG, "n_particles must be 1..2^30");
+    if (eig->n_cycles < 1 || eig->n_inactive < 0 || eig->n_inactive > eig->n_cycles)
+        return fail(h, MCX_E_INVALID_ARG, "need n_cycles >= 1 and 0 <= n_inactive <= n_cycles");
+    if (!eig->k_cycle || !eig->n_source) return fail(h, MCX_E_INVALID_ARG, "null k_cycle or n_source");
+    o.digest = nullptr;
+    o.first_history = 0;
+    o.n_histories = 0;
+    hipStream_t stream = (hipStream_t)o.hip_stream;
+    h->tallies_valid = false;
+    h->have_forward = false;
+    // buffers: source banks hold up to 2N + 1024 particles; a history banks
+    // at most 15 neutrons
+    const size_t cap = 2 * (size_t)N + 1024;
+    if (h->eig_cap < cap) {
+        size_t c0 = 0;
+        for (double *&b : h->d_sbank) {
+            c0 = 0;
+            HIP_TRY(h, grow(b, c0, 3 * cap));
+        }
+        c0 = 0;
+        HIP_TRY(h, grow(h->d_fn, c0, cap));
+        c0 = 0;
+        HIP_TRY(h, grow(h->d_fpos, c0, 3 * cap));
+        h->eig_cap = cap;
+    }
+    HIP_TRY(h, grow(h->d_tsum, h->tsum_cap, (size_t)eigen_tiles(16 * (uint64_t)cap) + 1));
+    if (!h->d_scratch) HIP_TRY(h, hipMalloc(&h->d_scratch, std::max<size_t>(h->total_bins, 1) * 8));
+    if (!h->d_tot) HIP_TRY(h, hipMalloc(&h->d_tot, 64));
+    if (!h->h_tot) HIP_TRY(h, hipHostMalloc((void **)&h->h_tot, 64, hipHostMallocDefault));
+    HIP_TRY(h, hipMemsetAsync(h->d_tally, 0, std::max<size_t>(h->total_bins, 1) * 8, stream));
+
+    mcx_counters_t sum{};
+    unsigned __int128 qsum = 0;
+    uint64_t Nc = N;
+    const double *src = nullptr;      // cycle 0: the problem's own source
+    int next = 0;
+    ProbDev &P = h->pd[0];
+    auto restore = [&]() {
+        P.sbank = nullptr;
+        P.fn = nullptr;
+        P.fpos = nullptr;
+        P.stream = 0;
+        P.tally = h->d_tally;
+    };
+    for (int c = 0; c < eig->n_cycles; ++c) {
+        P.sbank = src;
+        P.fn = h->d_fn;
+        P.fpos = h->d_fpos;
+        P.stream = (uint32_t)c;
+        P.tally = c >= eig->n_inactive ? h->d_tally : h->d_scratch;
+        std::vector<uint64_t> first{0}, count{Nc};
+        unsigned int err = 0;
+        s = run_pass(h, o, MODE_FWD, first, count, nullptr, &err);
+        restore();
+        if (s != MCX_OK) return s;
+        if (err & ERR_OVERFLOW) return fail(h, MCX_E_OVERFLOW, "fixed-point tally total reached 2^63");
+        const mcx_counters_t &pc = h->counters;
+        sum.sourced += pc.sourced; sum.flights += pc.flights; sum.collisions += pc.collisions;
+        sum.scatters += pc.scatters; sum.absorbs += pc.absorbs; sum.crossings += pc.crossings;
+        sum.leaks += pc.leaks; sum.reflections += pc.reflections; sum.cutoffs += pc.cutoffs;
+        sum.killed += pc.killed; sum.pieces += pc.pieces; sum.events += pc.events;
+        sum.lane_slots += pc.lane_slots; sum.dispatches += pc.dispatches; sum.spills += pc.spills;
+        sum.refills += pc.refills; sum.make_work += pc.make_work; sum.rounds += pc.rounds;
+        sum.launches += pc.launches; sum.kernel_ms += pc.kernel_ms; sum.fissions += pc.fissions;
+        sum.grid_blocks = pc.grid_blocks; sum.block_threads = pc.block_threads; sum.lds_bytes = pc.lds_bytes;
+        qsum += pc.qsum;
+        // the bank: each history's neutrons, in history order
+        uint64_t M = 0;
+        hipError_t e = eigen_count_sites(h->d_fn, Nc, h->d_tsum, h->d_tot, stream);
+        if (e != hipSuccess) return hip_fail(h, e, "fission bank count");
+        s = read_total(h, stream, M);
+        if (s != MCX_OK) return s;
+        eig->n_source[c] = Nc;
+        eig->k_cycle[c] = (double)M / (double)Nc;
+        sum.sites += M;
+        if (M == 0) return fail(h, MCX_E_STATE, "cycle %d banked no fission neutron", c);
+        if (M >= (1ull << 32)) return fail(h, MCX_E_CAPACITY, "cycle %d banked 2^32 neutrons or more", c);
+        HIP_TRY(h, grow(h->d_sites, h->sites_cap, 3 * (size_t)M));
+        e = eigen_gather_sites(h->d_fn, h->d_fpos, Nc, h->d_tsum, h->d_sites, stream);
+        if (e != hipSuccess) return hip_fail(h, e, "fission bank gather");
+        // splitting-roulette back to about N
+        const double r = (double)N / (double)M;
+        const double fl = std::floor(r);
+        const double fr = r - fl;
+        uint64_t Nn = 0;
+        e = eigen_count_copies(P.key0, P.key1, (uint32_t)c, (uint64_t)fl, fr, M, h->d_tsum, h->d_tot, stream);
+        if (e != hipSuccess) return hip_fail(h, e, "population control count");
+        s = read_total(h, stream, Nn);
+        if (s != MCX_OK) return s;
+        if (Nn == 0) return fail(h, MCX_E_STATE, "population control left no particle after cycle %d", c);
+        if (Nn > cap) return fail(h, MCX_E_CAPACITY, "source bank overflow after cycle %d", c);
+        e = eigen_scatter_copies(P.key0, P.key1, (uint32_t)c, (uint64_t)fl, fr, M, h->d_tsum, h->d_sites,
+                                 h->d_sbank[next], cap, stream);
+        if (e != hipSuccess) return hip_fail(h, e, "population control scatter");
+        src = h->d_sbank[next];
+        next ^= 1;
+        Nc = Nn;
+    }
+    HIP_TRY(h, hipStreamSynchronize(stream));
+    sum.qsum = (uint64_t)qsum;
+    sum.overflow = qsum >= ((unsigned __int128)1 << 63) ? 1 : 0;
+    h->counters = sum;
+    if (sum.overflow) return fail(h, MCX_E_OVERFLOW, "fixed-point tally total reached 2^63");
+    h->tallies_valid = true;
     return MCX_OK;
 }
 

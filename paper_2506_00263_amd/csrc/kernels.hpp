@@ -101,4 +101,16 @@ hipError_t launch_stack_time(const LaunchArgs &a, Workspace &ws, LaunchStats &st
                              unsigned int *host_flag_pinned);
 hipError_t launch_async_time(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm);
 
+// k-eigenvalue banking between cycles (eigen.hip).  tsum holds
+// eigen_tiles(n) words; totals are written to device memory.
+uint64_t eigen_tiles(uint64_t n);
+hipError_t eigen_count_sites(const uint32_t *fn, uint64_t n, uint64_t *tsum, uint64_t *total, hipStream_t s);
+hipError_t eigen_gather_sites(const uint32_t *fn, const double *fpos, uint64_t n, const uint64_t *tsum,
+                              double *sites, hipStream_t s);
+hipError_t eigen_count_copies(uint32_t key0, uint32_t key1, uint32_t stream, uint64_t fl, double fr, uint64_t m,
+                              uint64_t *tsum, uint64_t *total, hipStream_t s);
+hipError_t eigen_scatter_copies(uint32_t key0, uint32_t key1, uint32_t stream, uint64_t fl, double fr, uint64_t m,
+                                const uint64_t *tsum, const double *sites, double *next, uint64_t cap,
+                                hipStream_t s);
+
 }  // namespace mcx

@@ -65,7 +65,7 @@ struct ProbDev {
     // tl_off[t]: offset of table t in 8-byte words (TL_CMAT: in 4-byte words).
     const double *tl_src;
     int32_t tl_bytes;                // packed size, a multiple of 16
-    int32_t tl_off[12];
+    int32_t tl_off[15];
     // time-binned tally (temporal tally resolution, paper Sec. 4): n_tbins
     // equal bins of width tw = t_max / n_tbins; 0 = no time dimension.  A
     // particle moves at speed[g] (multigroup, a packed table) or
@@ -75,9 +75,23 @@ struct ProbDev {
     long long nbase;                 // bins of the tally without time
     long long n_bins;                // all bins of this problem's tally
     const double *speed;
+    // fission (k-eigenvalue cycles, multigroup): Sigma_f, nu per (material,
+    // group) and the cumulative fission spectrum chi per material (packed
+    // tables).  Cycle state, null outside k-eigenvalue cycles: the cycle's
+    // source positions (3 per history) and, per history, the neutrons it
+    // banks and its fission site (3 doubles).
+    const double *sigf, *nu, *chi;
+    const double *sbank;
+    uint32_t *fn;
+    double *fpos;
+    uint32_t stream;                 // random-number stream: the cycle (0 otherwise)
+    int32_t pad2;
 };
 
-enum : int { TL_SIG_T = 0, TL_SIG_S, TL_CDF, TL_XPL, TL_YPL, TL_CXS, TL_CYS, TL_MX, TL_MY, TL_MZ, TL_SPEED, TL_CMAT };
+enum : int {
+    TL_SIG_T = 0, TL_SIG_S, TL_CDF, TL_XPL, TL_YPL, TL_CXS, TL_CYS, TL_MX, TL_MY, TL_MZ, TL_SPEED,
+    TL_SIGF, TL_NU, TL_CHI, TL_CMAT
+};
 constexpr int TL_NDBL = TL_CMAT;      // tables of doubles in front of the int32 materials
 constexpr int TL_MAX_BYTES = 32768;   // larger tables stay in global memory
 constexpr int LT_MAX_BINS = 4096;     // tallies up to this size can be summed in LDS per block
@@ -87,7 +101,7 @@ constexpr long long TREP_MAX_BINS = 1ll << 24;
 enum Counter : int {
     C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,
     C_CUTOFFS, C_KILLED, C_PIECES, C_EVENTS, C_LANE_SLOTS, C_DISPATCHES, C_SPILLS, C_REFILLS, C_MAKE_WORK,
-    C_COMPLETED, C_QSUM, C_PASSA_U, C_NUM
+    C_FISSIONS, C_COMPLETED, C_QSUM, C_PASSA_U, C_NUM
 };
 constexpr int C_WAVE = C_COMPLETED;   // entries counted per wavefront (32-bit)
 

@@ -29,7 +29,8 @@ namespace mcx {
 enum : int { EV_STEP = 0, EV_LOOKUP = 0, EV_MOVE = 1, EV_SURFACE = 2, EV_COLLIDE = 3, EV_DEAD = 7 };
 enum : uint32_t {
     O_SOURCE = 1u << 0, O_FLIGHT = 1u << 1, O_COLL = 1u << 2, O_SCAT = 1u << 3, O_ABS = 1u << 4,
-    O_CROSS = 1u << 5, O_LEAK = 1u << 6, O_REFL = 1u << 7, O_CUT = 1u << 8, O_KILL = 1u << 9
+    O_CROSS = 1u << 5, O_LEAK = 1u << 6, O_REFL = 1u << 7, O_CUT = 1u << 8, O_KILL = 1u << 9,
+    O_FISS = 1u << 10
 };
 enum : uint32_t { FATE_LEAK = 0, FATE_ABSORB = 1, FATE_CUTOFF = 2, FATE_KILLED = 3 };
 
@@ -101,6 +102,9 @@ struct TabsG {
     __device__ __forceinline__ const double *my() const { return P.my; }
     __device__ __forceinline__ const double *mz() const { return P.mz; }
     __device__ __forceinline__ const double *speed() const { return P.speed; }
+    __device__ __forceinline__ const double *sigf() const { return P.sigf; }
+    __device__ __forceinline__ const double *nu() const { return P.nu; }
+    __device__ __forceinline__ const double *chi() const { return P.chi; }
     __device__ __forceinline__ const int32_t *cmat() const { return P.cmat; }
 };
 
@@ -118,6 +122,9 @@ struct TabsL {
     __device__ __forceinline__ const double *my() const { return d + P.tl_off[TL_MY]; }
     __device__ __forceinline__ const double *mz() const { return d + P.tl_off[TL_MZ]; }
     __device__ __forceinline__ const double *speed() const { return d + P.tl_off[TL_SPEED]; }
+    __device__ __forceinline__ const double *sigf() const { return d + P.tl_off[TL_SIGF]; }
+    __device__ __forceinline__ const double *nu() const { return d + P.tl_off[TL_NU]; }
+    __device__ __forceinline__ const double *chi() const { return d + P.tl_off[TL_CHI]; }
     __device__ __forceinline__ const int32_t *cmat() const { return (const int32_t *)d + P.tl_off[TL_CMAT]; }
 };
 
@@ -582,10 +589,16 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
 {
     Key k{P.key0, P.key1};
     double x0, x1, x2, x3, x4, x5;
-    uniform_pair(k, hid, 0, 0, x0, x1);
-    uniform_pair(k, hid, 0, 1, x2, x3);
-    uniform_pair(k, hid, 0, 2, x4, x5);
-    if (P.src_kind == 0) {
+    uniform_pair(k, hid, 0, 0, x0, x1, P.stream);
+    uniform_pair(k, hid, 0, 1, x2, x3, P.stream);
+    uniform_pair(k, hid, 0, 2, x4, x5, P.stream);
+    const uint64_t idx = P.gbase + (uint64_t)(hid - P.first);
+    const bool banked = P.sbank != nullptr;   // a k-eigenvalue cycle after the first
+    if (banked) {
+        p.x = P.sbank[3 * idx];
+        p.y = P.sbank[3 * idx + 1];
+        p.z = P.sbank[3 * idx + 2];
+    } else if (P.src_kind == 0) {
         p.x = P.src_pos[0]; p.y = P.src_pos[1]; p.z = P.src_pos[2];
     } else if (P.src_kind == 1) {
         p.x = P.src_lo[0] + (x0 * P.src_ext[0]);
@@ -599,13 +612,27 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
         p.y = P.src_pos[1] + (r * s);
         p.z = P.src_pos[2];
     }
-    if (P.src_iso) {
+    if (P.src_iso || banked) {
         isotropic(x3, x4, p);
     } else {
         p.u = P.src_dir[0]; p.v = P.src_dir[1]; p.w = P.src_dir[2];
     }
     p.e = P.e_src;
     p.gc = locate<GEOM>(P, T, p.x, p.y, p.u, p.v, P.src_group);
+    if (banked) {
+        // a banked fission neutron: group from the fission spectrum of the
+        // material at its site (slot 0)
+        const double *row = T.chi() + (long)material<GEOM>(P, T, p.gc) * P.n_grp;
+        int g = P.n_grp - 1;
+        for (int k2 = 0; k2 < P.n_grp; ++k2) {
+            if (x0 < row[k2]) {
+                g = k2;
+                break;
+            }
+        }
+        p.gc = (p.gc & ~0xffu) | (uint32_t)g;
+    }
+    if (P.fn) P.fn[idx] = 0u;
     p.hid = hid;
     p.prob = prob;
     p.step = 1;
@@ -751,6 +778,16 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
         if (!((xi1 * sigt) < ss)) {
             out |= O_ABS;
             if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 1, mg, (long long)to_fixed(p.G, P.gscale));
+            // k-eigenvalue cycle: the absorption is a fission with probability
+            // Sigma_f / Sigma_a and banks floor(nu + xi) neutrons at the site
+            if (MODE == MODE_FWD && P.fn && ((xi2 * (sigt - ss)) < T.sigf()[mg])) {
+                const uint64_t idx = P.gbase + (uint64_t)(p.hid - P.first);
+                P.fn[idx] = (uint32_t)(T.nu()[mg] + xi3);
+                P.fpos[3 * idx] = p.x;
+                P.fpos[3 * idx + 1] = p.y;
+                P.fpos[3 * idx + 2] = p.z;
+                out |= O_FISS;
+            }
             finish<MODE>(P, cx, ln, p, FATE_ABSORB);
             return false;
         }
@@ -806,7 +843,7 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
     else sigt = ce_lookup(P, m, p.e, X);
     Key k{P.key0, P.key1};
     double xi0, xi1;
-    uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
+    uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
     int surf;
     const int res = fly<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, sigt, xi0, m, surf);
     out |= O_FLIGHT;
@@ -817,8 +854,8 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
     }
     if (res == FLY_COLLIDE) {
         double xi2, xi3, xi4, xi5;
-        uniform_pair(k, p.hid, p.step, 1, xi2, xi3);
-        uniform_pair(k, p.hid, p.step, 2, xi4, xi5);
+        uniform_pair(k, p.hid, p.step, 1, xi2, xi3, P.stream);
+        uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
         if (!collide<EMODE, MODE>(P, T, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
     } else {
         if (!cross<GEOM>(P, T, p, surf, out)) {
@@ -838,7 +875,7 @@ __device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCt
     int m = material<GEOM>(P, T, p.gc);
     Key k{P.key0, P.key1};
     double xi0, xi1;
-    uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
+    uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
     int surf;
     const int res = fly<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, p.sigt, xi0, m, surf);
     out |= O_FLIGHT;
@@ -872,9 +909,9 @@ __device__ __forceinline__ int ev_collide(const ProbDev &P, const TB &T, const E
     if (EMODE == EMODE_CE) ce_lookup(P, m, p.e, X);
     Key k{P.key0, P.key1};
     double xi0, xi1, xi2, xi3, xi4, xi5;
-    uniform_pair(k, p.hid, p.step, 0, xi0, xi1);
-    uniform_pair(k, p.hid, p.step, 1, xi2, xi3);
-    uniform_pair(k, p.hid, p.step, 2, xi4, xi5);
+    uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
+    uniform_pair(k, p.hid, p.step, 1, xi2, xi3, P.stream);
+    uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
     if (!collide<EMODE, MODE>(P, T, cx, ln, p, m, p.sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
     p.step += 1;
     return EV_LOOKUP;
@@ -933,6 +970,7 @@ struct WaveCount {
         c[C_REFLECTIONS] += (uint32_t)__popcll(__ballot(act && (out & O_REFL)));
         c[C_CUTOFFS] += (uint32_t)__popcll(__ballot(act && (out & O_CUT)));
         c[C_KILLED] += (uint32_t)__popcll(__ballot(act && (out & O_KILL)));
+        c[C_FISSIONS] += (uint32_t)__popcll(__ballot(act && (out & O_FISS)));
     }
     __device__ __forceinline__ void dispatch(bool act)
     {

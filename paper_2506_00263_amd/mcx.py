@@ -49,6 +49,7 @@ class ProblemDesc(C.Structure):
         ("mesh_z", C.c_void_p), ("n_ebins", C.c_int32), ("e_edges", C.c_void_p), ("tally_scale_log2", C.c_int32),
         ("problem_id", C.c_uint32), ("seed", C.c_uint64), ("n_histories", C.c_uint64), ("max_steps", C.c_int64),
         ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p), ("speed_coef", C.c_double),
+        ("sigma_f", C.c_void_p), ("nu", C.c_void_p), ("chi", C.c_void_p),
     ]
 
 
@@ -72,7 +73,12 @@ COUNTER_NAMES = ["sourced", "flights", "collisions", "scatters", "absorbs", "cro
 class Counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in COUNTER_NAMES] + [
         ("kernel_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
-        ("lds_bytes", C.c_int32), ("pad", C.c_int32)]
+        ("lds_bytes", C.c_int32), ("pad", C.c_int32), ("fissions", C.c_uint64), ("sites", C.c_uint64)]
+
+
+class EigenOpts(C.Structure):
+    _fields_ = [("n_particles", C.c_uint64), ("n_cycles", C.c_int32), ("n_inactive", C.c_int32),
+                ("k_cycle", C.c_void_p), ("n_source", C.c_void_p)]
 
 
 DIGEST_DTYPE = np.dtype([("qsum", "<i8"), ("flights", "<u4"), ("collisions", "<u4"), ("fate", "<u4"),
@@ -95,6 +101,7 @@ def lib():
         L.mcx_tallies.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32]
         L.mcx_backward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(RunOpts)]
         L.mcx_counters.argtypes = [C.c_void_p, P(Counters)]
+        L.mcx_run_eigen.argtypes = [C.c_void_p, P(RunOpts), P(EigenOpts)]
         L.mcx_problem_info.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int32), P(C.c_int32),
                                        P(C.c_uint64)]
         L.mcx_destroy_problem.argtypes = [C.c_void_p]
@@ -193,6 +200,15 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
             raise ValueError("time bins need one speed per group")
         s.speed = arr("speed", np.float64)
     s.speed_coef = float(d.get("speed_coef", 0.0))
+    s.sigma_f = s.nu = s.chi = None
+    if d.get("sigma_f") is not None:
+        mg = int(d["n_mat"]) * int(d["n_grp"])
+        for name in ("sigma_f", "nu", "chi"):
+            if np.asarray(d[name]).size != mg:
+                raise ValueError(f"{name} needs n_mat * n_grp entries")
+        s.sigma_f = arr("sigma_f", np.float64)
+        s.nu = arr("nu", np.float64)
+        s.chi = arr("chi", np.float64)
     return s
 
 
@@ -284,6 +300,16 @@ class Problem:
         self._check(lib().mcx_run(self.h, C.byref(o)))
         return self
 
+    def run_eigen(self, n_particles: int, n_cycles: int, n_inactive: int, **kw) -> dict:
+        """k-eigenvalue power iteration: returns k and the source size of every
+        cycle; the tallies then hold the active cycles' sum."""
+        o = run_opts(**kw)
+        k = np.zeros(n_cycles, np.float64)
+        ns = np.zeros(n_cycles, np.uint64)
+        e = EigenOpts(int(n_particles), int(n_cycles), int(n_inactive), _ptr(k), _ptr(ns))
+        self._check(lib().mcx_run_eigen(self.h, C.byref(o), C.byref(e)))
+        return dict(k=k, n_source=ns.astype(np.int64))
+
     def tallies(self, problem: int = 0) -> np.ndarray:
         n = self.info(problem)["n_bins"]
         out = np.empty(n, np.int64)
@@ -320,6 +346,6 @@ class Problem:
         self._check(lib().mcx_counters(self.h, C.byref(c)))
         out = {n: int(getattr(c, n)) for n in COUNTER_NAMES}
         out.update(kernel_ms=c.kernel_ms, grid_blocks=c.grid_blocks, block_threads=c.block_threads,
-                   lds_bytes=c.lds_bytes)
+                   lds_bytes=c.lds_bytes, fissions=int(c.fissions), sites=int(c.sites))
         return out
 

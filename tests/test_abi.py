@@ -37,9 +37,10 @@ def test_struct_sizes_match_header():
 #include <stddef.h>
 #include "mcx.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu\n", sizeof(mcx_problem_desc), sizeof(mcx_run_opts), sizeof(mcx_counters_t),
-         sizeof(mcx_digest), offsetof(mcx_problem_desc, max_steps), offsetof(mcx_run_opts, time_kernels),
-         offsetof(mcx_problem_desc, speed_coef));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mcx_problem_desc), sizeof(mcx_run_opts),
+         sizeof(mcx_counters_t), sizeof(mcx_digest), offsetof(mcx_problem_desc, max_steps),
+         offsetof(mcx_run_opts, time_kernels), offsetof(mcx_problem_desc, speed_coef), sizeof(mcx_eigen_opts),
+         offsetof(mcx_counters_t, sites));
   return 0;
 }
 '''
@@ -58,3 +59,5 @@ int main(void) {
     assert sizes[4] == mcx.ProblemDesc.max_steps.offset
     assert sizes[5] == mcx.RunOpts.time_kernels.offset
     assert sizes[6] == mcx.ProblemDesc.speed_coef.offset
+    assert sizes[7] == ctypes.sizeof(mcx.EigenOpts)
+    assert sizes[8] == mcx.Counters.sites.offset
