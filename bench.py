@@ -72,7 +72,18 @@ def _wall(P, reps, **kw):
     return float(np.median(ts[1:]))
 
 
-SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "backward", "batch")
+SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "eigen", "backward", "batch")
+
+
+def eigen_run(P, n, cycles, **kw):
+    """Wall time of one k-eigenvalue run (cycles, 25 % inactive) and its
+    histories (the source sizes summed over cycles)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = P.run_eigen(n, cycles, cycles // 4, **kw)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, int(r["n_source"].sum()), r
 
 
 def sweep(parts=SWEEP_PARTS) -> dict:
@@ -144,6 +155,26 @@ def sweep(parts=SWEEP_PARTS) -> dict:
                                               "ms": 1e3 * t, "hist_per_s": d["n_histories"] / t})
                     print("sweep tally_path", out["tally_path"][-1], file=sys.stderr, flush=True)
             del P
+    # k-eigenvalue power iteration (the paper's C5G7 experiment, §4-5.1):
+    # histories/s against histories per cycle, 24 and 48 cycles (25 % inactive)
+    if "eigen" in parts:
+        P = mcx.Problem(inputs.with_fission(inputs.cfg2_lattice(1)))
+        for cycles in (24, 48):
+            for n in (10_000, 100_000, 1_000_000, 10_000_000):
+                if cycles == 48 and n == 10_000_000:
+                    continue
+                for s, dc in scheds:
+                    eigen_run(P, n, 2, sched=s, decomp=dc)
+                    ts = []
+                    for _ in range(2):
+                        t, nh, r = eigen_run(P, n, cycles, sched=s, decomp=dc)
+                        ts.append(t)
+                    t = float(np.median(ts))
+                    out["eigen"].append({"cycles": cycles, "per_cycle": n, "sched": s, "decomp": dc,
+                                         "ms": 1e3 * t, "hist_per_s": nh / t,
+                                         "k_active": float(np.mean(r["k"][cycles // 4:]))})
+                    print("sweep eigen", out["eigen"][-1], file=sys.stderr, flush=True)
+        del P
     import torch
     d = inputs.cfg4_lattice_grad(1_000_000)
     P = mcx.Problem(d) if "backward" in parts else None
@@ -333,6 +364,25 @@ def main():
                     raise SystemExit(f"batched tally mismatch: {s} {knobs}")
             bres[s] = rec
         out["batched"] = {"problems": len(probs), "histories": nb, **bres}
+        # k-eigenvalue: the lattice with synthetic fission, 1e6 particles per
+        # cycle, 24 cycles (6 inactive), default knobs
+        E = mcx.Problem(inputs.with_fission(inputs.cfg2_lattice(1)))
+        eres = {}
+        eref = None
+        for s, dc in (("naive", "fused"), ("stack", "fused"), ("async", "fused")):
+            eigen_run(E, N_HIST, 2, sched=s, decomp=dc)
+            ts = []
+            for _ in range(2):
+                t, nh, r = eigen_run(E, N_HIST, 24, sched=s, decomp=dc)
+                ts.append(t)
+            if eref is None:
+                eref = (r["k"], E.tallies())
+            elif not (np.array_equal(eref[0], r["k"]) and np.array_equal(eref[1], E.tallies())):
+                raise SystemExit(f"k-eigenvalue mismatch between schedulers: {s}/{dc}")
+            t = float(np.median(ts))
+            eres[f"{s}_{dc}"] = {"ms": 1e3 * t, "hist_per_s": nh / t}
+        out["eigen"] = {"per_cycle": N_HIST, "cycles": 24, "inactive": 6,
+                        "k_active_mean": float(np.mean(eref[0][6:])), **eres}
 
     if not args.no_cpu:
         # the oracle as it stands, on the host cores: the whole workload,
