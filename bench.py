@@ -72,7 +72,8 @@ def _wall(P, reps, **kw):
     return float(np.median(ts[1:]))
 
 
-SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "eigen", "backward", "batch")
+SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "eigen", "async_waves", "backward",
+               "batch")
 
 
 def eigen_run(P, n, cycles, **kw):
@@ -175,6 +176,26 @@ def sweep(parts=SWEEP_PARTS) -> dict:
                                          "k_active": float(np.mean(r["k"][cycles // 4:]))})
                     print("sweep eigen", out["eigen"][-1], file=sys.stderr, flush=True)
         del P
+    # wavefronts per asynchronous block (each with its own stash; the block
+    # shares the LDS tables and tally sums)
+    if "async_waves" in parts:
+        cases = [("lattice 1e5", inputs.cfg2_lattice(100_000), {}), ("lattice 1e6", inputs.cfg2_lattice(1_000_000), {}),
+                 ("lattice 1e7", inputs.cfg2_lattice(10_000_000), {}), ("box 1e6", inputs.cfg1_box(1_000_000), {})]
+        for nt in (1, 16, 32):
+            cases.append((f"pin cell 100 x {nt} time bins, LDS sums",
+                          inputs.with_time_bins(inputs.cfg3_pincell(n_ebins=100, n_histories=1_000_000), nt, 5e-7,
+                                                speed_coef=NEUTRON_SPEED), {"tally_path": "lds"}))
+        for name, d, kw in cases:
+            P = mcx.Problem(d)
+            for dc in ("fused", "split"):
+                for wpb in (1, 2, 4):
+                    t = _wall(P, 2, sched="async", decomp=dc, async_block_waves=wpb, **kw)
+                    c = P.counters()
+                    out["async_waves"].append({"case": name, "decomp": dc, "waves_per_block": wpb, "ms": 1e3 * t,
+                                               "hist_per_s": d["n_histories"] / t, "grid_blocks": c["grid_blocks"],
+                                               "block_threads": c["block_threads"], "lds_bytes": c["lds_bytes"]})
+                    print("sweep async_waves", out["async_waves"][-1], file=sys.stderr, flush=True)
+            del P
     import torch
     d = inputs.cfg4_lattice_grad(1_000_000)
     P = mcx.Problem(d) if "backward" in parts else None

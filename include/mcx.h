@@ -197,7 +197,12 @@ typedef struct {
                                  go (mcx_tally_path; 0 = chosen by tally size
                                  and scheduler).  Batches and backward passes
                                  add into the tallies directly.               */
-    int32_t reserved[2];
+    int32_t async_block_waves;/* async: wavefronts per block, 1, 2 or 4; each
+                                 keeps its own stash, the block shares one LDS
+                                 copy of the tables and tally sums (0 =
+                                 library default, 4; fewer when the block's
+                                 LDS would not fit)                           */
+    int32_t reserved[1];
 } mcx_run_opts;
 
 /* Tally paths (results are the same integers on every path):

@@ -1,7 +1,7 @@
 """Autotuner for the remapping schedulers.
 
-Grid search over the tuning knobs of a scheduler (async: resident
-wavefronts per CU and stash links; stack: events a popped particle runs
+Grid search over the tuning knobs of a scheduler (async: wavefronts per
+block, resident wavefronts per CU and stash links; stack: events a popped particle runs
 before it is pushed again, at least and in the tail; naive: block size) on a
 calibration run, timed with HIP events inside the library.  Knobs never
 change results: every candidate's tally is checked against the first
@@ -26,9 +26,10 @@ def candidates(sched: str, decomp: str) -> list:
     events = 4 if decomp == "split" else 1
     if sched == "async":
         out = []
-        for wpc in (0, 4, 6):
-            for links in sorted({events + 1, events + 2, events + 3}):
-                out.append(dict(waves_per_cu=wpc, stash_links=links))
+        for wpb in (4, 1):
+            for wpc in (0, 8):
+                for links in sorted({events + 1, events + 2, events + 3}):
+                    out.append(dict(async_block_waves=wpb, waves_per_cu=wpc, stash_links=links))
         return out
     if sched == "stack":
         return [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 256)]

@@ -114,11 +114,11 @@ static mcx_status hip_fail(mcx_problem_t p, hipError_t e, const char *where)
 
 // Default tally paths, from measurements on MI355X (1e6 histories: box with
 // 2000 mesh bins, continuous-energy pin cell with 100 energy x 1..64 time
-// bins, lattice with 364140 mesh bins): LDS sums are fastest up to 4096 bins
-// except for the asynchronous scheduler, whose one-wavefront blocks each hold
-// a copy (fused: faster up to about 2048 bins, split, with its larger stash:
-// up to about 1024); replicas beat direct adds by 2-15x below 65536 bins and
-// tie at 364140.
+// bins, lattice with 364140 mesh bins): LDS sums are fastest up to 4096 bins,
+// except for asynchronous launches with one-wavefront blocks, where each
+// wavefront holds a copy (fused: faster up to about 2048 bins, split, with
+// its larger stash: up to about 1024); replicas beat direct adds by 2-15x
+// below 65536 bins and tie at 364140.
 constexpr long long ASYNC_LDS_TALLY_BINS_FUSED = 2048;
 constexpr long long ASYNC_LDS_TALLY_BINS_SPLIT = 1024;
 constexpr long long AUTO_REPLICA_MAX_BINS = 1 << 16;
@@ -678,6 +678,9 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
         o.stack_min_events < 0)
         return fail(h, MCX_E_INVALID_ARG, "negative tuning value");
     if (o.consolidate < 0 || o.consolidate > 2) return fail(h, MCX_E_INVALID_ARG, "bad consolidate");
+    if (o.async_block_waves != 0 && o.async_block_waves != 1 && o.async_block_waves != 2 &&
+        o.async_block_waves != 4)
+        return fail(h, MCX_E_INVALID_ARG, "async_block_waves must be 0, 1, 2 or 4");
     if (o.tally_path < MCX_TALLY_PATH_AUTO || o.tally_path > MCX_TALLY_PATH_DIRECT)
         return fail(h, MCX_E_INVALID_ARG, "bad tally_path");
     if (o.tally_path == MCX_TALLY_PATH_LDS && h->hp[0].n_bins > LT_MAX_BINS)
@@ -709,7 +712,8 @@ static int tally_path(mcx_problem_t h, const mcx_run_opts &o, int mode)
     if (o.tally_path != MCX_TALLY_PATH_AUTO) return o.tally_path;
     const long long nb = h->hp[0].n_bins;
     long long lds_max = LT_MAX_BINS;
-    if (o.sched == MCX_SCHED_ASYNC)
+    const int wpb = o.async_block_waves > 0 ? o.async_block_waves : ASYNC_BLOCK_WAVES;
+    if (o.sched == MCX_SCHED_ASYNC && wpb == 1)
         lds_max = o.decomp == MCX_DECOMP_SPLIT ? ASYNC_LDS_TALLY_BINS_SPLIT : ASYNC_LDS_TALLY_BINS_FUSED;
     if (nb <= lds_max) return MCX_TALLY_PATH_LDS;
     if (nb <= AUTO_REPLICA_MAX_BINS) return MCX_TALLY_PATH_REPLICAS;
@@ -782,6 +786,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.consolidate = o.consolidate;
     a.stack_tail_events = o.stack_tail_events;
     a.stack_min_events = o.stack_min_events;
+    a.async_block_waves = o.async_block_waves;
 
     LaunchStats st;
     LaunchTimer tm;

@@ -77,7 +77,15 @@ struct LaunchArgs {
     int consolidate;                       // async: 0 default, 1 on, 2 off
     int stack_tail_events;                 // stack: events per pop in the tail (0 = default)
     int stack_min_events;                  // stack: events per pop at least (0 = default 1)
+    int async_block_waves;                 // async: wavefronts per block, 1, 2 or 4 (0 = ASYNC_BLOCK_WAVES)
 };
+
+// Default wavefronts per asynchronous block.  Measured on MI355X (1e6
+// histories unless noted): sharing the block's LDS tables and tally sums
+// among 4 wavefronts made the continuous-energy pin cell with 3200 LDS bins
+// 1.7x (fused) and 1.9x (split) faster, the box 1.2x and the 1e7 lattice 1.1x,
+// and changed the rest by a few percent either way.
+constexpr int ASYNC_BLOCK_WAVES = 4;
 
 struct LaunchStats {
     unsigned long long launches = 0, rounds = 0;

@@ -50,6 +50,7 @@ struct AsyncArgs {
     int force_spill;             // testing: spill every k-th filled link
     int consolidate;             // drained sparse stashes are handed to the arena and merged
     int tl_bytes;                // packed tables copied to LDS (single problem)
+    int wpb;                     // wavefronts per block (each with its own stash)
 };
 
 constexpr uint32_t NIL = 0xFFFFFFFFu;
@@ -327,16 +328,23 @@ struct AsyncWave {
     }
 };
 
+// A block holds A.wpb wavefronts.  Each runs independently with its own
+// stash; the block shares one LDS copy of the tables and one set of LDS
+// tally sums, which one-wavefront blocks would each hold (the occupancy cost
+// the paper attributes to per-warp stashes, Sec. 5.2).
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int TIME>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2))) async_kernel(AsyncArgs A)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2))) async_kernel(AsyncArgs A)
 {
     using LAY = Layout<EMODE, MODE, SPLIT, TIME>;
     constexpr int E = SPLIT ? 4 : 1;
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const bool dig = A.digest != nullptr;
     const int L = A.links;
-    unsigned long long *lacc = (unsigned long long *)(lds + (long)L * A.link_bytes);
-    char *tl = lds + tabs_lds_offset((size_t)L * A.link_bytes + (size_t)A.lacc_words * 8);
+    const int wib = (int)(threadIdx.x >> 6);                       // wavefront in block
+    const unsigned int gw = blockIdx.x * (unsigned int)A.wpb + (unsigned int)wib;   // global wavefront
+    const size_t stash_bytes = (size_t)A.wpb * L * A.link_bytes;
+    unsigned long long *lacc = (unsigned long long *)(lds + stash_bytes);
+    char *tl = lds + tabs_lds_offset(stash_bytes + (size_t)A.lacc_words * 8);
     if constexpr (!BATCH) tabs_to_lds(A.probs[0], tl);
     // LDS block sums: pass B's per-(material, group) sums, or the bins of a small
     // energy-bin tally (single-problem launches)
@@ -346,11 +354,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(BATCH ?
         lacc_zero(lacc, A.lacc_words);
         __syncthreads();
     }
-    Lane ln{0, 0, 0, 0, (uint32_t)(blockIdx.x % TREP)};
+    Lane ln{0, 0, 0, 0, (uint32_t)(gw % TREP)};
     WaveCount wc;
     wc.zero();
     const int lane = __lane_id();
-    AsyncWave W{A, lds, LAY::nd(dig), LAY::nu(dig), blockIdx.x * 2654435761u, Stash{}, 0u};
+    AsyncWave W{A, lds + (size_t)wib * L * A.link_bytes, LAY::nd(dig), LAY::nu(dig), gw * 2654435761u, Stash{}, 0u};
     W.S.freem = (L >= 32) ? 0xFFFFFFFFu : ((1u << L) - 1u);
     W.S.readym = 0;
     W.S.clo = 0;
@@ -510,16 +518,26 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     if (L > 16) L = 16;
     int link_bytes = 64 * LAY::bytes(dig);
     const int tl_bytes = BATCH ? 0 : a.tl_bytes;
-    size_t lds = tabs_lds_offset((size_t)L * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
+    int wpb = a.async_block_waves > 0 ? a.async_block_waves : ASYNC_BLOCK_WAVES;
+    if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
     auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, TIME>;
+    // fewer wavefronts per block when the block's LDS would not fit
+    size_t lds = 0;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64, lds);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    for (;; wpb >>= 1) {
+        lds = tabs_lds_offset((size_t)wpb * L * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu >= 1 || wpb == 1) break;
+    }
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    int wpc = a.waves_per_cu > 0 ? std::min(a.waves_per_cu, per_cu) : per_cu;
-    long blocks = (long)a.num_cus * wpc;
+    int wpc = per_cu * wpb;           // resident wavefronts per CU
+    if (a.waves_per_cu > 0 && a.waves_per_cu < wpc) wpc = std::max(wpb, a.waves_per_cu / wpb * wpb);
+    long blocks = (long)a.num_cus * (wpc / wpb);
+    long waves = blocks * wpb;
     const int Q = 64;                 // one queue per lane of a wavefront
-    int n_arena = a.arena_links > 0 ? a.arena_links : (int)(blocks * (E + 2) + 1024);
+    int n_arena = a.arena_links > 0 ? a.arena_links : (int)(waves * (E + 2) + 1024);
     size_t arena_bytes = (size_t)n_arena * link_bytes;
     size_t need = arena_bytes + (size_t)n_arena * 8 + (size_t)Q * 16 + 1024;
     e = ws_reserve(ws, need);
@@ -547,13 +565,14 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.force_spill = a.force_spill;
     A.consolidate = a.consolidate == 1 ? 1 : 0;   // off unless asked for
     A.tl_bytes = tl_bytes;
+    A.wpb = wpb;
     int ib = (std::max(n_arena, Q) + 255) / 256;
-    hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A, (unsigned int)blocks);
+    hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A, (unsigned int)waves);
     st.grid_blocks = (int)blocks;
-    st.block_threads = 64;
+    st.block_threads = 64 * wpb;
     st.lds_bytes = (int)lds;
     tm.begin();
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64), lds, a.stream, A);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, A);
     tm.end();
     st.launches += 2;
     st.rounds = 1;

@@ -50,6 +50,9 @@ def test_lattice_eigen(mcx, lattice_k, sched, decomp):
     P = mcx.Problem(d)
     got = P.run_eigen(20_000, 5, 2, sched=sched, decomp=decomp)
     _check(P, got, ref, (sched, decomp))
+    if sched == "async":
+        got = P.run_eigen(20_000, 5, 2, sched=sched, decomp=decomp, async_block_waves=4)
+        _check(P, got, ref, (sched, decomp, "4 waves per block"))
 
 
 def test_slab_eigen_leakage_and_tally_paths(mcx, oracle):

@@ -327,3 +327,43 @@ def test_tally_paths(mcx, oracle, cfg1, sched, decomp):
     assert e.value.status == 1
     with pytest.raises(mcx.McxError):
         R.run(sched=sched, decomp=decomp, tally_path=7)
+
+
+@pytest.mark.parametrize("wpb", [2, 4])
+def test_async_block_waves(mcx, oracle, cfg1, cfg2, wpb):
+    # several wavefronts per block, each with its own stash, sharing the
+    # block's LDS tables and tally sums: same integers, digests and counters
+    for d, ref in (cfg1, cfg2):
+        P = mcx.Problem(d)
+        for decomp in ("fused", "split"):
+            dg = _digest(mcx, d["n_histories"])
+            P.run(sched="async", decomp=decomp, async_block_waves=wpb, digest=dg)
+            assert np.array_equal(P.tallies(), ref["tally"]), decomp
+            _check_counts(P.counters(), ref["counts"])
+            assert np.array_equal(_digest_np(dg, mcx), ref["digest"])
+            assert P.counters()["block_threads"] in (64, 128, 256)
+            P.run(sched="async", decomp=decomp, async_block_waves=wpb, force_spill=3, stash_links=6)
+            assert np.array_equal(P.tallies(), ref["tally"]), (decomp, "spills")
+            assert P.counters()["spills"] > 0
+    # an energy tally summed in LDS by the whole block
+    dc = inputs.with_time_bins(inputs.pincell_ce(n_ebins=400, n_histories=500), 8, 3e-7, speed_coef=1.383e6)
+    refc = oracle.run(dc)
+    Q = mcx.Problem(dc)
+    for decomp in ("fused", "split"):
+        Q.run(sched="async", decomp=decomp, async_block_waves=wpb, tally_path="lds")
+        assert np.array_equal(Q.tallies(), refc["tally"]), decomp
+    # pass B sums shared by the block; a batch
+    d = inputs.lattice_mg(n_histories=3000)
+    w = np.random.default_rng(5).normal(size=inputs.n_bins(d))
+    refb = oracle.backward(d, w)
+    R = mcx.Problem(d)
+    R.run(sched="async", async_block_waves=wpb)
+    gt, gs = R.backward(w, sched="async", async_block_waves=wpb)
+    assert np.array_equal(gt, refb["grad_sigma_t"]) and np.array_equal(gs, refb["grad_sigma_s"])
+    probs = inputs.cfg5_batch(n_problems=10, hist_scale=0.02)
+    B = mcx.Problem(probs)
+    B.run(sched="async", async_block_waves=wpb)
+    for k, pd in enumerate(probs):
+        assert np.array_equal(B.tallies(k), oracle.run(pd)["tally"]), k
+    with pytest.raises(mcx.McxError):
+        B.run(sched="async", async_block_waves=3)
