@@ -352,6 +352,7 @@ typedef struct {
     double t0, v, tw;
     int32_t tk;
     int64_t nbase;
+    double wt;                /* the particle's weight (1 in analog runs)      */
 } orc_acc;
 
 static void orc_score_bin(const orc_problem *p, orc_acc *acc, int64_t bin, double len)
@@ -394,21 +395,21 @@ static int32_t orc_time_bin(double t, double dt, int32_t n)
 static void orc_score_piece(const orc_problem *p, orc_acc *acc, int64_t bin, double a, double b)
 {
     if (p->n_tbins <= 0) {
-        orc_score_bin(p, acc, bin, b - a);
+        orc_score_bin(p, acc, bin, (b - a) * acc->wt);
         return;
     }
     for (;;) {
         int32_t k = acc->tk;
         if (k + 1 >= p->n_tbins) {
-            orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, b - a);
+            orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, (b - a) * acc->wt);
             return;
         }
         double se = (((double)(k + 1) * acc->tw) - acc->t0) * acc->v;
         if (se >= b) {
-            orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, b - a);
+            orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, (b - a) * acc->wt);
             return;
         }
-        orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, se - a);
+        orc_score_bin(p, acc, (int64_t)k * acc->nbase + bin, (se - a) * acc->wt);
         a = se;
         acc->tk = k + 1;
     }
@@ -585,6 +586,7 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                          : (int64_t)p->n_ebins;
     }
     acc->hq = 0;
+    acc->wt = 1.0;
     acc->G = 0.0;
     acc->L = 0.0;
     acc->nfl = 0;
@@ -657,7 +659,10 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
             double c4 = orc_uniform(seed, pid, h, st32, 4, stream);
             if (p->energy_mode == 0) {
                 double ss = p->sigma_s[m * p->n_grp + g];
-                if (!((c1 * sigma_t) < ss)) {
+                if (p->implicit_capture) {
+                    /* implicit capture: no absorption, the weight carries it */
+                    acc->wt = acc->wt * (ss / sigma_t);
+                } else if (!((c1 * sigma_t) < ss)) {
                     fate = ORC_FATE_ABSORB;
                     cnt->absorbs += 1;
                     if (acc->mode == 2) gr->SA[m * p->n_grp + g] += orc_qs(Gh, gr->scale);
@@ -693,7 +698,9 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                     if (target < xs.cum[s]) { sp = s; break; }
                 }
                 double sa = xs.sa[sp], ss = xs.ss[sp];
-                if (!((c2 * (sa + ss)) < ss)) {
+                if (p->implicit_capture) {
+                    acc->wt = acc->wt * (ss / (sa + ss));
+                } else if (!((c2 * (sa + ss)) < ss)) {
                     fate = ORC_FATE_ABSORB;
                     cnt->absorbs += 1;
                     break;
@@ -706,6 +713,17 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                     break;
                 }
                 e = enew;
+            }
+            /* closeout: weight roulette below the cutoff (slot 5) */
+            if (p->implicit_capture && acc->wt < p->w_cutoff) {
+                double c5 = orc_uniform(seed, pid, h, st32, 5, stream);
+                if ((c5 * p->w_survival) < acc->wt) {
+                    acc->wt = p->w_survival;
+                } else {
+                    fate = ORC_FATE_ROULETTE;
+                    cnt->roulettes += 1;
+                    break;
+                }
             }
         } else {
             /* surface crossing: snap to the plane, then leak, reflect or
@@ -856,6 +874,7 @@ int orc_eigen(const orc_problem *p, uint64_t N, int32_t n_cycles, int32_t n_inac
         total.absorbs += local.absorbs; total.crossings += local.crossings; total.leaks += local.leaks;
         total.reflections += local.reflections; total.cutoffs += local.cutoffs; total.killed += local.killed;
         total.pieces += local.pieces; total.fissions += local.fissions; total.sites += local.sites;
+        total.roulettes += local.roulettes;
         total.qsum = q_before + acc.qsum_total;
         if (acc.overflow || total.qsum < q_before || total.qsum >= 0x8000000000000000ull) total.overflow = 1;
         /* the bank: each history's neutrons in history order */
@@ -925,6 +944,7 @@ void orc_tally_segment(const orc_problem *p, const double pos[3], const double d
     orc_acc acc;
     memset(&acc, 0, sizeof acc);
     acc.mode = 3;
+    acc.wt = 1.0;
     acc.dtally = out;
     acc.cnt = &local;
     orc_problem q = *p;           /* the mesh walk alone, without time bins */

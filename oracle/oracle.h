@@ -73,10 +73,19 @@ typedef struct {
        collision site.  chi [M*G]: cumulative fission spectrum per material.
        Fixed-source runs ignore fission (it is one kind of absorption). */
     const double *sigma_f, *nu, *chi;
+    /* non-analog weights (the closeout of a collision): with implicit
+       capture a collision never absorbs, the particle scatters with its
+       weight times the scattering probability (Sigma_s / Sigma_t, or the
+       chosen species' sigma_s / (sigma_a + sigma_s)); then, if the weight is
+       below w_cutoff, Russian roulette (slot 5) keeps it with probability
+       w / w_survival at weight w_survival, else the history ends (fate
+       ROULETTE).  Every tally piece scores length times weight. */
+    int32_t implicit_capture;
+    double w_cutoff, w_survival;
 } orc_problem;
 
 /* what a history ended with */
-enum { ORC_FATE_LEAK = 0, ORC_FATE_ABSORB = 1, ORC_FATE_CUTOFF = 2, ORC_FATE_KILLED = 3 };
+enum { ORC_FATE_LEAK = 0, ORC_FATE_ABSORB = 1, ORC_FATE_CUTOFF = 2, ORC_FATE_KILLED = 3, ORC_FATE_ROULETTE = 4 };
 
 typedef struct {              /* one record per history                    */
     int64_t qsum;             /* sum of its fixed-point tally contributions */
@@ -91,6 +100,7 @@ typedef struct {              /* totals over a run (scheduler invariant)   */
     uint64_t leaks, reflections, cutoffs, killed, pieces, qsum;
     uint64_t overflow;        /* 1 if the total of all q reached 2^63       */
     uint64_t fissions, sites; /* k-eigenvalue runs: fissions, neutrons banked */
+    uint64_t roulettes;       /* histories ended by weight roulette          */
 } orc_counts;
 
 /* primitives, exposed for tests */

@@ -49,6 +49,7 @@ class OrcProblem(C.Structure):
         ("tally_scale_log2", C.c_int32), ("problem_id", C.c_uint32), ("seed", C.c_uint64),
         ("max_steps", C.c_int64), ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p),
         ("speed_coef", C.c_double), ("sigma_f", C.c_void_p), ("nu", C.c_void_p), ("chi", C.c_void_p),
+        ("implicit_capture", C.c_int32), ("w_cutoff", C.c_double), ("w_survival", C.c_double),
     ]
 
 
@@ -60,7 +61,7 @@ class OrcDigest(C.Structure):
 DIGEST_DTYPE = np.dtype([("qsum", "<i8"), ("flights", "<u4"), ("collisions", "<u4"),
                          ("fate", "<u4"), ("pad", "<u4")])
 COUNT_NAMES = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks",
-               "reflections", "cutoffs", "killed", "pieces", "qsum", "overflow", "fissions", "sites"]
+               "reflections", "cutoffs", "killed", "pieces", "qsum", "overflow", "fissions", "sites", "roulettes"]
 
 
 class OrcCounts(C.Structure):
@@ -183,6 +184,9 @@ class Problem:
         if s.n_tbins > 0 and d["energy_mode"] == 0:
             s.speed = arr("speed", np.float64)
         s.speed_coef = float(d.get("speed_coef", 0.0))
+        s.implicit_capture = int(d.get("implicit_capture", 0))
+        s.w_cutoff = float(d.get("w_cutoff", 0.0))
+        s.w_survival = float(d.get("w_survival", 0.0))
         if d.get("sigma_f") is not None:
             s.sigma_f = arr("sigma_f", np.float64)
             s.nu = arr("nu", np.float64)
@@ -316,6 +320,8 @@ def grads_from_sums(d: dict, SL, SA, SS, s: int, n: int):
 def backward(d: dict, w: np.ndarray, threads: int | None = None):
     """Score-function vector-Jacobian product for the normalised tally
     T = raw * 2^-S / N: returns (grad Sigma_t, grad Sigma_s), each [M*G]."""
+    if d.get("implicit_capture", 0):
+        raise ValueError("the score-function backward needs analog histories (no implicit capture)")
     G, U = replay_a(d, w, threads=threads)
     s = grad_scale(U)
     SL, SA, SS = replay_b(d, G, s, threads=threads)
@@ -331,6 +337,8 @@ def eigen(d: dict, n_particles: int, n_cycles: int, n_inactive: int, bank_cap: i
     P = Problem(d)
     if d.get("sigma_f") is None:
         raise ValueError("k-eigenvalue runs need fission data")
+    if d.get("implicit_capture", 0):
+        raise ValueError("k-eigenvalue runs are analog (no implicit capture)")
     L = lib()
     tally = np.zeros(P.n_bins, dtype=np.int64)
     k = np.zeros(n_cycles, dtype=np.float64)

@@ -101,6 +101,7 @@ def _base(n_histories: int, seed: int, problem_id: int) -> dict:
         tally_kind=TALLY_MESH, mesh_n=_i32([1, 1, 1]), mesh_x=_f64([0, 1]), mesh_y=_f64([0, 1]),
         mesh_z=_f64([0, 1]), n_ebins=0, e_edges=_f64([0.0, 1.0]), tally_scale_log2=32,
         n_tbins=0, t_max=0.0, speed=_f64([1.0]), speed_coef=0.0,
+        implicit_capture=0, w_cutoff=0.0, w_survival=0.0,
     )
 
 
@@ -327,6 +328,17 @@ def with_time_bins(d: dict, n_tbins: int, t_max: float, speed=None, speed_coef: 
         g = np.arange(int(d["n_grp"]), dtype=np.float64)
         d["speed"] = _f64(speed if speed is not None else 10.0 ** (-0.5 * g))
     d["speed_coef"] = float(speed_coef)
+    return d
+
+
+def with_implicit_capture(d: dict, w_cutoff: float = 0.25, w_survival: float = 0.5) -> dict:
+    """A copy of problem d with non-analog weights: implicit capture (every
+    collision scatters, the weight carries the absorption) and weight roulette
+    below w_cutoff to weight w_survival."""
+    d = dict(d)
+    d["implicit_capture"] = 1
+    d["w_cutoff"] = float(w_cutoff)
+    d["w_survival"] = float(w_survival)
     return d
 
 
