@@ -70,7 +70,7 @@ enum { MCX_TALLY_MESH = 0, MCX_TALLY_ENERGY = 1 };
 typedef enum { MCX_SCHED_NAIVE = 0, MCX_SCHED_STACK = 1, MCX_SCHED_ASYNC = 2 } mcx_sched;
 typedef enum { MCX_DECOMP_FUSED = 0, MCX_DECOMP_SPLIT = 1 } mcx_decomp;
 typedef enum { MCX_LOOKUP_BINARY = 0, MCX_LOOKUP_HASH = 1 } mcx_lookup;
-enum { MCX_FATE_LEAK = 0, MCX_FATE_ABSORB = 1, MCX_FATE_CUTOFF = 2, MCX_FATE_KILLED = 3 };
+enum { MCX_FATE_LEAK = 0, MCX_FATE_ABSORB = 1, MCX_FATE_CUTOFF = 2, MCX_FATE_KILLED = 3, MCX_FATE_ROULETTE = 4 };
 
 /* One fixed-source problem.  All arrays are host memory; mcx_create_problem
  * deep-copies them, so the caller may free them afterwards.
@@ -146,7 +146,7 @@ typedef struct {
      * CUTOFF, counted in cutoffs); a track piece is split where the
      * particle's time passes a bin edge.  Bins are laid out [time bin][bins
      * without time].  n_tbins = 0: no time dimension (the other three
-     * fields are ignored).  Every problem of a handle has time bins or none. */
+     * fields are ignored). */
     int32_t n_tbins;
     double t_max;
     const double *speed;
@@ -159,6 +159,18 @@ typedef struct {
      * non-decreasing, ending at 1.0).  NULL sigma_f: no fission data.  Other
      * runs treat a fission as an absorption. */
     const double *sigma_f, *nu, *chi;
+    /* Non-analog weights (the closeout of the paper's decomposed transport
+     * loop, Sec. 4: weights and weight windows).  implicit_capture = 1: a
+     * collision never absorbs; the particle scatters with its weight times
+     * the scattering probability (sigma_s / sigma_t, or the chosen species'
+     * sigma_s / (sigma_a + sigma_s)); then, if the weight is below w_cutoff,
+     * Russian roulette (random-number slot 5) keeps it with probability
+     * w / w_survival at weight w_survival, else the history ends (fate
+     * ROULETTE).  Tally pieces score length times weight.  Needs
+     * 0 <= w_cutoff <= w_survival, w_survival > 0.  Forward runs only (the
+     * backward and k-eigenvalue runs take analog problems). */
+    int32_t implicit_capture;
+    double w_cutoff, w_survival;
 } mcx_problem_desc;
 
 /* Options of one run.  Zero-initialise and set what you need; zero means the
@@ -242,6 +254,7 @@ typedef struct {
     int32_t pad;
     uint64_t fissions;        /* k-eigenvalue runs: fissions (all cycles)       */
     uint64_t sites;           /*   and neutrons banked                          */
+    uint64_t roulettes;       /* histories ended by weight roulette             */
 } mcx_counters_t;
 
 /* k-eigenvalue power iteration (the multigroup workload of Sec. 4 of the
@@ -294,7 +307,8 @@ mcx_status mcx_tallies(mcx_problem_t p, int32_t problem, int64_t *out, int64_t n
  * and scatters per (material, group), in int64 fixed point at an adaptive
  * power-of-two scale).  problem = -1 covers all problems of a batch:
  * dL_dT is then the concatenation of every problem's bins and the gradients
- * the concatenation of every problem's n_mat*n_grp entries.  Multigroup only.
+ * the concatenation of every problem's n_mat*n_grp entries.  Multigroup, analog
+ * (no implicit capture) problems only.
  * opts selects the scheduler and tuning for the replays (accumulate, range
  * and digest fields are ignored). */
 mcx_status mcx_backward(mcx_problem_t p, int32_t problem, const double *dL_dT, double *grad_sigma_t,

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libmcx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["api.cpp", "sched_naive.hip", "sched_stack.hip", "sched_async.hip",
-           "sched_naive_time.hip", "sched_stack_time.hip", "sched_async_time.hip", "eigen.hip"]
+           "sched_naive_ext.hip", "sched_stack_ext.hip", "sched_async_ext.hip", "eigen.hip"]
 ARCH = os.environ.get("MCX_OFFLOAD_ARCH", "gfx950")
 
 

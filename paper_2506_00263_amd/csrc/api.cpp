@@ -340,6 +340,11 @@ static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int
         }
         hp.fission = true;
     }
+    if (d.implicit_capture != 0 && d.implicit_capture != 1)
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: implicit_capture must be 0 or 1", k);
+    if (d.implicit_capture &&
+        !(d.w_cutoff >= 0.0 && d.w_survival > 0.0 && d.w_cutoff <= d.w_survival && std::isfinite(d.w_survival)))
+        return fail(h, MCX_E_INVALID_ARG, "problem %d: need 0 <= w_cutoff <= w_survival, w_survival > 0", k);
     hp.nbase = hp.n_bins;
     hp.speed = {1.0};
     if (d.n_tbins < 0 || d.n_tbins > (1 << 20))
@@ -549,6 +554,9 @@ static mcx_status upload(mcx_problem_t h)
         P.nbase = hp.nbase;
         P.n_bins = hp.n_bins;
         P.speed = (const double *)(base + o.speed);
+        P.implicit = d.implicit_capture ? 1 : 0;
+        P.w_cut = d.implicit_capture ? d.w_cutoff : 0.0;
+        P.w_surv = d.implicit_capture ? d.w_survival : 1.0;
     }
     return MCX_OK;
 }
@@ -570,8 +578,6 @@ extern "C" mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t 
         for (int k = 1; k < n_problems; ++k)
             if (descs[k].geometry != h->geom || descs[k].energy_mode != h->emode || descs[k].tally_kind != h->tally_kind)
                 s = fail(h, MCX_E_INVALID_ARG, "problems of one handle must share geometry, energy mode and tally kind");
-            else if ((descs[k].n_tbins > 0) != (descs[0].n_tbins > 0))
-                s = fail(h, MCX_E_INVALID_ARG, "problems of one handle must all have time bins or none");
     }
     if (s == MCX_OK) {
         hipError_t e = hipGetDevice(&h->device);
@@ -769,7 +775,9 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     a.emode = h->emode;
     a.mode = mode;
     a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
-    a.time = h->pd[0].n_tbins > 0 ? 1 : 0;
+    a.ext = 0;
+    for (int k = 0; k < h->n; ++k)
+        if (h->pd[k].n_tbins > 0 || h->pd[k].implicit) a.ext = 1;
     a.lacc_words = 0;
     if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
     if (path == MCX_TALLY_PATH_LDS) a.lacc_words = (int)h->hp[0].n_bins;
@@ -841,6 +849,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     c.refills = tot[C_REFILLS];
     c.make_work = tot[C_MAKE_WORK];
     c.fissions = tot[C_FISSIONS];
+    c.roulettes = tot[C_ROULETTES];
     c.rounds = st.rounds;
     c.launches = st.launches;
     c.kernel_ms = tm.total_ms();
@@ -927,6 +936,7 @@ extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, c
     const HostProblem &hp = h->hp[0];
     if (!hp.fission) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs need fission data");
     if (hp.d.n_tbins > 0) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs take no time bins");
+    if (hp.d.implicit_capture) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs are analog (no implicit capture)");
     const uint64_t N = eig->n_particles;
     if (N < 1 || N > (1ull << 30)) return fail(h, MCX_E_INVALID_ARG, "n_particles must be 1..2^30");
     if (eig->n_cycles < 1 || eig->n_inactive < 0 || eig->n_inactive > eig->n_cycles)
@@ -992,6 +1002,7 @@ extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, c
         sum.lane_slots += pc.lane_slots; sum.dispatches += pc.dispatches; sum.spills += pc.spills;
         sum.refills += pc.refills; sum.make_work += pc.make_work; sum.rounds += pc.rounds;
         sum.launches += pc.launches; sum.kernel_ms += pc.kernel_ms; sum.fissions += pc.fissions;
+        sum.roulettes += pc.roulettes;
         sum.grid_blocks = pc.grid_blocks; sum.block_threads = pc.block_threads; sum.lds_bytes = pc.lds_bytes;
         qsum += pc.qsum;
         // the bank: each history's neutrons, in history order
@@ -1051,6 +1062,9 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
 {
     if (!h || !opts || !dL_dT || !grad_sigma_t || !grad_sigma_s) return MCX_E_INVALID_ARG;
     if (h->emode != MCX_MG) return fail(h, MCX_E_INVALID_ARG, "the backward needs multigroup problems");
+    for (int k = 0; k < h->n; ++k)
+        if (h->hp[k].d.implicit_capture)
+            return fail(h, MCX_E_INVALID_ARG, "the backward needs analog histories (no implicit capture)");
     if (problem < -1 || problem >= h->n) return fail(h, MCX_E_INVALID_ARG, "bad problem index");
     if (!h->have_forward) return fail(h, MCX_E_STATE, "mcx_backward needs a successful forward run first");
     mcx_run_opts o = *opts;

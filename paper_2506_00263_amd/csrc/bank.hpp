@@ -10,20 +10,21 @@
 namespace mcx {
 
 // Which fields a particle carries for an event program.
-template <int EMODE, int MODE, int SPLIT, int TIME>
+template <int EMODE, int MODE, int SPLIT, int EXT>
 struct Layout {
     static constexpr bool CE = EMODE == EMODE_CE;
     static constexpr bool SIG = SPLIT != 0;
     static constexpr bool GG = MODE != MODE_FWD;
     static constexpr bool LL = MODE == MODE_REPLAY_A;
-    static constexpr bool TM = TIME != 0;
+    static constexpr bool TM = EXT != 0;                // particle time and weight
     static constexpr bool DIGEST = MODE == MODE_FWD;   // present only when digests are requested
     static constexpr int D_E = 6;
     static constexpr int D_SIG = D_E + (CE ? 1 : 0);
     static constexpr int D_G = D_SIG + (SIG ? 1 : 0);
     static constexpr int D_L = D_G + (GG ? 1 : 0);
     static constexpr int D_T = D_L + (LL ? 1 : 0);
-    static constexpr int D_HQ = D_T + (TM ? 1 : 0);
+    static constexpr int D_W = D_T + (TM ? 1 : 0);
+    static constexpr int D_HQ = D_W + (TM ? 1 : 0);
     static constexpr int ND_CORE = D_HQ;                // without the digest field
     static constexpr int NU_CORE = 4;                   // hid, step, gc, prob (+ ncoll)
     __host__ __device__ static int nd(bool dig) { return ND_CORE + ((DIGEST && dig) ? 1 : 0); }
@@ -79,7 +80,10 @@ __device__ __forceinline__ void put(const R &s, long i, const Part &p, bool dig)
     if (LAY::SIG) *dptr(s, i, LAY::D_SIG) = p.sigt;
     if (LAY::GG) *dptr(s, i, LAY::D_G) = p.G;
     if (LAY::LL) *dptr(s, i, LAY::D_L) = p.L;
-    if (LAY::TM) *dptr(s, i, LAY::D_T) = p.t;
+    if (LAY::TM) {
+        *dptr(s, i, LAY::D_T) = p.t;
+        *dptr(s, i, LAY::D_W) = p.wgt;
+    }
     *uptr(s, i, 0) = p.hid;
     *uptr(s, i, 1) = p.step;
     *uptr(s, i, 2) = p.gc;
@@ -104,6 +108,7 @@ __device__ __forceinline__ void get(const R &s, long i, Part &p, bool dig)
     p.G = LAY::GG ? *dptr(s, i, LAY::D_G) : 0.0;
     p.L = LAY::LL ? *dptr(s, i, LAY::D_L) : 0.0;
     p.t = LAY::TM ? *dptr(s, i, LAY::D_T) : 0.0;
+    p.wgt = LAY::TM ? *dptr(s, i, LAY::D_W) : 1.0;
     p.hid = *uptr(s, i, 0);
     p.step = *uptr(s, i, 1);
     p.gc = *uptr(s, i, 2);

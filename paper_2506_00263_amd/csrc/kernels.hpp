@@ -1,7 +1,7 @@
 // Host-visible launch interface of the scheduler kernels (kernels in
 // sched_naive.hpp, sched_stack.hpp and sched_async.hpp; each is built once
-// for runs without time bins, sched_*.hip, and once for runs with them,
-// sched_*_time.hip).
+// for particles without extended state, sched_*.hip, and once for particles
+// that carry time and weight, sched_*_ext.hip).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -63,7 +63,8 @@ struct LaunchArgs {
     RunCtl *ctl;                           // device control block
     void *digest;                          // device Digest array or null
     int geom, emode, mode, split;
-    int time;                              // 1: the problems have time-binned tallies
+    int ext;                               // 1: particles carry time and weight (time bins or
+                                           //    implicit capture in some problem)
     int lacc_words;                        // pass B per-block sums in LDS (single problem), 0 = none
     int tl_bytes;                          // single problem: packed tables copied to LDS; 0 = read globally
     hipStream_t stream;
@@ -104,10 +105,10 @@ hipError_t launch_naive(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm);
 hipError_t launch_stack(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
                         unsigned int *host_flag_pinned);
 hipError_t launch_async(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm);
-hipError_t launch_naive_time(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm);
-hipError_t launch_stack_time(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
+hipError_t launch_naive_ext(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm);
+hipError_t launch_stack_ext(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
                              unsigned int *host_flag_pinned);
-hipError_t launch_async_time(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm);
+hipError_t launch_async_ext(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm);
 
 // k-eigenvalue banking between cycles (eigen.hip).  tsum holds
 // eigen_tiles(n) words; totals are written to device memory.

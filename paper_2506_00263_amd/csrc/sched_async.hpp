@@ -332,10 +332,10 @@ struct AsyncWave {
 // stash; the block shares one LDS copy of the tables and one set of LDS
 // tally sums, which one-wavefront blocks would each hold (the occupancy cost
 // the paper attributes to per-warp stashes, Sec. 5.2).
-template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int TIME>
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2))) async_kernel(AsyncArgs A)
 {
-    using LAY = Layout<EMODE, MODE, SPLIT, TIME>;
+    using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
     extern __shared__ __attribute__((aligned(16))) char lds[];
     const bool dig = A.digest != nullptr;
@@ -472,7 +472,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH 
         uint32_t out = 0;
         if (act) {
             const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
-            ne = run_event<GEOM, EMODE, MODE, SPLIT, TIME>(ev, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
+            ne = run_event<GEOM, EMODE, MODE, SPLIT, EXT>(ev, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
         }
         wc.dispatch(act);
         wc.outcomes(act, out);
@@ -504,10 +504,10 @@ static __global__ void arena_init(AsyncArgs A, unsigned int waves)
     }
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int TIME>
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
 static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
-    using LAY = Layout<EMODE, MODE, SPLIT, TIME>;
+    using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
     const bool dig = a.digest != nullptr;
     // one partial link per event plus one: a stash with no free link then
@@ -520,7 +520,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     const int tl_bytes = BATCH ? 0 : a.tl_bytes;
     int wpb = a.async_block_waves > 0 ? a.async_block_waves : ASYNC_BLOCK_WAVES;
     if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
-    auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, TIME>;
+    auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>;
     // fewer wavefronts per block when the block's LDS would not fit
     size_t lds = 0;
     int per_cu = 0;
@@ -579,36 +579,36 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     return hipGetLastError();
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, int TIME>
+template <int GEOM, int EMODE, int MODE, int SPLIT, int EXT>
 static hipError_t async_b(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
-    return (a.n_probs > 1 || a.tl_bytes == 0) ? async_t<GEOM, EMODE, MODE, SPLIT, true, TIME>(a, ws, st, tm)
-                                              : async_t<GEOM, EMODE, MODE, SPLIT, false, TIME>(a, ws, st, tm);
+    return (a.n_probs > 1 || a.tl_bytes == 0) ? async_t<GEOM, EMODE, MODE, SPLIT, true, EXT>(a, ws, st, tm)
+                                              : async_t<GEOM, EMODE, MODE, SPLIT, false, EXT>(a, ws, st, tm);
 }
 
-template <int GEOM, int EMODE, int MODE, int TIME>
+template <int GEOM, int EMODE, int MODE, int EXT>
 static hipError_t async_s(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
-    return a.split ? async_b<GEOM, EMODE, MODE, 1, TIME>(a, ws, st, tm)
-                   : async_b<GEOM, EMODE, MODE, 0, TIME>(a, ws, st, tm);
+    return a.split ? async_b<GEOM, EMODE, MODE, 1, EXT>(a, ws, st, tm)
+                   : async_b<GEOM, EMODE, MODE, 0, EXT>(a, ws, st, tm);
 }
 
 // every event program of one time mode (runs with or without time bins)
-template <int TIME>
+template <int EXT>
 static hipError_t launch_async_tm(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
     if (a.emode == EMODE_CE) {
         if (a.geom != GEOM_LATTICE || a.mode != MODE_FWD) return hipErrorInvalidValue;
-        return async_s<GEOM_LATTICE, EMODE_CE, MODE_FWD, TIME>(a, ws, st, tm);
+        return async_s<GEOM_LATTICE, EMODE_CE, MODE_FWD, EXT>(a, ws, st, tm);
     }
     if (a.geom == GEOM_BOX) {
-        if (a.mode == MODE_FWD) return async_s<GEOM_BOX, EMODE_MG, MODE_FWD, TIME>(a, ws, st, tm);
-        if (a.mode == MODE_REPLAY_A) return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_A, TIME>(a, ws, st, tm);
-        return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_B, TIME>(a, ws, st, tm);
+        if (a.mode == MODE_FWD) return async_s<GEOM_BOX, EMODE_MG, MODE_FWD, EXT>(a, ws, st, tm);
+        if (a.mode == MODE_REPLAY_A) return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_A, EXT>(a, ws, st, tm);
+        return async_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_B, EXT>(a, ws, st, tm);
     }
-    if (a.mode == MODE_FWD) return async_s<GEOM_LATTICE, EMODE_MG, MODE_FWD, TIME>(a, ws, st, tm);
-    if (a.mode == MODE_REPLAY_A) return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A, TIME>(a, ws, st, tm);
-    return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B, TIME>(a, ws, st, tm);
+    if (a.mode == MODE_FWD) return async_s<GEOM_LATTICE, EMODE_MG, MODE_FWD, EXT>(a, ws, st, tm);
+    if (a.mode == MODE_REPLAY_A) return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A, EXT>(a, ws, st, tm);
+    return async_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B, EXT>(a, ws, st, tm);
 }
 
 }  // namespace mcx

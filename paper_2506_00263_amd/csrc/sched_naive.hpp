@@ -9,7 +9,7 @@
 
 namespace mcx {
 
-template <int GEOM, int EMODE, int MODE, bool BATCH, int TIME>
+template <int GEOM, int EMODE, int MODE, bool BATCH, int EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) naive_kernel(const ProbDev *__restrict__ probs, int n_probs,
                                                     const unsigned long long *__restrict__ prefix,
                                                     unsigned long long total, RunCtl *ctl, Digest *digest,
@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
             uint32_t out = 0;
             if (alive) {
                 const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
-                ev = ev_step<GEOM, EMODE, MODE, TIME>(P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
+                ev = ev_step<GEOM, EMODE, MODE, EXT>(P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
             }
             wc.dispatch(alive);
             wc.outcomes(alive, out);
@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
     }
 }
 
-template <int GEOM, int EMODE, int MODE, bool BATCH, int TIME>
+template <int GEOM, int EMODE, int MODE, bool BATCH, int EXT>
 static hipError_t launch_naive_t(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
 {
     int bs = a.block_size > 0 ? a.block_size : 256;
@@ -76,36 +76,36 @@ static hipError_t launch_naive_t(const LaunchArgs &a, LaunchStats &st, LaunchTim
     st.block_threads = bs;
     st.lds_bytes = (int)lds;
     tm.begin();
-    hipLaunchKernelGGL((naive_kernel<GEOM, EMODE, MODE, BATCH, TIME>), dim3((unsigned)blocks), dim3(bs), lds, a.stream,
+    hipLaunchKernelGGL((naive_kernel<GEOM, EMODE, MODE, BATCH, EXT>), dim3((unsigned)blocks), dim3(bs), lds, a.stream,
                        a.probs, a.n_probs, a.prefix, a.total, a.ctl, (Digest *)a.digest, a.lacc_words);
     tm.end();
     st.launches += 1;
     return hipGetLastError();
 }
 
-template <int GEOM, int EMODE, int MODE, int TIME>
+template <int GEOM, int EMODE, int MODE, int EXT>
 static hipError_t naive_b(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
 {
-    return (a.n_probs > 1 || a.tl_bytes == 0) ? launch_naive_t<GEOM, EMODE, MODE, true, TIME>(a, st, tm)
-                                              : launch_naive_t<GEOM, EMODE, MODE, false, TIME>(a, st, tm);
+    return (a.n_probs > 1 || a.tl_bytes == 0) ? launch_naive_t<GEOM, EMODE, MODE, true, EXT>(a, st, tm)
+                                              : launch_naive_t<GEOM, EMODE, MODE, false, EXT>(a, st, tm);
 }
 
 // every event program of one time mode (runs with or without time bins)
-template <int TIME>
+template <int EXT>
 static hipError_t launch_naive_tm(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
 {
     if (a.emode == EMODE_CE) {
         if (a.geom != GEOM_LATTICE || a.mode != MODE_FWD) return hipErrorInvalidValue;
-        return naive_b<GEOM_LATTICE, EMODE_CE, MODE_FWD, TIME>(a, st, tm);
+        return naive_b<GEOM_LATTICE, EMODE_CE, MODE_FWD, EXT>(a, st, tm);
     }
     if (a.geom == GEOM_BOX) {
-        if (a.mode == MODE_FWD) return naive_b<GEOM_BOX, EMODE_MG, MODE_FWD, TIME>(a, st, tm);
-        if (a.mode == MODE_REPLAY_A) return naive_b<GEOM_BOX, EMODE_MG, MODE_REPLAY_A, TIME>(a, st, tm);
-        return naive_b<GEOM_BOX, EMODE_MG, MODE_REPLAY_B, TIME>(a, st, tm);
+        if (a.mode == MODE_FWD) return naive_b<GEOM_BOX, EMODE_MG, MODE_FWD, EXT>(a, st, tm);
+        if (a.mode == MODE_REPLAY_A) return naive_b<GEOM_BOX, EMODE_MG, MODE_REPLAY_A, EXT>(a, st, tm);
+        return naive_b<GEOM_BOX, EMODE_MG, MODE_REPLAY_B, EXT>(a, st, tm);
     }
-    if (a.mode == MODE_FWD) return naive_b<GEOM_LATTICE, EMODE_MG, MODE_FWD, TIME>(a, st, tm);
-    if (a.mode == MODE_REPLAY_A) return naive_b<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A, TIME>(a, st, tm);
-    return naive_b<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B, TIME>(a, st, tm);
+    if (a.mode == MODE_FWD) return naive_b<GEOM_LATTICE, EMODE_MG, MODE_FWD, EXT>(a, st, tm);
+    if (a.mode == MODE_REPLAY_A) return naive_b<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A, EXT>(a, st, tm);
+    return naive_b<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B, EXT>(a, st, tm);
 }
 
 }  // namespace mcx

@@ -142,10 +142,10 @@ __device__ __forceinline__ unsigned int event_chunks(const StackArgs &A, int set
     return c;
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int TIME>
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH || EMODE == EMODE_CE) ? 3 : 2))) stack_round(StackArgs A, int round)
 {
-    using LAY = Layout<EMODE, MODE, SPLIT, TIME>;
+    using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
     extern __shared__ __attribute__((aligned(16))) unsigned long long lacc[];
     char *tl = (char *)lacc + tabs_lds_offset((size_t)A.lacc_words * 8);
@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH
                 uint32_t out = 0;
                 if (live) {
                     const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
-                    ne = run_event<GEOM, EMODE, MODE, SPLIT, TIME>(cur, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
+                    ne = run_event<GEOM, EMODE, MODE, SPLIT, EXT>(cur, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
                 }
                 wc.dispatch(live);
                 wc.outcomes(live, out);
@@ -273,16 +273,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH
     }
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int TIME>
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
 static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm, unsigned int *flag)
 {
-    using LAY = Layout<EMODE, MODE, SPLIT, TIME>;
+    using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
     const bool dig = a.digest != nullptr;
     const int block = 256;
     // every block of a round is resident at once: the grid is the resident
     // capacity (or the requested waves per CU, if fewer)
-    auto kern = stack_round<GEOM, EMODE, MODE, SPLIT, BATCH, TIME>;
+    auto kern = stack_round<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>;
     const size_t lds_need = tabs_lds_offset((size_t)a.lacc_words * 8) + (size_t)(BATCH ? 0 : a.tl_bytes);
     int per_cu = 0;
     hipError_t oe = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, lds_need);
@@ -396,37 +396,37 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     return hipSuccess;
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, int TIME>
+template <int GEOM, int EMODE, int MODE, int SPLIT, int EXT>
 static hipError_t stack_b(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm, unsigned int *flag)
 {
-    return (a.n_probs > 1 || a.tl_bytes == 0) ? stack_t<GEOM, EMODE, MODE, SPLIT, true, TIME>(a, ws, st, tm, flag)
-                                              : stack_t<GEOM, EMODE, MODE, SPLIT, false, TIME>(a, ws, st, tm, flag);
+    return (a.n_probs > 1 || a.tl_bytes == 0) ? stack_t<GEOM, EMODE, MODE, SPLIT, true, EXT>(a, ws, st, tm, flag)
+                                              : stack_t<GEOM, EMODE, MODE, SPLIT, false, EXT>(a, ws, st, tm, flag);
 }
 
-template <int GEOM, int EMODE, int MODE, int TIME>
+template <int GEOM, int EMODE, int MODE, int EXT>
 static hipError_t stack_s(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm, unsigned int *flag)
 {
-    return a.split ? stack_b<GEOM, EMODE, MODE, 1, TIME>(a, ws, st, tm, flag)
-                   : stack_b<GEOM, EMODE, MODE, 0, TIME>(a, ws, st, tm, flag);
+    return a.split ? stack_b<GEOM, EMODE, MODE, 1, EXT>(a, ws, st, tm, flag)
+                   : stack_b<GEOM, EMODE, MODE, 0, EXT>(a, ws, st, tm, flag);
 }
 
 // every event program of one time mode (runs with or without time bins)
-template <int TIME>
+template <int EXT>
 static hipError_t launch_stack_tm(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
                                   unsigned int *flag)
 {
     if (a.emode == EMODE_CE) {
         if (a.geom != GEOM_LATTICE || a.mode != MODE_FWD) return hipErrorInvalidValue;
-        return stack_s<GEOM_LATTICE, EMODE_CE, MODE_FWD, TIME>(a, ws, st, tm, flag);
+        return stack_s<GEOM_LATTICE, EMODE_CE, MODE_FWD, EXT>(a, ws, st, tm, flag);
     }
     if (a.geom == GEOM_BOX) {
-        if (a.mode == MODE_FWD) return stack_s<GEOM_BOX, EMODE_MG, MODE_FWD, TIME>(a, ws, st, tm, flag);
-        if (a.mode == MODE_REPLAY_A) return stack_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_A, TIME>(a, ws, st, tm, flag);
-        return stack_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_B, TIME>(a, ws, st, tm, flag);
+        if (a.mode == MODE_FWD) return stack_s<GEOM_BOX, EMODE_MG, MODE_FWD, EXT>(a, ws, st, tm, flag);
+        if (a.mode == MODE_REPLAY_A) return stack_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_A, EXT>(a, ws, st, tm, flag);
+        return stack_s<GEOM_BOX, EMODE_MG, MODE_REPLAY_B, EXT>(a, ws, st, tm, flag);
     }
-    if (a.mode == MODE_FWD) return stack_s<GEOM_LATTICE, EMODE_MG, MODE_FWD, TIME>(a, ws, st, tm, flag);
-    if (a.mode == MODE_REPLAY_A) return stack_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A, TIME>(a, ws, st, tm, flag);
-    return stack_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B, TIME>(a, ws, st, tm, flag);
+    if (a.mode == MODE_FWD) return stack_s<GEOM_LATTICE, EMODE_MG, MODE_FWD, EXT>(a, ws, st, tm, flag);
+    if (a.mode == MODE_REPLAY_A) return stack_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_A, EXT>(a, ws, st, tm, flag);
+    return stack_s<GEOM_LATTICE, EMODE_MG, MODE_REPLAY_B, EXT>(a, ws, st, tm, flag);
 }
 
 }  // namespace mcx

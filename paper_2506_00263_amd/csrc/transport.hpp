@@ -30,9 +30,9 @@ enum : int { EV_STEP = 0, EV_LOOKUP = 0, EV_MOVE = 1, EV_SURFACE = 2, EV_COLLIDE
 enum : uint32_t {
     O_SOURCE = 1u << 0, O_FLIGHT = 1u << 1, O_COLL = 1u << 2, O_SCAT = 1u << 3, O_ABS = 1u << 4,
     O_CROSS = 1u << 5, O_LEAK = 1u << 6, O_REFL = 1u << 7, O_CUT = 1u << 8, O_KILL = 1u << 9,
-    O_FISS = 1u << 10
+    O_FISS = 1u << 10, O_ROUL = 1u << 11
 };
-enum : uint32_t { FATE_LEAK = 0, FATE_ABSORB = 1, FATE_CUTOFF = 2, FATE_KILLED = 3 };
+enum : uint32_t { FATE_LEAK = 0, FATE_ABSORB = 1, FATE_CUTOFF = 2, FATE_KILLED = 3, FATE_ROULETTE = 4 };
 
 struct Digest {   // same layout as mcx_digest
     long long qsum;
@@ -46,6 +46,7 @@ struct Part {
     double sigt;      // total cross section of the current flight (split events)
     double G, L;      // backward accumulators
     double t;         // particle time (time-binned tallies)
+    double wgt;       // statistical weight (non-analog runs; 1 otherwise)
     long long hq;     // this history's tally sum (digest)
     uint32_t hid;     // history index within its problem
     uint32_t step;    // flight counter (0 = source)
@@ -427,30 +428,36 @@ __device__ __forceinline__ int time_bin(double t, double dt, int n)
 }
 
 // Score the piece [a, b] of the current flight (distances from its start)
-// into bin `bin` of the tally without time.  With time bins the piece is cut
-// where the particle's time t0 + s / v passes a bin edge: the edge closing
-// bin k lies at s = ((k + 1) tw - t0) v; the last time bin takes the rest.
-template <int MODE, int TIME>
+// into bin `bin` of the tally without time; a piece scores its length times
+// the particle's weight (extended state; the weight is 1 unless the problem
+// uses implicit capture).  With time bins the piece is cut where the
+// particle's time t0 + s / v passes a bin edge: the edge closing bin k lies
+// at s = ((k + 1) tw - t0) v; the last time bin takes the rest.
+template <int MODE, int EXT>
 __device__ __forceinline__ void score_piece(const ProbDev &P, Lane &ln, Part &p, TSplit &ts, long bin, double a,
                                             double b, unsigned long long *lt)
 {
-    if (!TIME) {
+    if (!EXT) {
         score<MODE>(P, ln, p, bin, b - a, lt);
+        return;
+    }
+    if (P.n_tbins <= 0) {
+        score<MODE>(P, ln, p, bin, (b - a) * p.wgt, lt);
         return;
     }
     for (;;) {
         const int k = ts.k;
         const long kb = (long)k * P.nbase + bin;
         if (k + 1 >= P.n_tbins) {
-            score<MODE>(P, ln, p, kb, b - a, lt);
+            score<MODE>(P, ln, p, kb, (b - a) * p.wgt, lt);
             return;
         }
         double se = (((double)(k + 1) * P.tw) - ts.t0) * ts.v;
         if (se >= b) {
-            score<MODE>(P, ln, p, kb, b - a, lt);
+            score<MODE>(P, ln, p, kb, (b - a) * p.wgt, lt);
             return;
         }
-        score<MODE>(P, ln, p, kb, se - a, lt);
+        score<MODE>(P, ln, p, kb, (se - a) * p.wgt, lt);
         a = se;
         ts.k = k + 1;
     }
@@ -468,7 +475,7 @@ __device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, do
 // Track-length mesh tally of one flight of length d from the current
 // position: visit the mesh cells the segment crosses; every crossing
 // parameter is measured from the flight start; ties go x, y, z.
-template <int MODE, int TIME, class TB>
+template <int MODE, int EXT, class TB>
 __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &ln, Part &p, double d, int g,
                                           TSplit &ts, unsigned long long *lt)
 {
@@ -488,7 +495,7 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &l
         if (t2 < tm) { tm = t2; a = 2; }
         double tend = (tm < d) ? tm : d;
         long bin = (((long)g * n2 + i2) * n1 + i1) * n0 + i0;
-        score_piece<MODE, TIME>(P, ln, p, ts, bin, tprev, tend, lt);
+        score_piece<MODE, EXT>(P, ln, p, ts, bin, tprev, tend, lt);
         if (tm >= d) break;
         if (a == 0) {
             i0 += (p.u > 0.0) ? 1 : -1;
@@ -523,7 +530,7 @@ __device__ __forceinline__ void pass_b_add(const ProbDev &P, const EvCtx &cx, in
 }
 
 // Score a flight of length d that started at the particle's position.
-template <int EMODE, int MODE, int TIME, class TB>
+template <int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, double d,
                                              int m, TSplit &ts)
 {
@@ -533,7 +540,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         return;
     }
     if (P.tally_kind == 0) {
-        walk_mesh<MODE, TIME>(P, T, ln, p, d, g, ts, cx.ltally);
+        walk_mesh<MODE, EXT>(P, T, ln, p, d, g, ts, cx.ltally);
     } else {
         int k;
         if (P.ebin_inv != 0.0) {
@@ -544,7 +551,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         } else {
             k = edge_index(P.eedges, P.n_ebins, p.e, 1.0);
         }
-        score_piece<MODE, TIME>(P, ln, p, ts, k, 0.0, d, cx.ltally);
+        score_piece<MODE, EXT>(P, ln, p, ts, k, 0.0, d, cx.ltally);
     }
     if (MODE == MODE_REPLAY_A) p.L = p.L + d;
 }
@@ -642,6 +649,7 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
     p.L = 0.0;
     p.G = 0.0;
     p.t = 0.0;
+    p.wgt = 1.0;
     if (MODE == MODE_REPLAY_B) p.G = P.G[P.gbase + (uint64_t)(hid - P.first)];
 }
 
@@ -678,7 +686,7 @@ enum : int { FLY_SURFACE = 0, FLY_COLLIDE = 1, FLY_TIME = 2 };
 // the time boundary) and the history ends; otherwise the particle's time
 // advances by d / v.  That sum can round to just past t_max; the remaining
 // length is then zero, never negative.
-template <int GEOM, int EMODE, int MODE, int TIME, class TB>
+template <int GEOM, int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ int fly(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, double sigt,
                                    double xi0, int m, int &surf)
 {
@@ -687,7 +695,8 @@ __device__ __forceinline__ int fly(const ProbDev &P, const TB &T, const EvCtx &c
     int res = (dcol < dsurf) ? FLY_COLLIDE : FLY_SURFACE;
     double d = (res == FLY_COLLIDE) ? dcol : dsurf;
     TSplit ts{0.0, 0.0, 0};
-    if (TIME) {
+    const bool timed = EXT && P.n_tbins > 0;
+    if (timed) {
         const double v = (EMODE == EMODE_MG) ? T.speed()[gc_group(p.gc)] : P.speed_coef * root(p.e);
         const double dtime = (P.t_max - p.t) * v;
         if (!(d < dtime)) {
@@ -698,11 +707,11 @@ __device__ __forceinline__ int fly(const ProbDev &P, const TB &T, const EvCtx &c
         ts.v = v;
         ts.k = time_bin(p.t, P.tw, P.n_tbins);
     }
-    score_flight<EMODE, MODE, TIME>(P, T, cx, ln, p, d, m, ts);
+    score_flight<EMODE, MODE, EXT>(P, T, cx, ln, p, d, m, ts);
     p.x = p.x + (d * p.u);
     p.y = p.y + (d * p.v);
     p.z = p.z + (d * p.w);
-    if (TIME && res != FLY_TIME) p.t = p.t + (d / ts.v);
+    if (timed && res != FLY_TIME) p.t = p.t + (d / ts.v);
     return res;
 }
 
@@ -762,20 +771,26 @@ __device__ __forceinline__ bool cross(const ProbDev &P, const TB &T, Part &p, in
     return true;
 }
 
-// Collision at the current site with the flight's random numbers xi1..xi4.
-// Returns false if the history ends (absorption or energy cutoff).
-template <int EMODE, int MODE, class TB>
+// Collision at the current site with the flight's random numbers xi1..xi5.
+// Returns false if the history ends (absorption, energy cutoff, roulette).
+// With implicit capture (extended state) a collision never absorbs: the
+// particle scatters with its weight times the scattering probability, and
+// the closeout then plays weight roulette below the cutoff (xi5).
+template <int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, int m,
                                         double sigt, const CEXS &X, double xi1, double xi2, double xi3, double xi4,
-                                        uint32_t &out)
+                                        double xi5, uint32_t &out)
 {
     out |= O_COLL;
     p.ncoll += 1;
+    const bool implicit = EXT && P.implicit;
     if (EMODE == EMODE_MG) {
         int g = gc_group(p.gc);
         int mg = m * P.n_grp + g;
         double ss = T.sig_s()[mg];
-        if (!((xi1 * sigt) < ss)) {
+        if (implicit) {
+            p.wgt = p.wgt * (ss / sigt);
+        } else if (!((xi1 * sigt) < ss)) {
             out |= O_ABS;
             if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 1, mg, (long long)to_fixed(p.G, P.gscale));
             // k-eigenvalue cycle: the absorption is a fission with probability
@@ -803,7 +818,6 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
         }
         p.gc = (p.gc & ~0xffu) | (uint32_t)gn;
         isotropic(xi3, xi4, p);
-        return true;
     } else {
         double target = xi1 * sigt;
         int sp = P.n_species - 1;
@@ -814,7 +828,9 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
 #pragma unroll
         for (int s = 0; s < MAX_SPECIES; ++s)
             if (s == sp) { sa = X.sa[s]; ss = X.ss[s]; }
-        if (!((xi2 * (sa + ss)) < ss)) {
+        if (implicit) {
+            p.wgt = p.wgt * (ss / (sa + ss));
+        } else if (!((xi2 * (sa + ss)) < ss)) {
             out |= O_ABS;
             finish<MODE>(P, cx, ln, p, FATE_ABSORB);
             return false;
@@ -827,12 +843,22 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
             return false;
         }
         p.e = enew;
-        return true;
     }
+    // closeout: weight roulette below the cutoff
+    if (implicit && p.wgt < P.w_cut) {
+        if ((xi5 * P.w_surv) < p.wgt) {
+            p.wgt = P.w_surv;
+        } else {
+            out |= O_ROUL;
+            finish<MODE>(P, cx, ln, p, FATE_ROULETTE);
+            return false;
+        }
+    }
+    return true;
 }
 
 // Monolithic event: one whole flight (lookup, move with tally, collide or cross).
-template <int GEOM, int EMODE, int MODE, int TIME, class TB>
+template <int GEOM, int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
     if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
@@ -845,9 +871,9 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
     double xi0, xi1;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
     int surf;
-    const int res = fly<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, sigt, xi0, m, surf);
+    const int res = fly<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, sigt, xi0, m, surf);
     out |= O_FLIGHT;
-    if (TIME && res == FLY_TIME) {
+    if (EXT && res == FLY_TIME) {
         out |= O_CUT;
         finish<MODE>(P, cx, ln, p, FATE_CUTOFF);
         return EV_DEAD;
@@ -856,7 +882,7 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
         double xi2, xi3, xi4, xi5;
         uniform_pair(k, p.hid, p.step, 1, xi2, xi3, P.stream);
         uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
-        if (!collide<EMODE, MODE>(P, T, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
+        if (!collide<EMODE, MODE, EXT>(P, T, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, xi5, out)) return EV_DEAD;
     } else {
         if (!cross<GEOM>(P, T, p, surf, out)) {
             finish<MODE>(P, cx, ln, p, FATE_LEAK);
@@ -869,7 +895,7 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
 
 // Decomposed events ------------------------------------------------------
 
-template <int GEOM, int EMODE, int MODE, int TIME, class TB>
+template <int GEOM, int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
     int m = material<GEOM>(P, T, p.gc);
@@ -877,9 +903,9 @@ __device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCt
     double xi0, xi1;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
     int surf;
-    const int res = fly<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, p.sigt, xi0, m, surf);
+    const int res = fly<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, p.sigt, xi0, m, surf);
     out |= O_FLIGHT;
-    if (TIME && res == FLY_TIME) {
+    if (EXT && res == FLY_TIME) {
         out |= O_CUT;
         finish<MODE>(P, cx, ln, p, FATE_CUTOFF);
         return EV_DEAD;
@@ -900,7 +926,7 @@ __device__ __forceinline__ int ev_surface(const ProbDev &P, const TB &T, const E
     return EV_LOOKUP;
 }
 
-template <int GEOM, int EMODE, int MODE, class TB>
+template <int GEOM, int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ int ev_collide(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
                                           uint32_t &out)
 {
@@ -912,20 +938,20 @@ __device__ __forceinline__ int ev_collide(const ProbDev &P, const TB &T, const E
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
     uniform_pair(k, p.hid, p.step, 1, xi2, xi3, P.stream);
     uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
-    if (!collide<EMODE, MODE>(P, T, cx, ln, p, m, p.sigt, X, xi1, xi2, xi3, xi4, out)) return EV_DEAD;
+    if (!collide<EMODE, MODE, EXT>(P, T, cx, ln, p, m, p.sigt, X, xi1, xi2, xi3, xi4, xi5, out)) return EV_DEAD;
     p.step += 1;
     return EV_LOOKUP;
 }
 
-template <int GEOM, int EMODE, int MODE, int SPLIT, int TIME, class TB>
+template <int GEOM, int EMODE, int MODE, int SPLIT, int EXT, class TB>
 __device__ __forceinline__ int run_event(int ev, const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
                                          uint32_t &out)
 {
-    if (!SPLIT) return ev_step<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, out);
+    if (!SPLIT) return ev_step<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
     if (ev == EV_LOOKUP) return ev_lookup<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
-    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE, TIME>(P, T, cx, ln, p, out);
+    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
     if (ev == EV_SURFACE) return ev_surface<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
-    return ev_collide<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
+    return ev_collide<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
 }
 
 // ------------------------------------------------------- wavefront helpers
@@ -971,6 +997,7 @@ struct WaveCount {
         c[C_CUTOFFS] += (uint32_t)__popcll(__ballot(act && (out & O_CUT)));
         c[C_KILLED] += (uint32_t)__popcll(__ballot(act && (out & O_KILL)));
         c[C_FISSIONS] += (uint32_t)__popcll(__ballot(act && (out & O_FISS)));
+        c[C_ROULETTES] += (uint32_t)__popcll(__ballot(act && (out & O_ROUL)));
     }
     __device__ __forceinline__ void dispatch(bool act)
     {
@@ -1017,7 +1044,7 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
         }
         if (err) atomicOr(&ctl->error, err);
         unsigned long long ended = (unsigned long long)wc.c[C_LEAKS] + wc.c[C_ABSORBS] + wc.c[C_CUTOFFS] +
-                                   wc.c[C_KILLED];
+                                   wc.c[C_KILLED] + wc.c[C_ROULETTES];
         if (ended) atomicAdd(&S[C_COMPLETED], ended);
 #pragma unroll
         for (int i = 0; i < C_WAVE; ++i)

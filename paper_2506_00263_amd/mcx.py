@@ -50,6 +50,7 @@ class ProblemDesc(C.Structure):
         ("problem_id", C.c_uint32), ("seed", C.c_uint64), ("n_histories", C.c_uint64), ("max_steps", C.c_int64),
         ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p), ("speed_coef", C.c_double),
         ("sigma_f", C.c_void_p), ("nu", C.c_void_p), ("chi", C.c_void_p),
+        ("implicit_capture", C.c_int32), ("w_cutoff", C.c_double), ("w_survival", C.c_double),
     ]
 
 
@@ -73,7 +74,8 @@ COUNTER_NAMES = ["sourced", "flights", "collisions", "scatters", "absorbs", "cro
 class Counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in COUNTER_NAMES] + [
         ("kernel_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
-        ("lds_bytes", C.c_int32), ("pad", C.c_int32), ("fissions", C.c_uint64), ("sites", C.c_uint64)]
+        ("lds_bytes", C.c_int32), ("pad", C.c_int32), ("fissions", C.c_uint64), ("sites", C.c_uint64),
+        ("roulettes", C.c_uint64)]
 
 
 class EigenOpts(C.Structure):
@@ -200,6 +202,9 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
             raise ValueError("time bins need one speed per group")
         s.speed = arr("speed", np.float64)
     s.speed_coef = float(d.get("speed_coef", 0.0))
+    s.implicit_capture = int(d.get("implicit_capture", 0))
+    s.w_cutoff = float(d.get("w_cutoff", 0.0))
+    s.w_survival = float(d.get("w_survival", 0.0))
     s.sigma_f = s.nu = s.chi = None
     if d.get("sigma_f") is not None:
         mg = int(d["n_mat"]) * int(d["n_grp"])
@@ -347,6 +352,7 @@ class Problem:
         self._check(lib().mcx_counters(self.h, C.byref(c)))
         out = {n: int(getattr(c, n)) for n in COUNTER_NAMES}
         out.update(kernel_ms=c.kernel_ms, grid_blocks=c.grid_blocks, block_threads=c.block_threads,
-                   lds_bytes=c.lds_bytes, fissions=int(c.fissions), sites=int(c.sites))
+                   lds_bytes=c.lds_bytes, fissions=int(c.fissions), sites=int(c.sites),
+                   roulettes=int(c.roulettes))
         return out
 

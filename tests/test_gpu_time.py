@@ -173,7 +173,3 @@ def test_time_bins_invalid(mcx):
     # one speed per group, checked before the descriptor is built
     with pytest.raises(ValueError):
         mcx.Problem(dict(tb, speed=np.array([1.0])))
-    # a batch mixes time-binned and time-free problems: rejected
-    with pytest.raises(mcx.McxError) as e:
-        mcx.Problem([base, tb])
-    assert e.value.status == 1

@@ -1,0 +1,135 @@
+"""GPU parity of non-analog weights (implicit capture and the closeout's
+weight roulette) against the CPU oracle.
+
+The weight changes which histories end where (roulette) and what every
+piece scores (length times weight), so tallies, invariant counters and
+per-history digests must match bit for bit on every scheduler and event
+decomposition, through every tally path, with time bins, in mixed batches
+and through the global link arena.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_00263_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+INVARIANT = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks", "reflections",
+             "cutoffs", "killed", "pieces", "qsum", "overflow", "roulettes"]
+SCHEDS = [("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"), ("async", "split")]
+
+
+@pytest.fixture(scope="module")
+def mcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_00263_amd import mcx as M
+    M.lib()
+    return M
+
+
+def _digest(n):
+    import torch
+    return torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+
+
+def _check(mcx, P, dg, ref, what):
+    assert np.array_equal(P.tallies(), ref["tally"]), what
+    got = P.counters()
+    for k in INVARIANT:
+        assert got[k] == ref["counts"][k], (what, k, got[k], ref["counts"][k])
+    if dg is not None:
+        assert np.array_equal(dg.cpu().numpy().view(mcx.DIGEST_DTYPE), ref["digest"]), what
+
+
+@pytest.fixture(scope="module")
+def lattice_w(oracle):
+    d = inputs.with_implicit_capture(inputs.cfg2_lattice(12_000), 0.25, 0.5)
+    ref = oracle.run(d, digest=True)
+    assert ref["counts"]["roulettes"] > 0 and ref["counts"]["absorbs"] == 0
+    return d, ref
+
+
+@pytest.mark.parametrize("sched,decomp", SCHEDS)
+def test_lattice_implicit_capture(mcx, lattice_w, sched, decomp):
+    d, ref = lattice_w
+    P = mcx.Problem(d)
+    dg = _digest(d["n_histories"])
+    P.run(sched=sched, decomp=decomp, digest=dg)
+    _check(mcx, P, dg, ref, (sched, decomp))
+
+
+def test_box_weights_every_tally_path(mcx, oracle):
+    d = inputs.with_implicit_capture(inputs.cfg1_box(8000), 0.2, 0.6)
+    ref = oracle.run(d, digest=True)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        for path in ("lds", "replicas", "direct"):
+            dg = _digest(d["n_histories"])
+            P.run(sched=sched, decomp=decomp, tally_path=path, digest=dg)
+            _check(mcx, P, dg, ref, (sched, decomp, path))
+
+
+def test_ce_weights(mcx, oracle):
+    d = inputs.with_implicit_capture(inputs.pincell_ce(n_ebins=300, n_histories=400), 0.1, 0.4)
+    ref = oracle.run(d, digest=True)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        for lookup in ("binary", "hash"):
+            dg = _digest(d["n_histories"])
+            P.run(sched=sched, decomp=decomp, lookup=lookup, digest=dg)
+            _check(mcx, P, dg, ref, (sched, decomp, lookup))
+
+
+def test_weights_with_time_bins_and_spills(mcx, oracle):
+    d = inputs.with_implicit_capture(inputs.with_time_bins(inputs.cfg2_lattice(6000), 4, 100.0), 0.25, 0.5)
+    ref = oracle.run(d, digest=True)
+    assert ref["counts"]["cutoffs"] > 0 and ref["counts"]["roulettes"] > 0
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        dg = _digest(d["n_histories"])
+        P.run(sched=sched, decomp=decomp, digest=dg)
+        _check(mcx, P, dg, ref, (sched, decomp))
+    for decomp in ("fused", "split"):
+        P.run(sched="async", decomp=decomp, force_spill=3, stash_links=6)
+        _check(mcx, P, None, ref, (decomp, "spills"))
+        assert P.counters()["spills"] > 0
+
+
+def test_mixed_batch(mcx, oracle):
+    # analog, time-binned, weighted and both in one launch
+    probs = inputs.cfg5_batch(n_problems=16, hist_scale=0.03)
+    mixed = []
+    for k, d in enumerate(probs):
+        if k % 4 == 1:
+            d = inputs.with_time_bins(d, 3, 40.0 + 5.0 * k)
+        elif k % 4 == 2:
+            d = inputs.with_implicit_capture(d, 0.2, 0.5)
+        elif k % 4 == 3:
+            d = inputs.with_implicit_capture(inputs.with_time_bins(d, 2, 60.0), 0.3, 0.6)
+        mixed.append(d)
+    refs = [oracle.run(d) for d in mixed]
+    P = mcx.Problem(mixed)
+    for sched, decomp in SCHEDS:
+        P.run(sched=sched, decomp=decomp)
+        for k, ref in enumerate(refs):
+            assert np.array_equal(P.tallies(k), ref["tally"]), (sched, decomp, k)
+        c = P.counters()
+        for key in ("flights", "roulettes", "cutoffs", "pieces"):
+            assert c[key] == sum(r["counts"][key] for r in refs), (sched, decomp, key)
+
+
+def test_weights_rejected_where_analog_is_required(mcx):
+    d = inputs.with_implicit_capture(inputs.lattice_mg(n_histories=500))
+    P = mcx.Problem(d)
+    P.run(sched="async")
+    with pytest.raises(mcx.McxError) as e:
+        P.backward(np.zeros(inputs.n_bins(d)), sched="async")
+    assert e.value.status == 1
+    with pytest.raises(mcx.McxError):
+        mcx.Problem(inputs.with_fission(d)).run_eigen(100, 2, 1)
+    for wc, ws in ((-0.1, 0.5), (0.6, 0.5), (0.1, 0.0), (0.1, float("inf"))):
+        with pytest.raises(mcx.McxError) as e:
+            mcx.Problem(inputs.with_implicit_capture(inputs.cfg1_box(64), wc, ws))
+        assert e.value.status == 1
