@@ -72,8 +72,8 @@ def _wall(P, reps, **kw):
     return float(np.median(ts[1:]))
 
 
-SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "eigen", "async_waves", "backward",
-               "batch")
+SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "eigen", "async_waves", "weights",
+               "backward", "batch")
 
 
 def eigen_run(P, n, cycles, **kw):
@@ -196,6 +196,20 @@ def sweep(parts=SWEEP_PARTS) -> dict:
                                                "block_threads": c["block_threads"], "lds_bytes": c["lds_bytes"]})
                     print("sweep async_waves", out["async_waves"][-1], file=sys.stderr, flush=True)
             del P
+    # non-analog weights: implicit capture with roulette below 0.25 to 0.5
+    # against analog histories (histories run longer: more flights each)
+    if "weights" in parts:
+        for name, d0 in (("lattice 1e6", inputs.cfg2_lattice(1_000_000)), ("box 1e6", inputs.cfg1_box(1_000_000))):
+            for label, d in (("analog", d0), ("implicit capture", inputs.with_implicit_capture(d0, 0.25, 0.5))):
+                P = mcx.Problem(d)
+                for s, dc in scheds:
+                    t = _wall(P, 2, sched=s, decomp=dc)
+                    c = P.counters()
+                    out["weights"].append({"case": name, "weights": label, "sched": s, "decomp": dc, "ms": 1e3 * t,
+                                           "hist_per_s": d["n_histories"] / t,
+                                           "flights_per_history": c["flights"] / d["n_histories"]})
+                    print("sweep weights", out["weights"][-1], file=sys.stderr, flush=True)
+                del P
     import torch
     d = inputs.cfg4_lattice_grad(1_000_000)
     P = mcx.Problem(d) if "backward" in parts else None
