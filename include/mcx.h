@@ -320,6 +320,12 @@ mcx_status mcx_backward(mcx_problem_t p, int32_t problem, const double *dL_dT, d
  * are filled; mcx_backward does not apply to it. */
 mcx_status mcx_run_eigen(mcx_problem_t p, const mcx_run_opts *opts, const mcx_eigen_opts *eig);
 
+/* Device scratch (bytes) that mcx_run with these options would allocate
+ * for its scheduler state (stack banks and counters, or the async link
+ * arena) and tally replicas; 0 for the naive scheduler.  The library grows
+ * its own workspace to this size on the first such run and keeps it. */
+mcx_status mcx_workspace_size(mcx_problem_t p, const mcx_run_opts *opts, size_t *bytes);
+
 mcx_status mcx_counters(mcx_problem_t p, mcx_counters_t *out);
 
 /* Sizes of problem `problem`: tally bins, materials, groups, histories. */

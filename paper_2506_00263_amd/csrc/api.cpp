@@ -726,6 +726,45 @@ static int tally_path(mcx_problem_t h, const mcx_run_opts &o, int mode)
     return MCX_TALLY_PATH_DIRECT;
 }
 
+// Launch description of one pass (scheduler-independent fields and tuning).
+static LaunchArgs launch_args(mcx_problem_t h, const mcx_run_opts &o, int mode, unsigned long long total, int path,
+                              void *digest)
+{
+    LaunchArgs a{};
+    a.probs = h->d_probs;
+    a.n_probs = h->n;
+    a.prefix = h->d_prefix;
+    a.total = total;
+    a.ctl = h->d_ctl;
+    a.digest = digest;
+    a.geom = h->geom;
+    a.emode = h->emode;
+    a.mode = mode;
+    a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
+    a.ext = 0;
+    for (int k = 0; k < h->n; ++k)
+        if (h->pd[k].n_tbins > 0 || h->pd[k].implicit) a.ext = 1;
+    a.lacc_words = 0;
+    if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
+    if (path == MCX_TALLY_PATH_LDS) a.lacc_words = (int)h->hp[0].n_bins;
+    a.tl_bytes = (h->n == 1 && h->pd[0].tl_bytes <= TL_MAX_BYTES) ? h->pd[0].tl_bytes : 0;
+    a.stream = (hipStream_t)o.hip_stream;
+    a.num_cus = h->num_cus;
+    a.block_size = o.block_size;
+    a.waves_per_cu = o.waves_per_cu;
+    a.stack_capacity = o.stack_capacity;
+    a.stack_threshold = o.stack_threshold;
+    a.stash_links = o.stash_links;
+    a.arena_links = o.arena_links;
+    a.force_spill = o.force_spill;
+    a.consolidate = o.consolidate;
+    a.stack_tail_events = o.stack_tail_events;
+    a.stack_min_events = o.stack_min_events;
+    a.async_block_waves = o.async_block_waves;
+    a.ws_query = nullptr;
+    return a;
+}
+
 // One pass over the run's histories with the given mode.
 static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, const std::vector<uint64_t> &first,
                            const std::vector<uint64_t> &count, void *digest, unsigned int *err_out)
@@ -764,37 +803,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     ctl.total = total;
     HIP_TRY(h, hipMemcpyAsync(h->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, stream));
 
-    LaunchArgs a{};
-    a.probs = h->d_probs;
-    a.n_probs = h->n;
-    a.prefix = h->d_prefix;
-    a.total = total;
-    a.ctl = h->d_ctl;
-    a.digest = digest;
-    a.geom = h->geom;
-    a.emode = h->emode;
-    a.mode = mode;
-    a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
-    a.ext = 0;
-    for (int k = 0; k < h->n; ++k)
-        if (h->pd[k].n_tbins > 0 || h->pd[k].implicit) a.ext = 1;
-    a.lacc_words = 0;
-    if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
-    if (path == MCX_TALLY_PATH_LDS) a.lacc_words = (int)h->hp[0].n_bins;
-    a.tl_bytes = (h->n == 1 && h->pd[0].tl_bytes <= TL_MAX_BYTES) ? h->pd[0].tl_bytes : 0;
-    a.stream = stream;
-    a.num_cus = h->num_cus;
-    a.block_size = o.block_size;
-    a.waves_per_cu = o.waves_per_cu;
-    a.stack_capacity = o.stack_capacity;
-    a.stack_threshold = o.stack_threshold;
-    a.stash_links = o.stash_links;
-    a.arena_links = o.arena_links;
-    a.force_spill = o.force_spill;
-    a.consolidate = o.consolidate;
-    a.stack_tail_events = o.stack_tail_events;
-    a.stack_min_events = o.stack_min_events;
-    a.async_block_waves = o.async_block_waves;
+    LaunchArgs a = launch_args(h, o, mode, total, path, digest);
 
     LaunchStats st;
     LaunchTimer tm;
@@ -1140,6 +1149,38 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
     hipMemcpyKind kind = where == MCX_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
     HIP_TRY(h, hipMemcpy(grad_sigma_t, gt.data(), nb, kind));
     HIP_TRY(h, hipMemcpy(grad_sigma_s, gs.data(), nb, kind));
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_workspace_size(mcx_problem_t h, const mcx_run_opts *opts, size_t *bytes)
+{
+    if (!h || !opts || !bytes) return MCX_E_INVALID_ARG;
+    const mcx_run_opts &o = *opts;
+    mcx_status s = check_opts(h, o);
+    if (s != MCX_OK) return s;
+    unsigned long long total = 0;
+    if (h->n == 1) {
+        uint64_t N = h->hp[0].d.n_histories;
+        if (o.first_history > N) return fail(h, MCX_E_INVALID_ARG, "first_history beyond n_histories");
+        total = o.n_histories ? o.n_histories : N - o.first_history;
+    } else {
+        for (int k = 0; k < h->n; ++k) total += h->hp[k].d.n_histories;
+    }
+    const int path = tally_path(h, o, MODE_FWD);
+    LaunchArgs a = launch_args(h, o, MODE_FWD, total, path, o.digest);
+    size_t need = 0;
+    a.ws_query = &need;
+    LaunchStats st;
+    LaunchTimer tm;
+    hipError_t e = hipSuccess;
+    if (total > 0) {
+        if (o.sched == MCX_SCHED_NAIVE) e = launch_naive(a, st, tm);
+        else if (o.sched == MCX_SCHED_STACK) e = launch_stack(a, h->ws, st, tm, h->h_flag);
+        else e = launch_async(a, h->ws, st, tm);
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "workspace query");
+    if (path == MCX_TALLY_PATH_REPLICAS) need += (size_t)TREP * (size_t)h->hp[0].n_bins * 8;
+    *bytes = need;
     return MCX_OK;
 }
 

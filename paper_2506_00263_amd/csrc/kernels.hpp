@@ -79,6 +79,8 @@ struct LaunchArgs {
     int stack_tail_events;                 // stack: events per pop in the tail (0 = default)
     int stack_min_events;                  // stack: events per pop at least (0 = default 1)
     int async_block_waves;                 // async: wavefronts per block, 1, 2 or 4 (0 = ASYNC_BLOCK_WAVES)
+    size_t *ws_query;                      // non-null: only report the workspace bytes the launch
+                                           // needs (nothing is allocated or launched)
 };
 
 // Default wavefronts per asynchronous block.  Measured on MI355X (1e6

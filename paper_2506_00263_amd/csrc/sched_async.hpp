@@ -540,6 +540,10 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     int n_arena = a.arena_links > 0 ? a.arena_links : (int)(waves * (E + 2) + 1024);
     size_t arena_bytes = (size_t)n_arena * link_bytes;
     size_t need = arena_bytes + (size_t)n_arena * 8 + (size_t)Q * 16 + 1024;
+    if (a.ws_query) {
+        *a.ws_query = need;
+        return hipSuccess;
+    }
     e = ws_reserve(ws, need);
     if (e != hipSuccess) return e;
     AsyncArgs A;

@@ -72,6 +72,10 @@ static hipError_t launch_naive_t(const LaunchArgs &a, LaunchStats &st, LaunchTim
     if (blocks > cap) blocks = cap;
     if (blocks == 0) blocks = 1;
     size_t lds = tabs_lds_offset((size_t)a.lacc_words * 8) + (BATCH ? 0 : (size_t)a.tl_bytes);
+    if (a.ws_query) {
+        *a.ws_query = 0;      // the naive kernel keeps particles in registers only
+        return hipSuccess;
+    }
     st.grid_blocks = (int)blocks;
     st.block_threads = bs;
     st.lds_bytes = (int)lds;

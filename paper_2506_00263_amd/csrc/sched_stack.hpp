@@ -310,6 +310,10 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     long event_bytes = stripe_bytes * (NSTRIPE - 1) + ocap / 64 * tile_bytes;
     size_t ctr_bytes = (size_t)3 * E * NSTRIPE * CTR_STRIDE * 4;
     size_t need = (size_t)event_bytes * E * 2 + ctr_bytes;
+    if (a.ws_query) {
+        *a.ws_query = need;
+        return hipSuccess;
+    }
     hipError_t e = ws_reserve(ws, need);
     if (e != hipSuccess) return e;
     StackArgs A;

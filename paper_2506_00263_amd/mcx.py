@@ -104,6 +104,7 @@ def lib():
         L.mcx_backward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(RunOpts)]
         L.mcx_counters.argtypes = [C.c_void_p, P(Counters)]
         L.mcx_run_eigen.argtypes = [C.c_void_p, P(RunOpts), P(EigenOpts)]
+        L.mcx_workspace_size.argtypes = [C.c_void_p, P(RunOpts), P(C.c_size_t)]
         L.mcx_problem_info.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int32), P(C.c_int32),
                                        P(C.c_uint64)]
         L.mcx_destroy_problem.argtypes = [C.c_void_p]
@@ -305,6 +306,13 @@ class Problem:
         o = run_opts(**kw)
         self._check(lib().mcx_run(self.h, C.byref(o)))
         return self
+
+    def workspace_size(self, **kw) -> int:
+        """Device scratch bytes a run with these options would allocate."""
+        o = run_opts(**kw)
+        n = C.c_size_t(0)
+        self._check(lib().mcx_workspace_size(self.h, C.byref(o), C.byref(n)))
+        return int(n.value)
 
     def run_eigen(self, n_particles: int, n_cycles: int, n_inactive: int, **kw) -> dict:
         """k-eigenvalue power iteration: returns k and the source size of every

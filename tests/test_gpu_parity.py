@@ -367,3 +367,27 @@ def test_async_block_waves(mcx, oracle, cfg1, cfg2, wpb):
         assert np.array_equal(B.tallies(k), oracle.run(pd)["tally"]), k
     with pytest.raises(mcx.McxError):
         B.run(sched="async", async_block_waves=3)
+
+
+def test_workspace_size(mcx, cfg2):
+    # the query allocates and launches nothing and follows the layouts: one
+    # more async arena link costs one 64-particle link (64 x 64 bytes for the
+    # fused multigroup forward) plus its two 4-byte header words
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    assert P.workspace_size(sched="naive") == 0
+    a1 = P.workspace_size(sched="async", arena_links=1000)
+    a2 = P.workspace_size(sched="async", arena_links=2000)
+    assert a2 - a1 == 1000 * (64 * 64 + 8)
+    s1 = P.workspace_size(sched="stack", stack_capacity=100_000)
+    s2 = P.workspace_size(sched="stack", stack_capacity=200_000)
+    assert 0 < s1 < s2
+    assert P.workspace_size(sched="stack", decomp="split") > P.workspace_size(sched="stack")
+    with pytest.raises(mcx.McxError):
+        P.tallies()                      # no run yet: the queries did not run anything
+    P.run(sched="async", arena_links=2000)
+    assert np.array_equal(P.tallies(), ref["tally"])
+    # an energy tally above the LDS limit adds its 16 replicas
+    dc = inputs.pincell_ce(n_ebins=10_000, n_histories=100)
+    Q = mcx.Problem(dc)
+    assert Q.workspace_size(sched="naive") == 16 * 10_000 * 8
