@@ -521,15 +521,23 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     int wpb = a.async_block_waves > 0 ? a.async_block_waves : ASYNC_BLOCK_WAVES;
     if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
     auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>;
-    // fewer wavefronts per block when the block's LDS would not fit
+    // when the block's LDS would not fit: first the smallest default stash
+    // (one link per event plus one), then fewer wavefronts per block
     size_t lds = 0;
     int per_cu = 0;
     hipError_t e = hipSuccess;
-    for (;; wpb >>= 1) {
+    for (;;) {
         lds = tabs_lds_offset((size_t)wpb * L * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
         if (e != hipSuccess) return e;
-        if (per_cu >= 1 || wpb == 1) break;
+        if (per_cu >= 1) break;
+        if (a.stash_links == 0 && L > E + 1) {
+            L = E + 1;
+        } else if (wpb > 1) {
+            wpb >>= 1;
+        } else {
+            break;
+        }
     }
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     int wpc = per_cu * wpb;           // resident wavefronts per CU
