@@ -605,7 +605,7 @@ static hipError_t async_s(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
                    : async_b<GEOM, EMODE, MODE, 0, EXT>(a, ws, st, tm);
 }
 
-// every event program of one time mode (runs with or without time bins)
+// every event program of one particle-state mode (without or with time and weight)
 template <int EXT>
 static hipError_t launch_async_tm(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {

@@ -94,7 +94,7 @@ static hipError_t naive_b(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
                                               : launch_naive_t<GEOM, EMODE, MODE, false, EXT>(a, st, tm);
 }
 
-// every event program of one time mode (runs with or without time bins)
+// every event program of one particle-state mode (without or with time and weight)
 template <int EXT>
 static hipError_t launch_naive_tm(const LaunchArgs &a, LaunchStats &st, LaunchTimer &tm)
 {

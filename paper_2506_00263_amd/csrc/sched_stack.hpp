@@ -414,7 +414,7 @@ static hipError_t stack_s(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
                    : stack_b<GEOM, EMODE, MODE, 0, EXT>(a, ws, st, tm, flag);
 }
 
-// every event program of one time mode (runs with or without time bins)
+// every event program of one particle-state mode (without or with time and weight)
 template <int EXT>
 static hipError_t launch_stack_tm(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm,
                                   unsigned int *flag)

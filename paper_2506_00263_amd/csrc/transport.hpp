@@ -1,4 +1,6 @@
-// Event programs of analog fixed-source Monte Carlo transport.
+// Event programs of Monte Carlo particle transport: analog fixed-source
+// histories, with optional time bins, non-analog weights (implicit capture
+// with a roulette closeout) and k-eigenvalue fission banking.
 //
 // A history is: a source event (position, direction, group or energy from
 // the history's own random numbers), then flights.  One flight samples a
@@ -16,8 +18,14 @@
 //
 // Random-number slots per flight k >= 1: 0 distance; 1 absorb/scatter (MG)
 // or species (CE); 2 outgoing group (MG) or absorb/scatter (CE); 3 polar
-// cosine (MG) or centre-of-mass cosine (CE); 4 azimuth.  Source (k = 0):
-// 0-2 position, 3 polar cosine, 4 azimuth.
+// cosine (MG) or centre-of-mass cosine (CE); 4 azimuth; 5 weight roulette.
+// At an absorption (k-eigenvalue cycles) 2 decides fission and 3 rounds nu.
+// Source (k = 0): 0-2 position, 3 polar cosine, 4 azimuth; a banked fission
+// neutron uses 0 for its group.  The fourth counter word is the k-eigenvalue
+// cycle (0 otherwise).
+//
+// The extended kernels (template flag EXT) carry each particle's time and
+// weight; the others carry neither and score plain track lengths.
 #pragma once
 #include "problem.hpp"
 #include "rng_math.hpp"
@@ -25,6 +33,24 @@
 #pragma clang fp contract(off)
 
 namespace mcx {
+
+// A pointer to global memory with its address space stated: buffers named by
+// the problem record (packed tables, source bank, fission records, digests)
+// would otherwise be accessed with flat instructions, which on gfx9 count on
+// the LDS counter as well and so hold up later LDS reads.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gmem(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
+// the same pointer as a plain one, for code that takes plain pointers: after
+// inlining the compiler still sees that it points to global memory
+template <class T>
+__device__ __forceinline__ T *gptr(T *p)
+{
+    return (T *)gmem(p);
+}
 
 enum : int { EV_STEP = 0, EV_LOOKUP = 0, EV_MOVE = 1, EV_SURFACE = 2, EV_COLLIDE = 3, EV_DEAD = 7 };
 enum : uint32_t {
@@ -92,21 +118,21 @@ struct EvCtx {
 // wait behind the wavefront's outstanding tally atomics, which go to memory.
 struct TabsG {
     const ProbDev &P;
-    __device__ __forceinline__ const double *sig_t() const { return P.sig_t; }
-    __device__ __forceinline__ const double *sig_s() const { return P.sig_s; }
-    __device__ __forceinline__ const double *cdf() const { return P.cdf; }
-    __device__ __forceinline__ const double *xpl() const { return P.xpl; }
-    __device__ __forceinline__ const double *ypl() const { return P.ypl; }
-    __device__ __forceinline__ const double *cxs() const { return P.cxs; }
-    __device__ __forceinline__ const double *cys() const { return P.cys; }
-    __device__ __forceinline__ const double *mx() const { return P.mx; }
-    __device__ __forceinline__ const double *my() const { return P.my; }
-    __device__ __forceinline__ const double *mz() const { return P.mz; }
-    __device__ __forceinline__ const double *speed() const { return P.speed; }
-    __device__ __forceinline__ const double *sigf() const { return P.sigf; }
-    __device__ __forceinline__ const double *nu() const { return P.nu; }
-    __device__ __forceinline__ const double *chi() const { return P.chi; }
-    __device__ __forceinline__ const int32_t *cmat() const { return P.cmat; }
+    __device__ __forceinline__ const double *sig_t() const { return gptr(P.sig_t); }
+    __device__ __forceinline__ const double *sig_s() const { return gptr(P.sig_s); }
+    __device__ __forceinline__ const double *cdf() const { return gptr(P.cdf); }
+    __device__ __forceinline__ const double *xpl() const { return gptr(P.xpl); }
+    __device__ __forceinline__ const double *ypl() const { return gptr(P.ypl); }
+    __device__ __forceinline__ const double *cxs() const { return gptr(P.cxs); }
+    __device__ __forceinline__ const double *cys() const { return gptr(P.cys); }
+    __device__ __forceinline__ const double *mx() const { return gptr(P.mx); }
+    __device__ __forceinline__ const double *my() const { return gptr(P.my); }
+    __device__ __forceinline__ const double *mz() const { return gptr(P.mz); }
+    __device__ __forceinline__ const double *speed() const { return gptr(P.speed); }
+    __device__ __forceinline__ const double *sigf() const { return gptr(P.sigf); }
+    __device__ __forceinline__ const double *nu() const { return gptr(P.nu); }
+    __device__ __forceinline__ const double *chi() const { return gptr(P.chi); }
+    __device__ __forceinline__ const int32_t *cmat() const { return gptr(P.cmat); }
 };
 
 struct TabsL {
@@ -133,9 +159,9 @@ struct TabsL {
 // takes part; ends with a block barrier).
 __device__ __forceinline__ void tabs_to_lds(const ProbDev &P, char *dst)
 {
-    const uint4 *src = (const uint4 *)P.tl_src;
-    uint4 *d = (uint4 *)dst;
-    const int n = P.tl_bytes >> 4;
+    const auto *src = gmem((const unsigned long long *)P.tl_src);
+    unsigned long long *d = (unsigned long long *)dst;
+    const int n = P.tl_bytes >> 3;
     for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) d[i] = src[i];
     __syncthreads();
 }
@@ -296,8 +322,8 @@ __device__ __forceinline__ int ce_bracket(const ProbDev &P, int s, const double 
         double t = (lnE - P.hash_ln_lo) * P.hash_inv;
         int b = 0;
         if (t > 0.0) b = (t < (double)P.hash_bins) ? (int)t : P.hash_bins - 1;
-        lo = P.hash_lo[s * P.hash_bins + b];
-        hi = P.hash_hi[s * P.hash_bins + b];
+        lo = gptr(P.hash_lo)[s * P.hash_bins + b];
+        hi = gptr(P.hash_hi)[s * P.hash_bins + b];
         while (lo > 0 && g[lo] > e) lo = lo - 1;
         while (hi < n - 1 && g[hi] <= e) hi = hi + 1;
     }
@@ -320,9 +346,9 @@ __device__ __forceinline__ double ce_lookup(const ProbDev &P, int m, double e, C
         X.ss[s] = 0.0;
         X.cum[s] = cum;
         if (s < P.n_species) {
-            const double *g = P.egrid + (long)s * n;
-            const double *a = P.siga + (long)s * n;
-            const double *b = P.sigs + (long)s * n;
+            const double *g = gptr(P.egrid) + (long)s * n;
+            const double *a = gptr(P.siga) + (long)s * n;
+            const double *b = gptr(P.sigs) + (long)s * n;
             double ec = e;
             if (ec < g[0]) ec = g[0];
             if (ec > g[n - 1]) ec = g[n - 1];
@@ -332,7 +358,7 @@ __device__ __forceinline__ double ce_lookup(const ProbDev &P, int m, double e, C
             double ss = b[i] + (f * (b[i + 1] - b[i]));
             X.sa[s] = sa;
             X.ss[s] = ss;
-            cum = cum + (P.dens[m * P.n_species + s] * (sa + ss));
+            cum = cum + (gptr(P.dens)[m * P.n_species + s] * (sa + ss));
             X.cum[s] = cum;
         }
     }
@@ -378,6 +404,24 @@ __device__ __forceinline__ void isotropic(double xi_mu, double xi_phi, Part &p)
 
 // ---------------------------------------------------------------- tallies
 
+// Integer adds with the address space stated.  Tally and sum pointers come
+// out of the problem record, so the compiler cannot tell global memory from
+// LDS and would issue flat atomics; on gfx9 a flat access counts on both
+// the vector-memory and the LDS counters, so every later LDS table read
+// would wait for the atomic's round trip to memory.
+typedef __attribute__((address_space(1))) unsigned long long gu64;
+typedef __attribute__((address_space(3))) unsigned long long lu64;
+
+__device__ __forceinline__ void add_global(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add((gu64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void add_lds(unsigned long long *p, unsigned long long v)
+{
+    __hip_atomic_fetch_add((lu64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // lt: this block's LDS copy of the bins (a small tally: every flight would hit
 // the same few global words, and the device serialises atomics per address),
 // or null to add into the global tally directly
@@ -389,13 +433,13 @@ __device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long 
         long long q = (long long)to_fixed(len, P.tscale);
         if (q != 0) {
             if (lt) {
-                __hip_atomic_fetch_add(lt + bin, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                add_lds(lt + bin, (unsigned long long)q);
             } else {
                 // a large energy-bin tally: particles of a round or wavefront
                 // have similar energies and hit the same few bins, so the adds
                 // are spread over replicas
                 unsigned long long *dst = P.trep ? P.trep + (size_t)ln.rep * (size_t)P.n_bins : P.tally;
-                __hip_atomic_fetch_add(dst + bin, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                add_global(dst + bin, (unsigned long long)q);
             }
             p.hq += q;
             unsigned long long before = ln.q;
@@ -404,7 +448,7 @@ __device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long 
             ln.pieces += 1;
         }
     } else if (MODE == MODE_REPLAY_A) {
-        p.G = p.G + (P.w[bin] * len);
+        p.G = p.G + (gptr(P.w)[bin] * len);
     }
 }
 
@@ -522,10 +566,10 @@ __device__ __forceinline__ void pass_b_add(const ProbDev &P, const EvCtx &cx, in
 {
     if (q == 0) return;
     if (cx.lacc) {
-        atomicAdd(cx.lacc + (which * P.n_mat * P.n_grp + mg), (unsigned long long)q);
+        add_lds(cx.lacc + (which * P.n_mat * P.n_grp + mg), (unsigned long long)q);
     } else {
         unsigned long long *dst = (which == 0) ? P.SL : (which == 1) ? P.SA : P.SS;
-        __hip_atomic_fetch_add(dst + mg, (unsigned long long)q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        add_global(dst + mg, (unsigned long long)q);
     }
 }
 
@@ -547,9 +591,9 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
             double t = ((-neg_log(p.e)) - P.ebin_lnlo) * P.ebin_inv;
             int g = 0;
             if (t > 0.0) g = (t < (double)P.n_ebins) ? (int)t : P.n_ebins - 1;
-            k = edge_index_from(P.eedges, P.n_ebins, p.e, 1.0, g);
+            k = edge_index_from(gptr(P.eedges), P.n_ebins, p.e, 1.0, g);
         } else {
-            k = edge_index(P.eedges, P.n_ebins, p.e, 1.0);
+            k = edge_index(gptr(P.eedges), P.n_ebins, p.e, 1.0);
         }
         score_piece<MODE, EXT>(P, ln, p, ts, k, 0.0, d, cx.ltally);
     }
@@ -565,16 +609,15 @@ __device__ __forceinline__ void finish(const ProbDev &P, const EvCtx &cx, Lane &
     uint64_t idx = P.gbase + (uint64_t)(p.hid - P.first);
     if (MODE == MODE_FWD) {
         if (cx.digest) {
-            Digest dg;
-            dg.qsum = p.hq;
-            dg.flights = flights;
-            dg.collisions = p.ncoll;
-            dg.fate = fate;
-            dg.pad = 0;
-            cx.digest[idx] = dg;
+            auto *dg = gmem(cx.digest + idx);
+            dg->qsum = p.hq;
+            dg->flights = flights;
+            dg->collisions = p.ncoll;
+            dg->fate = fate;
+            dg->pad = 0;
         }
     } else if (MODE == MODE_REPLAY_A) {
-        P.G[idx] = p.G;
+        *gmem(P.G + idx) = p.G;
         double bound = ceil(fabs(p.G) * (p.L + (double)flights));
         if (!(bound < 0x1p63)) {
             ln.err |= ERR_BOUND;
@@ -583,7 +626,7 @@ __device__ __forceinline__ void finish(const ProbDev &P, const EvCtx &cx, Lane &
             ln.u = before + (unsigned long long)bound;
             if (ln.u < before) ln.err |= ERR_BOUND;
         } else {
-            unsigned long long old = __hip_atomic_fetch_add(P.U, (unsigned long long)bound, __ATOMIC_RELAXED,
+            unsigned long long old = __hip_atomic_fetch_add(gmem(P.U), (unsigned long long)bound, __ATOMIC_RELAXED,
                                                             __HIP_MEMORY_SCOPE_AGENT);
             if (old + (unsigned long long)bound < old) ln.err |= ERR_BOUND;
         }
@@ -602,9 +645,10 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
     const uint64_t idx = P.gbase + (uint64_t)(hid - P.first);
     const bool banked = P.sbank != nullptr;   // a k-eigenvalue cycle after the first
     if (banked) {
-        p.x = P.sbank[3 * idx];
-        p.y = P.sbank[3 * idx + 1];
-        p.z = P.sbank[3 * idx + 2];
+        const auto *sb = gmem(P.sbank + 3 * idx);
+        p.x = sb[0];
+        p.y = sb[1];
+        p.z = sb[2];
     } else if (P.src_kind == 0) {
         p.x = P.src_pos[0]; p.y = P.src_pos[1]; p.z = P.src_pos[2];
     } else if (P.src_kind == 1) {
@@ -639,7 +683,7 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
         }
         p.gc = (p.gc & ~0xffu) | (uint32_t)g;
     }
-    if (P.fn) P.fn[idx] = 0u;
+    if (P.fn) *gmem(P.fn + idx) = 0u;
     p.hid = hid;
     p.prob = prob;
     p.step = 1;
@@ -650,7 +694,7 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
     p.G = 0.0;
     p.t = 0.0;
     p.wgt = 1.0;
-    if (MODE == MODE_REPLAY_B) p.G = P.G[P.gbase + (uint64_t)(hid - P.first)];
+    if (MODE == MODE_REPLAY_B) p.G = *gmem(P.G + (P.gbase + (uint64_t)(hid - P.first)));
 }
 
 // flight cap; true if the history was killed
@@ -797,10 +841,11 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
             // Sigma_f / Sigma_a and banks floor(nu + xi) neutrons at the site
             if (MODE == MODE_FWD && P.fn && ((xi2 * (sigt - ss)) < T.sigf()[mg])) {
                 const uint64_t idx = P.gbase + (uint64_t)(p.hid - P.first);
-                P.fn[idx] = (uint32_t)(T.nu()[mg] + xi3);
-                P.fpos[3 * idx] = p.x;
-                P.fpos[3 * idx + 1] = p.y;
-                P.fpos[3 * idx + 2] = p.z;
+                *gmem(P.fn + idx) = (uint32_t)(T.nu()[mg] + xi3);
+                auto *fp = gmem(P.fpos + 3 * idx);
+                fp[0] = p.x;
+                fp[1] = p.y;
+                fp[2] = p.z;
                 out |= O_FISS;
             }
             finish<MODE>(P, cx, ln, p, FATE_ABSORB);
@@ -836,7 +881,7 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
             return false;
         }
         out |= O_SCAT;
-        double enew = elastic(P.awr[sp], p.e, xi3, xi4, p);
+        double enew = elastic(gptr(P.awr)[sp], p.e, xi3, xi4, p);
         if (enew < P.e_min) {
             out |= O_CUT;
             finish<MODE>(P, cx, ln, p, FATE_CUTOFF);
@@ -1076,7 +1121,7 @@ __device__ __forceinline__ void ltally_flush(const unsigned long long *lt, const
 {
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         unsigned long long v = lt[i];
-        if (v) __hip_atomic_fetch_add(P.tally + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (v) add_global(P.tally + i, v);
     }
 }
 
@@ -1087,7 +1132,7 @@ __device__ __forceinline__ void lacc_flush(unsigned long long *lacc, const ProbD
         unsigned long long v = lacc[i];
         if (v) {
             unsigned long long *dst = (i < mg) ? P.SL : (i < 2 * mg) ? P.SA : P.SS;
-            atomicAdd(dst + (i % mg), v);
+            add_global(dst + (i % mg), v);
         }
     }
 }
