@@ -332,8 +332,13 @@ struct AsyncWave {
 // stash; the block shares one LDS copy of the tables and one set of LDS
 // tally sums, which one-wavefront blocks would each hold (the occupancy cost
 // the paper attributes to per-warp stashes, Sec. 5.2).
+// The problem table is also passed as a read-only, unaliased kernel argument:
+// loads from it can then be scalar loads, which do not queue behind the
+// wavefront's outstanding tally atomics (vector loads retire in order on
+// gfx9, so a field read after a flight's adds would wait for all of them).
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2))) async_kernel(AsyncArgs A)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2)))
+async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
 {
     using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
@@ -345,10 +350,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH 
     const size_t stash_bytes = (size_t)A.wpb * L * A.link_bytes;
     unsigned long long *lacc = (unsigned long long *)(lds + stash_bytes);
     char *tl = lds + tabs_lds_offset(stash_bytes + (size_t)A.lacc_words * 8);
-    if constexpr (!BATCH) tabs_to_lds(A.probs[0], tl);
+    if constexpr (!BATCH) tabs_to_lds(probs[0], tl);
     // LDS block sums: pass B's per-(material, group) sums, or the bins of a small
     // energy-bin tally (single-problem launches)
-    EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
+    EvCtx cx{probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
              (MODE == MODE_FWD && A.lacc_words > 0) ? lacc : nullptr};
     if (A.lacc_words > 0) {
         lacc_zero(lacc, A.lacc_words);
@@ -395,7 +400,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH 
             Part p;
             if (act) {
                 int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
-                const ProbDev &P = A.probs[pi];
+                const ProbDev &P = probs[pi];
                 source<GEOM, MODE>(P, tabs_for<BATCH>(P, tl), p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
             }
             wc.outcomes(act, O_SOURCE);
@@ -471,18 +476,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH 
         int ne = EV_DEAD;
         uint32_t out = 0;
         if (act) {
-            const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
+            const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
             ne = run_event<GEOM, EMODE, MODE, SPLIT, EXT>(ev, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
         }
         wc.dispatch(act);
         wc.outcomes(act, out);
         W.template deposit<LAY, E>(act, ne, p, dig, wc, ln.err);
     }
-    flush_wave(A.ctl, wc, ln, A.probs, BATCH ? 0 : 1, MODE);
+    flush_wave(A.ctl, wc, ln, probs, BATCH ? 0 : 1, MODE);
     if (A.lacc_words > 0) {
         __syncthreads();
-        if (cx.lacc) lacc_flush(lacc, A.probs[0]);
-        if (cx.ltally) ltally_flush(lacc, A.probs[0], A.lacc_words);
+        if (cx.lacc) lacc_flush(lacc, probs[0]);
+        if (cx.ltally) ltally_flush(lacc, probs[0], A.lacc_words);
     }
 }
 
@@ -584,7 +589,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     st.block_threads = 64 * wpb;
     st.lds_bytes = (int)lds;
     tm.begin();
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, A);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(64 * wpb), lds, a.stream, A, a.probs);
     tm.end();
     st.launches += 2;
     st.rounds = 1;

@@ -142,8 +142,12 @@ __device__ __forceinline__ unsigned int event_chunks(const StackArgs &A, int set
     return c;
 }
 
+// The problem table is also passed as a read-only, unaliased kernel argument
+// so that loads from it can be scalar loads, which do not queue behind the
+// wavefront's outstanding tally atomics (vector loads retire in order).
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH || EMODE == EMODE_CE) ? 3 : 2))) stack_round(StackArgs A, int round)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH || EMODE == EMODE_CE) ? 3 : 2)))
+stack_round(StackArgs A, int round, const ProbDev *__restrict__ probs)
 {
     using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
@@ -171,10 +175,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH
         return;
     }
     // (a wavefront that returned above no longer takes part in block barriers)
-    if constexpr (!BATCH) tabs_to_lds(A.probs[0], tl);
+    if constexpr (!BATCH) tabs_to_lds(probs[0], tl);
     // LDS block sums: pass B's per-(material, group) sums, or the bins of a small
     // energy-bin tally (single-problem launches)
-    EvCtx cx{A.probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
+    EvCtx cx{probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
              (MODE == MODE_FWD && A.lacc_words > 0) ? lacc : nullptr};
     if (A.lacc_words > 0) {
         lacc_zero(lacc, A.lacc_words);
@@ -219,7 +223,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH
             for (int i = 0;;) {
                 uint32_t out = 0;
                 if (live) {
-                    const ProbDev &P = A.probs[BATCH ? (int)p.prob : 0];
+                    const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
                     ne = run_event<GEOM, EMODE, MODE, SPLIT, EXT>(cur, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
                 }
                 wc.dispatch(live);
@@ -257,7 +261,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH
             Part p;
             if (act) {
                 int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
-                const ProbDev &P = A.probs[pi];
+                const ProbDev &P = probs[pi];
                 source<GEOM, MODE>(P, tabs_for<BATCH>(P, tl), p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
             }
             wc.outcomes(act, O_SOURCE);
@@ -265,11 +269,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((BATCH
             push<LAY, E>(A, bout, set_out, home, act, EV_STEP, p, dig, ln.err);
         }
     }
-    flush_wave(A.ctl, wc, ln, A.probs, BATCH ? 0 : 1, MODE);
+    flush_wave(A.ctl, wc, ln, probs, BATCH ? 0 : 1, MODE);
     if (A.lacc_words > 0) {
         __syncthreads();
-        if (cx.lacc) lacc_flush(lacc, A.probs[0]);
-        if (cx.ltally) ltally_flush(lacc, A.probs[0], A.lacc_words);
+        if (cx.lacc) lacc_flush(lacc, probs[0]);
+        if (cx.ltally) ltally_flush(lacc, probs[0], A.lacc_words);
     }
 }
 
@@ -360,7 +364,7 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     auto queue_batch = [&](int slot) -> hipError_t {
         for (int i = 0; i < batch; ++i) {
             tm.begin();
-            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(block), lds, a.stream, A, round);
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(block), lds, a.stream, A, round, a.probs);
             tm.end();
             ++round;
             st.launches += 1;
