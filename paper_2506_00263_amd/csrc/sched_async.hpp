@@ -475,10 +475,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
         W.S.freem |= 1u << l;
         int ne = EV_DEAD;
         uint32_t out = 0;
-        if (act) {
-            const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
-            ne = run_event<GEOM, EMODE, MODE, SPLIT, EXT>(ev, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
-        }
+        if (act) ne = run_event_in<GEOM, EMODE, MODE, SPLIT, EXT, BATCH>(ev, probs, tl, cx, ln, p, out);
         wc.dispatch(act);
         wc.outcomes(act, out);
         W.template deposit<LAY, E>(act, ne, p, dig, wc, ln.err);

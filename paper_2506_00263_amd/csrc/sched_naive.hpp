@@ -45,10 +45,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) n
         while (__ballot(ev != EV_DEAD)) {
             bool alive = ev != EV_DEAD;
             uint32_t out = 0;
-            if (alive) {
-                const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
-                ev = ev_step<GEOM, EMODE, MODE, EXT>(P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
-            }
+            if (alive) ev = run_event_in<GEOM, EMODE, MODE, 0, EXT, BATCH>(EV_STEP, probs, tl, cx, ln, p, out);
             wc.dispatch(alive);
             wc.outcomes(alive, out);
         }

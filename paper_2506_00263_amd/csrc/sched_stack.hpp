@@ -222,10 +222,7 @@ stack_round(StackArgs A, int round, const ProbDev *__restrict__ probs)
             bool live = act;
             for (int i = 0;;) {
                 uint32_t out = 0;
-                if (live) {
-                    const ProbDev &P = probs[BATCH ? (int)p.prob : 0];
-                    ne = run_event<GEOM, EMODE, MODE, SPLIT, EXT>(cur, P, tabs_for<BATCH>(P, tl), cx, ln, p, out);
-                }
+                if (live) ne = run_event_in<GEOM, EMODE, MODE, SPLIT, EXT, BATCH>(cur, probs, tl, cx, ln, p, out);
                 wc.dispatch(live);
                 wc.outcomes(live, out);
                 if (++i >= K) break;

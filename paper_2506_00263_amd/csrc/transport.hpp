@@ -1015,6 +1015,30 @@ __device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long 
            (unsigned long long)first_lane_u32((uint32_t)v);
 }
 
+// Run one event for the active lanes with the problem record of each
+// particle.  Batched launches: when every active lane holds a particle of
+// the same problem (the common case: histories are sourced in consecutive
+// runs of ids) the record is read at a wave-uniform index, with scalar
+// loads that do not queue behind the wavefront's tally atomics; otherwise
+// per lane.  Call with only the active lanes executing.
+template <int GEOM, int EMODE, int MODE, int SPLIT, int EXT, bool BATCH>
+__device__ __forceinline__ int run_event_in(int ev, const ProbDev *__restrict__ probs, const char *tl,
+                                            const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
+{
+    if constexpr (!BATCH) {
+        const ProbDev &P = probs[0];
+        return run_event<GEOM, EMODE, MODE, SPLIT, EXT>(ev, P, tabs_for<false>(P, tl), cx, ln, p, out);
+    } else {
+        const uint32_t p0 = first_lane_u32(p.prob);
+        if (__ballot(p.prob != p0) == 0) {
+            const ProbDev &P = probs[p0];
+            return run_event<GEOM, EMODE, MODE, SPLIT, EXT>(ev, P, TabsG{P}, cx, ln, p, out);
+        }
+        const ProbDev &P = probs[p.prob];
+        return run_event<GEOM, EMODE, MODE, SPLIT, EXT>(ev, P, TabsG{P}, cx, ln, p, out);
+    }
+}
+
 __device__ __forceinline__ uint32_t lane_rank(uint64_t mask)
 {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
