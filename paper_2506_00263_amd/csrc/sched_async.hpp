@@ -332,12 +332,16 @@ struct AsyncWave {
 // stash; the block shares one LDS copy of the tables and one set of LDS
 // tally sums, which one-wavefront blocks would each hold (the occupancy cost
 // the paper attributes to per-warp stashes, Sec. 5.2).
+// Occupancy caps (waves per SIMD), measured on MI355X: single problems 2
+// (the event code keeps 160-175 registers live); batches 4, except split
+// batches 3 (a 256-problem batch: fused 10.9 ms at 4 against 11.7 at 3, split
+// 20.3 at 3 against 21.8 at 4).
 // The problem table is also passed as a read-only, unaliased kernel argument:
 // loads from it can then be scalar loads, which do not queue behind the
 // wavefront's outstanding tally atomics (vector loads retire in order on
 // gfx9, so a field read after a flight's adds would wait for all of them).
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? 4 : 2)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? (SPLIT ? 3 : 4) : 2)))
 async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
 {
     using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
