@@ -1,0 +1,131 @@
+"""GPU parity at the workloads' full sizes.
+
+The lattice (1e6 histories), the 256-problem batch, the multigroup
+backward at 1e6 histories and k-eigenvalue at 1e6 particles per cycle are
+compared with a complete oracle run, bin for bin.  The continuous-energy pin
+cell (1e6 and 1e7 histories) is too slow for the oracle to run whole, so
+every history's digest from the GPU is checked for a seeded sample of
+histories run one at a time by the oracle, and the bins, counters and
+digests must add up; all schedulers and both lookups must give the same
+integers.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_00263_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+INVARIANT = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks", "reflections",
+             "cutoffs", "killed", "pieces", "qsum", "overflow"]
+SCHEDS = [("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"), ("async", "split")]
+
+
+@pytest.fixture(scope="module")
+def mcx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2506_00263_amd import mcx as M
+    M.lib()
+    return M
+
+
+def _counts(got, ref, keys=INVARIANT):
+    for k in keys:
+        assert got[k] == ref[k], (k, got[k], ref[k])
+
+
+def _digest_run(mcx, P, n, **kw):
+    import torch
+    dg = torch.zeros(n * 24, dtype=torch.uint8, device="cuda")
+    P.run(digest=dg, **kw)
+    return dg.cpu().numpy().view(mcx.DIGEST_DTYPE)
+
+
+def test_lattice_1e6_every_scheduler(mcx, oracle):
+    d = inputs.cfg2_lattice(1_000_000)
+    ref = oracle.run(d)
+    P = mcx.Problem(d)
+    for sched, decomp in SCHEDS:
+        P.run(sched=sched, decomp=decomp)
+        assert np.array_equal(P.tallies(), ref["tally"]), (sched, decomp)
+        _counts(P.counters(), ref["counts"])
+
+
+@pytest.mark.parametrize("n_hist,n_ebins", [(1_000_000, 10_000), (10_000_000, 100)])
+def test_ce_pincell_sampled(mcx, oracle, n_hist, n_ebins):
+    d = inputs.pincell_ce(n_ebins=n_ebins, n_histories=n_hist)
+    P = mcx.Problem(d)
+    g = _digest_run(mcx, P, n_hist, sched="async", decomp="fused", lookup="hash")
+    tally = P.tallies()
+    c = P.counters()
+    assert int(tally.sum()) == c["qsum"] == int(g["qsum"].sum())
+    assert int(g["flights"].sum()) == c["flights"] and int(g["collisions"].sum()) == c["collisions"]
+    assert c["sourced"] == n_hist and c["overflow"] == 0
+    rng = np.random.default_rng(n_hist + n_ebins)
+    sample = np.concatenate([[0, n_hist - 1], np.sort(rng.choice(n_hist, size=400, replace=False))])
+    for h in sample:
+        ref = oracle.run(d, int(h), int(h) + 1, digest=True, threads=1)
+        assert ref["digest"][0] == g[h], h
+    if n_hist > 1_000_000:
+        return
+    # every scheduler and lookup gives the same integers
+    for sched, decomp in SCHEDS:
+        for lookup in ("binary", "hash"):
+            P.run(sched=sched, decomp=decomp, lookup=lookup)
+            assert np.array_equal(P.tallies(), tally), (sched, decomp, lookup)
+            _counts(P.counters(), c)
+
+
+def test_batch_256_problems(mcx, oracle):
+    probs = inputs.cfg5_batch()
+    assert len(probs) == 256
+    refs = [oracle.run(d) for d in probs]
+    P = mcx.Problem(probs)
+    for sched, decomp in (("async", "fused"), ("stack", "fused"), ("naive", "fused"), ("async", "split")):
+        P.run(sched=sched, decomp=decomp)
+        for k, ref in enumerate(refs):
+            assert np.array_equal(P.tallies(k), ref["tally"]), (sched, decomp, k)
+        c = P.counters()
+        for key in ("flights", "collisions", "qsum", "sourced"):
+            assert c[key] == sum(r["counts"][key] for r in refs), (sched, decomp, key)
+
+
+def test_batch_256_backward(mcx, oracle):
+    probs = inputs.cfg5_batch()
+    P = mcx.Problem(probs)
+    P.run(sched="async")
+    ws = [np.random.default_rng(50 + k).normal(size=inputs.n_bins(d)) for k, d in enumerate(probs)]
+    gt, gs = P.backward(np.concatenate(ws), problem=-1, sched="async")
+    off = 0
+    for d, w in zip(probs, ws):
+        ref = oracle.backward(d, w)
+        mg = d["n_mat"] * d["n_grp"]
+        assert np.array_equal(gt[off:off + mg], ref["grad_sigma_t"])
+        assert np.array_equal(gs[off:off + mg], ref["grad_sigma_s"])
+        off += mg
+
+
+def test_lattice_backward_1e6(mcx, oracle):
+    d = inputs.cfg2_lattice(1_000_000)
+    w = np.random.default_rng(11).normal(size=inputs.n_bins(d))
+    ref = oracle.backward(d, w)
+    P = mcx.Problem(d)
+    P.run(sched="async")
+    for sched, decomp in (("async", "fused"), ("stack", "split"), ("naive", "fused")):
+        gt, gs = P.backward(w, sched=sched, decomp=decomp)
+        assert np.array_equal(gt, ref["grad_sigma_t"]), (sched, decomp)
+        assert np.array_equal(gs, ref["grad_sigma_s"]), (sched, decomp)
+
+
+def test_eigen_1e6_per_cycle(mcx, oracle):
+    d = inputs.with_fission(inputs.cfg2_lattice(1))
+    ref = oracle.eigen(d, 1_000_000, 3, 1)
+    P = mcx.Problem(d)
+    for sched in ("async", "stack"):
+        got = P.run_eigen(1_000_000, 3, 1, sched=sched)
+        assert np.array_equal(got["k"], ref["k"]), sched
+        assert np.array_equal(got["n_source"], ref["n_source"]), sched
+        assert np.array_equal(P.tallies(), ref["tally"]), sched
+        _counts(P.counters(), ref["counts"], INVARIANT + ["fissions", "sites"])
