@@ -184,7 +184,10 @@ typedef struct {
     uint64_t n_histories;     /*   [first, first+n); n = 0 means all            */
     int64_t stack_capacity;   /* stack: particles per event stack               */
     int64_t stack_threshold;  /* stack: make_work stops above this fill         */
-    int32_t stash_links;      /* async: work links per wavefront stash          */
+    int32_t stash_links;      /* async: work links per wavefront stash (0 =
+                                 library default: one per event plus one,
+                                 plus one more for split events unless a
+                                 smaller stash keeps more wavefronts resident) */
     int32_t arena_links;      /* async: links in the global arena               */
     int32_t waves_per_cu;     /* stack/async: resident wavefronts per CU        */
     int32_t block_size;       /* naive: threads per block                       */
@@ -212,8 +215,10 @@ typedef struct {
     int32_t async_block_waves;/* async: wavefronts per block, 1, 2 or 4; each
                                  keeps its own stash, the block shares one LDS
                                  copy of the tables and tally sums (0 =
-                                 library default, 4; fewer when the block's
-                                 LDS would not fit)                           */
+                                 library default, 4; with stash_links 0, 2
+                                 with the smallest stash when that keeps more
+                                 wavefronts resident per CU; fewer when the
+                                 block's LDS would not fit)                   */
     int32_t reserved[1];
 } mcx_run_opts;
 

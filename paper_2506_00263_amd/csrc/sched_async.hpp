@@ -546,6 +546,26 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
         }
     }
     if (per_cu < 1) return hipErrorInvalidConfiguration;
+    // Default shape: two wavefronts per block with the smallest stash, when
+    // that keeps more wavefronts resident per CU than the default four (split
+    // events, whose stashes are large: 6 against 4 waves per CU on the
+    // lattice and the pin cell).  With large LDS tally sums four per block
+    // sharing them stay ahead, and fused events are register limited, so
+    // there the default stands.
+    auto capped = [&](int w) { return (a.waves_per_cu > 0 && a.waves_per_cu < w) ? a.waves_per_cu : w; };
+    if (a.async_block_waves == 0 && a.stash_links == 0 && wpb == 4) {
+        const int L2 = E + 1;
+        const size_t lds2 = tabs_lds_offset((size_t)2 * L2 * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
+        int per_cu2 = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, kern, 128, lds2);
+        if (e != hipSuccess) return e;
+        if (capped(2 * per_cu2) > capped(4 * per_cu)) {
+            wpb = 2;
+            L = L2;
+            lds = lds2;
+            per_cu = per_cu2;
+        }
+    }
     int wpc = per_cu * wpb;           // resident wavefronts per CU
     if (a.waves_per_cu > 0 && a.waves_per_cu < wpc) wpc = std::max(wpb, a.waves_per_cu / wpb * wpb);
     long blocks = (long)a.num_cus * (wpc / wpb);
