@@ -219,7 +219,11 @@ typedef struct {
                                  with the smallest stash when that keeps more
                                  wavefronts resident per CU; fewer when the
                                  block's LDS would not fit)                   */
-    int32_t reserved[1];
+    int32_t async_drain_events;/* async: once a wavefront has run out of full
+                                 links (source done, arena empty) a partly
+                                 filled link's particles run up to this many
+                                 events in place before they are packed again
+                                 (0 = library default, 8; 1 = one per pass)   */
 } mcx_run_opts;
 
 /* Tally paths (results are the same integers on every path):

@@ -687,6 +687,8 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
     if (o.async_block_waves != 0 && o.async_block_waves != 1 && o.async_block_waves != 2 &&
         o.async_block_waves != 4)
         return fail(h, MCX_E_INVALID_ARG, "async_block_waves must be 0, 1, 2 or 4");
+    if (o.async_drain_events < 0 || o.async_drain_events > 1024)
+        return fail(h, MCX_E_INVALID_ARG, "async_drain_events must be in [0, 1024]");
     if (o.tally_path < MCX_TALLY_PATH_AUTO || o.tally_path > MCX_TALLY_PATH_DIRECT)
         return fail(h, MCX_E_INVALID_ARG, "bad tally_path");
     if (o.tally_path == MCX_TALLY_PATH_LDS && h->hp[0].n_bins > LT_MAX_BINS)
@@ -761,6 +763,7 @@ static LaunchArgs launch_args(mcx_problem_t h, const mcx_run_opts &o, int mode, 
     a.stack_tail_events = o.stack_tail_events;
     a.stack_min_events = o.stack_min_events;
     a.async_block_waves = o.async_block_waves;
+    a.async_drain_events = o.async_drain_events;
     a.ws_query = nullptr;
     return a;
 }

@@ -79,6 +79,7 @@ struct LaunchArgs {
     int stack_tail_events;                 // stack: events per pop in the tail (0 = default)
     int stack_min_events;                  // stack: events per pop at least (0 = default 1)
     int async_block_waves;                 // async: wavefronts per block, 1, 2 or 4 (0 = ASYNC_BLOCK_WAVES)
+    int async_drain_events;                // async: events per pass on a drained wavefront's partial link (0 = default)
     size_t *ws_query;                      // non-null: only report the workspace bytes the launch
                                            // needs (nothing is allocated or launched)
 };
@@ -89,6 +90,7 @@ struct LaunchArgs {
 // 1.7x (fused) and 1.9x (split) faster, the box 1.2x and the 1e7 lattice 1.1x,
 // and changed the rest by a few percent either way.
 constexpr int ASYNC_BLOCK_WAVES = 4;
+constexpr int ASYNC_DRAIN_EVENTS = 8;
 
 struct LaunchStats {
     unsigned long long launches = 0, rounds = 0;

@@ -51,6 +51,7 @@ struct AsyncArgs {
     int consolidate;             // drained sparse stashes are handed to the arena and merged
     int tl_bytes;                // packed tables copied to LDS (single problem)
     int wpb;                     // wavefronts per block (each with its own stash)
+    int drain_events;            // events per pass on a drained wavefront's partial link
 };
 
 constexpr uint32_t NIL = 0xFFFFFFFFu;
@@ -377,9 +378,11 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
     bool src_done = false;
     bool may_donate = true;
     int idle = 0;
+    bool drained = false;                           // link l is a partial one of a drained stash
     unsigned long long res_next = 0, res_end = 0;   // reserved source ids
     for (;;) {
         int l = -1;
+        drained = false;
         if (W.S.readym) {
             l = __ffs(W.S.readym) - 1;
             W.S.readym &= ~(1u << l);
@@ -434,6 +437,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
                 if (tot > 0) {
                     l = W.S.partial(best);
                     W.S.set_partial(best, 0xff);
+                    drained = true;
                 } else {
                     // links may still be in flight to the arena; wait a bounded time
                     if (arena_fill(A) != 0 && !(ln.err & ERR_CAPACITY) && ++idle < A.spin_limit) {
@@ -445,6 +449,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
             } else if (tot > 0 && (tot >= DONATE_BELOW || !may_donate)) {
                 l = W.S.partial(best);
                 W.S.set_partial(best, 0xff);
+                drained = true;
             } else {
                 if (tot > 0) {
 #pragma unroll
@@ -470,7 +475,11 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
                 break;
             }
         }
-        // run the event of link l on its particles
+        // run the event of link l on its particles.  A drained wavefront's
+        // partial link has no full link to be packed with: its particles
+        // run up to drain_events events in place (their histories draw from
+        // their own keyed streams, so results do not change), which saves
+        // the unpack and pack of every event on the longest histories.
         int ev = W.S.ev(l);
         int c = W.S.cnt(l);
         bool act = lane < c;
@@ -478,10 +487,19 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
         if (act) get<LAY>(W.link(l), lane, p, dig);
         W.S.freem |= 1u << l;
         int ne = EV_DEAD;
-        uint32_t out = 0;
-        if (act) ne = run_event_in<GEOM, EMODE, MODE, SPLIT, EXT, BATCH>(ev, probs, tl, cx, ln, p, out);
-        wc.dispatch(act);
-        wc.outcomes(act, out);
+        const int K = drained ? A.drain_events : 1;
+        int cur = ev;
+        bool live = act;
+        for (int i = 0;;) {
+            uint32_t out = 0;
+            if (live) ne = run_event_in<GEOM, EMODE, MODE, SPLIT, EXT, BATCH>(cur, probs, tl, cx, ln, p, out);
+            wc.dispatch(live);
+            wc.outcomes(live, out);
+            if (++i >= K) break;
+            live = live && ne != EV_DEAD;
+            if (__ballot(live) == 0) break;
+            cur = ne;
+        }
         W.template deposit<LAY, E>(act, ne, p, dig, wc, ln.err);
     }
     flush_wave(A.ctl, wc, ln, probs, BATCH ? 0 : 1, MODE);
@@ -604,6 +622,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.consolidate = a.consolidate == 1 ? 1 : 0;   // off unless asked for
     A.tl_bytes = tl_bytes;
     A.wpb = wpb;
+    A.drain_events = a.async_drain_events > 0 ? a.async_drain_events : ASYNC_DRAIN_EVENTS;
     int ib = (std::max(n_arena, Q) + 255) / 256;
     hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A, (unsigned int)waves);
     st.grid_blocks = (int)blocks;

@@ -62,7 +62,7 @@ class RunOpts(C.Structure):
         ("waves_per_cu", C.c_int32), ("block_size", C.c_int32), ("hip_stream", C.c_void_p), ("digest", C.c_void_p),
         ("time_kernels", C.c_int32), ("force_spill", C.c_int32), ("consolidate", C.c_int32),
         ("stack_tail_events", C.c_int32), ("stack_min_events", C.c_int32), ("tally_path", C.c_int32),
-        ("async_block_waves", C.c_int32), ("reserved", C.c_int32 * 1),
+        ("async_block_waves", C.c_int32), ("async_drain_events", C.c_int32),
     ]
 
 
@@ -221,7 +221,8 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
 def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, first=0, n=0, stack_capacity=0,
              stack_threshold=0, stash_links=0, arena_links=0, waves_per_cu=0, block_size=0, stream=None,
              digest=None, time_kernels=False, force_spill=0, consolidate=0, stack_tail_events=0,
-             stack_min_events=0, tally_path="auto", async_block_waves=0) -> RunOpts:
+             stack_min_events=0, tally_path="auto", async_block_waves=0,
+             async_drain_events=0) -> RunOpts:
     o = RunOpts()
     o.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     o.decomp = DECOMP[decomp] if isinstance(decomp, str) else int(decomp)
@@ -243,6 +244,7 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
     o.stack_min_events = int(stack_min_events)
     o.tally_path = TALLY_PATH[tally_path] if isinstance(tally_path, str) else int(tally_path)
     o.async_block_waves = int(async_block_waves)
+    o.async_drain_events = int(async_drain_events)
     # async stash donation: None/"default" = library default, True/"on", False/"off"
     if isinstance(consolidate, bool):
         o.consolidate = 1 if consolidate else 2

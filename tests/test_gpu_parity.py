@@ -369,6 +369,45 @@ def test_async_block_waves(mcx, oracle, cfg1, cfg2, wpb):
         B.run(sched="async", async_block_waves=3)
 
 
+@pytest.mark.parametrize("k", [1, 3, 64])
+def test_async_drain_events(mcx, oracle, cfg1, cfg2, k):
+    # a drained wavefront runs its partial link's particles several events in
+    # place: same integers, digests and counters (events fused and split, with
+    # spills and consolidation, backward passes, weights, time bins, a batch)
+    for d, ref in (cfg1, cfg2):
+        P = mcx.Problem(d)
+        for decomp in ("fused", "split"):
+            dg = _digest(mcx, d["n_histories"])
+            P.run(sched="async", decomp=decomp, async_drain_events=k, digest=dg)
+            assert np.array_equal(P.tallies(), ref["tally"]), decomp
+            _check_counts(P.counters(), ref["counts"])
+            assert np.array_equal(_digest_np(dg, mcx), ref["digest"])
+            P.run(sched="async", decomp=decomp, async_drain_events=k, force_spill=3, stash_links=6, consolidate=1)
+            assert np.array_equal(P.tallies(), ref["tally"]), (decomp, "spills")
+    d = inputs.lattice_mg(n_histories=3000)
+    w = np.random.default_rng(5).normal(size=inputs.n_bins(d))
+    refb = oracle.backward(d, w)
+    R = mcx.Problem(d)
+    R.run(sched="async", async_drain_events=k)
+    for decomp in ("fused", "split"):
+        gt, gs = R.backward(w, sched="async", decomp=decomp, async_drain_events=k)
+        assert np.array_equal(gt, refb["grad_sigma_t"]) and np.array_equal(gs, refb["grad_sigma_s"])
+    dw = inputs.with_time_bins(inputs.with_implicit_capture(inputs.cfg2_lattice(4000)), 8, 60.0)
+    refw = oracle.run(dw)
+    W = mcx.Problem(dw)
+    for decomp in ("fused", "split"):
+        W.run(sched="async", decomp=decomp, async_drain_events=k)
+        assert np.array_equal(W.tallies(), refw["tally"]), decomp
+        _check_counts(W.counters(), refw["counts"])
+    probs = inputs.cfg5_batch(n_problems=10, hist_scale=0.02)
+    B = mcx.Problem(probs)
+    B.run(sched="async", decomp="split", async_drain_events=k)
+    for j, pd in enumerate(probs):
+        assert np.array_equal(B.tallies(j), oracle.run(pd)["tally"]), j
+    with pytest.raises(mcx.McxError):
+        B.run(sched="async", async_drain_events=-1)
+
+
 def test_workspace_size(mcx, cfg2):
     # the query allocates and launches nothing and follows the layouts: one
     # more async arena link costs one 64-particle link (64 x 64 bytes for the
