@@ -22,18 +22,19 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_autotune_cach
 
 
 def candidates(sched: str, decomp: str) -> list:
-    """Knob settings tried for one scheduler (0 = library default)."""
+    """Knob settings tried for one scheduler (0 = library default); the
+    first, with no knob set, is the library's own default choice."""
     events = 4 if decomp == "split" else 1
+    out = [dict()]
     if sched == "async":
-        out = []
-        for wpb in (4, 1):
+        for wpb in (4, 2, 1):
             for wpc in (0, 8):
                 for links in sorted({events + 1, events + 2, events + 3}):
                     out.append(dict(async_block_waves=wpb, waves_per_cu=wpc, stash_links=links))
         return out
     if sched == "stack":
-        return [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 256)]
-    return [dict(block_size=b) for b in (64, 128, 256)]
+        return out + [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 256)]
+    return out + [dict(block_size=b) for b in (64, 128, 256)]
 
 
 def problem_key(P: "mcx.Problem", sched: str, decomp: str, lookup: str, device: str) -> str:
