@@ -408,6 +408,22 @@ def test_async_drain_events(mcx, oracle, cfg1, cfg2, k):
         B.run(sched="async", async_drain_events=-1)
 
 
+def test_async_default_shape(mcx, cfg2):
+    # default launch shape: four wavefronts per block, or two with the
+    # smallest stash when that keeps more resident (split events on the
+    # lattice); explicit knobs are taken as given; results never change
+    d, ref = cfg2
+    P = mcx.Problem(d)
+    for decomp, kw, threads in (("fused", {}, 256), ("split", {}, 128), ("split", dict(async_block_waves=4), 256),
+                                ("split", dict(stash_links=6), 256), ("split", dict(async_block_waves=2), 128)):
+        P.run(sched="async", decomp=decomp, **kw)
+        c = P.counters()
+        assert c["block_threads"] == threads, (decomp, kw, c["block_threads"])
+        assert np.array_equal(P.tallies(), ref["tally"]), (decomp, kw)
+        _check_counts(c, ref["counts"])
+    assert P.workspace_size(sched="async", decomp="split") > 0
+
+
 def test_workspace_size(mcx, cfg2):
     # the query allocates and launches nothing and follows the layouts: one
     # more async arena link costs one 64-particle link (64 x 64 bytes for the
