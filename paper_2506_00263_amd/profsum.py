@@ -12,7 +12,7 @@ traffic per launch used by bench.py's roofline record.  Byte counters are
 scaled by what the same counter reads for the final 1 GiB device-to-device
 copy of the run (a kernel of known traffic).
 
-Usage: python -m paper_2506_00263_amd.profsum <dir> <out_dir> [--workload NAME]
+Usage: python -m paper_2506_00263_amd.profsum <dir> <out_dir> [--workload NAME] [--decomp split]
 """
 from __future__ import annotations
 
@@ -84,7 +84,7 @@ def kernel_stats(d: str, sched: str):
     return None
 
 
-def summarise(d: str, out_dir: str, workload: str) -> dict:
+def summarise(d: str, out_dir: str, workload: str, decomp: str = "fused") -> dict:
     src = build.source_hash()
     traffic = {}
     for sched, kern in KERNELS.items():
@@ -103,12 +103,13 @@ def summarise(d: str, out_dir: str, workload: str) -> dict:
         lines.append(f"Build source hash: `{src}`.  Commands (from the repository root):")
         lines.append("")
         lines.append("```")
+        dflag = "" if decomp == "fused" else f" --decomp {decomp}"
         lines.append(f"rocprofv3 --kernel-trace --stats -d <dir>/trace_{sched} -o run --output-format csv -- "
-                     f"python3 bench.py --sched {sched} --steps 5 --warmup 1 --no-extras --no-cpu")
+                     f"python3 bench.py --sched {sched}{dflag} --steps 5 --warmup 1 --no-extras --no-cpu")
         for p, cs in PASSES.items():
             lines.append(f"rocprofv3 --pmc {' '.join(cs)} -d <dir>/{p}_{sched} -o run --output-format csv -- "
-                         f"python3 bench.py --sched {sched} --steps 1 --warmup 1 --no-extras --no-cpu --copy-mib 1024")
-        lines.append(f"python3 -m paper_2506_00263_amd.profsum <dir> profiles")
+                         f"python3 bench.py --sched {sched}{dflag} --steps 1 --warmup 1 --no-extras --no-cpu --copy-mib 1024")
+        lines.append(f"python3 -m paper_2506_00263_amd.profsum <dir> profiles{dflag}")
         lines.append("```")
         lines.append("")
         if st:
@@ -150,7 +151,9 @@ def summarise(d: str, out_dir: str, workload: str) -> dict:
         if rd is not None and wr is not None:
             traffic[kern] = {"bytes_per_launch": rd + wr, "read": rd, "write": wr, "source_hash": src,
                              "workload": workload, "read_scale": rf, "write_scale": rw}
-    with open(os.path.join(out_dir, "traffic.json"), "w") as fh:
+    # the default (fused) figures are the ones bench.py reports
+    tname = "traffic.json" if decomp == "fused" else f"traffic_{decomp}.json"
+    with open(os.path.join(out_dir, tname), "w") as fh:
         json.dump(traffic, fh, indent=1, sort_keys=True)
     return traffic
 
@@ -159,9 +162,11 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("dir")
     ap.add_argument("out")
-    ap.add_argument("--workload", default="lattice_1e6")
+    ap.add_argument("--workload", default=None)
+    ap.add_argument("--decomp", default="fused", choices=["fused", "split"])
     a = ap.parse_args()
-    print(json.dumps(summarise(a.dir, a.out, a.workload), indent=1))
+    wl = a.workload or ("lattice_1e6" if a.decomp == "fused" else f"lattice_1e6_{a.decomp}")
+    print(json.dumps(summarise(a.dir, a.out, wl, a.decomp), indent=1))
 
 
 if __name__ == "__main__":
