@@ -15,6 +15,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -29,11 +30,62 @@ N_HIST = 1_000_000
 NEUTRON_SPEED = 1.383e6        # cm/s per sqrt(eV)
 
 
-def algorithmic_bytes(c: dict) -> int:
-    """Bytes the method itself must touch: one int64 tally update per scored
-    piece, Sigma_t per flight, Sigma_s and one transfer-CDF entry per
-    collision (8 bytes each)."""
-    return 8 * c["pieces"] + 8 * c["flights"] + 16 * c["collisions"]
+def algorithmic_bytes(c: dict, d: dict | None = None, lookup: str = "hash") -> float:
+    """Bytes the method itself must touch over a run with counters `c`: one
+    int64 tally update per scored piece (8 B); multigroup: Sigma_t per flight,
+    Sigma_s per collision and every transfer-CDF entry a scatter reads (8 B
+    each); continuous energy: one cross-section lookup per flight
+    (ce_lookup_bytes)."""
+    if d is not None and int(d.get("energy_mode", 0)) == 1:
+        return 8.0 * c["pieces"] + c["flights"] * ce_lookup_bytes(d, lookup)
+    return 8.0 * (c["pieces"] + c["flights"] + c["collisions"] + c["cdf_scans"])
+
+
+def ce_lookup_bytes(d: dict, lookup: str) -> float:
+    """Table bytes of one continuous-energy lookup, per species: the bracket
+    search (binary: ceil(log2(n-1)) probes of 8 B over the whole grid; hashed:
+    the 8-byte bin entry plus ceil(log2 width) probes, averaged over the hash
+    bins as the library builds them) and 48 B of interpolation (E, sigma_a,
+    sigma_s at both ends of the bracket)."""
+    S, n = int(d["n_species"]), int(d["grid_len"])
+    if lookup == "binary":
+        return S * (8.0 * math.ceil(math.log2(n - 1)) + 48.0)
+    g = np.asarray(d["e_grid"], np.float64).reshape(S, n)
+    M = int(d.get("hash_bins", 0) or 0) or max(64, n // 8)
+    lo, hi = math.log(g[:, 0].min()), math.log(g[:, -1].max())
+    inv = M / (hi - lo)
+    b = np.arange(M, dtype=np.float64)
+    e0, e1 = np.exp(lo + b / inv), np.exp(lo + (b + 1) / inv)
+    per = 0.0
+    for s in range(S):
+        lo_i = np.maximum(np.clip(np.searchsorted(g[s], e0, side="right") - 1, 0, n - 2) - 1, 0)
+        hi_i = np.minimum(np.clip(np.searchsorted(g[s], e1, side="right") - 1, 0, n - 2) + 2, n - 1)
+        probes = np.ceil(np.log2(np.maximum(hi_i - lo_i, 1)))
+        per += 8.0 + 8.0 * float(probes.mean()) + 48.0
+    return per
+
+
+def backward_bytes(c: dict, n_hist: int) -> float:
+    """Algorithmic bytes of the two replays of the score-function backward,
+    from the forward's counters of the same histories: pass A gathers dL/dT
+    per tally piece and writes G_h; both passes read Sigma_t per flight,
+    Sigma_s per collision and the CDF entries a scatter reads; pass B reads
+    G_h (the three per-(material, group) sums stay on chip)."""
+    replay = 8.0 * (c["flights"] + c["collisions"] + c["cdf_scans"])
+    return 8.0 * c["pieces"] + 2.0 * replay + 16.0 * n_hist
+
+
+def roofline_block(bytes_per_launch: float, mean_launch_ms: float, kernel: str, traffic=None, **extra) -> dict:
+    achieved = bytes_per_launch / (mean_launch_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "mean_launch_ms": mean_launch_ms, "bytes_per_launch": bytes_per_launch, **extra}
+
+
+def main_launches(c: dict, sched: str) -> int:
+    """Launches of the scheduler's main kernel in one run (the stack scheme
+    launches one per remapping round; the others one)."""
+    return int(c["rounds"]) if sched == "stack" else 1
 
 
 def measured_traffic(kernel: str):
@@ -297,18 +349,14 @@ def main():
     P = mcx.Problem(d)
     stream = torch.cuda.current_stream()
 
-    # headline: warmup, then exactly `steps` timed steps
+    # headline: warmup, then exactly `steps` timed steps (no per-launch
+    # events and no host reads inside the timed region)
     for _ in range(args.warmup):
         P.run(sched=args.sched, decomp=args.decomp, stream=stream)
     torch.cuda.synchronize()
-    kernel_ms = 0.0
-    launches = 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        P.run(sched=args.sched, decomp=args.decomp, stream=stream, time_kernels=True)
-        c = P.counters()
-        kernel_ms += c["kernel_ms"]
-        launches += c["rounds"] if args.sched == "stack" else 1
+        P.run(sched=args.sched, decomp=args.decomp, stream=stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
@@ -317,14 +365,18 @@ def main():
     tally = P.tallies()
 
     # roofline of the dominant kernel: algorithmic bytes per launch over the
-    # mean launch duration measured with HIP events on the run's stream
-    per_launch_bytes = algorithmic_bytes(c) / max(1, launches // args.steps)
-    mean_launch_ms = kernel_ms / max(1, launches)
-    achieved = per_launch_bytes / (mean_launch_ms * 1e-3) / 1e9
+    # mean launch duration, timed with HIP events on the run's stream over
+    # the same number of steps right after the timed region
+    kernel_ms, launches = 0.0, 0
+    for _ in range(args.steps):
+        P.run(sched=args.sched, decomp=args.decomp, stream=stream, time_kernels=True)
+        ck = P.counters()
+        kernel_ms += ck["kernel_ms"]
+        launches += main_launches(ck, args.sched)
+    torch.cuda.synchronize()
     kern = {"async": "async_kernel", "stack": "stack_round", "naive": "naive_kernel"}[args.sched]
-    roofline = {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(kern),
-                "kernel": kern, "mean_launch_ms": mean_launch_ms, "bytes_per_launch": per_launch_bytes}
+    roofline = roofline_block(algorithmic_bytes(c) / max(1, launches // args.steps), kernel_ms / max(1, launches),
+                              kern, measured_traffic(kern))
 
     out = {
         "metric": "particle histories/sec on 1 GPU (stack vs async TDR); backward/forward time ratio",
@@ -335,7 +387,7 @@ def main():
                                "51x51x20x7 mesh tally", "histories": N_HIST,
                    "scheduler": args.sched, "decomposition": args.decomp},
         "roofline": roofline,
-        "counters": {k: c[k] for k in ("flights", "collisions", "crossings", "pieces", "events", "lane_slots",
+        "counters": {k: c[k] for k in ("flights", "collisions", "cdf_scans", "crossings", "pieces", "events", "lane_slots",
                                        "dispatches", "spills", "refills", "rounds", "grid_blocks",
                                        "block_threads", "lds_bytes")},
         "active_lane_frac": c["events"] / max(1, c["lane_slots"]),
@@ -375,8 +427,14 @@ def main():
             P.backward(w, sched=args.sched, decomp=args.decomp)
             torch.cuda.synchronize()
             bwd.append(time.perf_counter() - t1)
+        P.run(sched=args.sched, decomp=args.decomp)
+        cf = P.counters()
+        P.backward(w, sched=args.sched, decomp=args.decomp, time_kernels=True)
+        cb = P.counters()
         out["backward"] = {"fwd_ms": 1e3 * float(np.median(fwd)), "bwd_ms": 1e3 * float(np.median(bwd)),
-                           "bwd_fwd_ratio": float(np.median(bwd) / np.median(fwd))}
+                           "bwd_fwd_ratio": float(np.median(bwd) / np.median(fwd)),
+                           "roofline": roofline_block(backward_bytes(cf, N_HIST), cb["kernel_ms"], kern + " x2",
+                                                      passes=2)}
         # batched: 256 problems of uneven size in one launch
         probs = inputs.cfg5_batch()
         B = mcx.Problem(probs)
@@ -390,15 +448,62 @@ def main():
                     knobs = autotune.tune(B, sched=s, decomp="fused", use_cache=False, reps=1)
                 B.run(sched=s, **knobs)
                 ts, kms = timed_runs(B, 3, sched=s, **knobs)
+                cc = B.counters()
+                bk = {"async": "async_kernel", "stack": "stack_round", "naive": "naive_kernel"}[s]
+                nl = main_launches(cc, s)
                 rec[label] = {"hist_per_s": nb / float(np.median(ts)), "ms": 1e3 * float(np.median(ts)),
-                              "knobs": knobs}
+                              "kernel_ms": float(np.median(kms)), "knobs": knobs,
+                              "roofline": roofline_block(algorithmic_bytes(cc) / nl, float(np.median(kms)) / nl, bk)}
                 t = [B.tallies(k) for k in range(len(probs))]
                 if bref is None:
                     bref = t
                 elif not all(np.array_equal(a, b) for a, b in zip(bref, t)):
                     raise SystemExit(f"batched tally mismatch: {s} {knobs}")
             bres[s] = rec
+        # batched backward (both replays, every problem), async
+        wb = np.concatenate([np.random.default_rng(k).normal(size=inputs.n_bins(p)) for k, p in enumerate(probs)])
+        B.run(sched="async")
+        cf = B.counters()
+        B.backward(wb, problem=-1, sched="async", time_kernels=True)
+        cb = B.counters()
+        bres["async_backward"] = {"kernel_ms": cb["kernel_ms"],
+                                  "roofline": roofline_block(backward_bytes(cf, nb), cb["kernel_ms"],
+                                                             "async_kernel x2", passes=2)}
         out["batched"] = {"problems": len(probs), "histories": nb, **bres}
+        # continuous-energy pin cell (3 species x 1e5-point tables in HBM):
+        # hashed and binary lookups, fused and split events, 1e6 and 1e7
+        # histories, every scheduler
+        ce = []
+        ce_cases = [(1_000_000, 100, "hash"), (1_000_000, 10000, "hash"), (1_000_000, 100, "binary"),
+                    (10_000_000, 100, "hash")]
+        ce_ref = {}
+        for n_ce, bins, lookup in ce_cases:
+            dce = inputs.cfg3_pincell(n_ebins=bins, n_histories=n_ce)
+            Q = mcx.Problem(dce)
+            per_lookup = ce_lookup_bytes(dce, lookup)
+            for s, dc in (("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"),
+                          ("async", "split")):
+                Q.run(sched=s, decomp=dc, lookup=lookup)
+                ts, kms = timed_runs(Q, 2, sched=s, decomp=dc, lookup=lookup)
+                cc = Q.counters()
+                key = (n_ce, bins)
+                tq = Q.tallies()
+                if key not in ce_ref:
+                    ce_ref[key] = tq
+                elif not np.array_equal(ce_ref[key], tq):
+                    raise SystemExit(f"CE tally mismatch: {n_ce} {bins} {lookup} {s}/{dc}")
+                bk = {"async": "async_kernel", "stack": "stack_round", "naive": "naive_kernel"}[s]
+                nl = main_launches(cc, s)
+                ce.append({"histories": n_ce, "bins": bins, "lookup": lookup, "sched": s, "decomp": dc,
+                           "ms": 1e3 * float(np.median(ts)), "hist_per_s": n_ce / float(np.median(ts)),
+                           "kernel_ms": float(np.median(kms)), "flights": cc["flights"],
+                           "lookup_bytes": per_lookup,
+                           "roofline": roofline_block(algorithmic_bytes(cc, dce, lookup) / nl,
+                                                      float(np.median(kms)) / nl, bk)})
+                print("bench pincell_ce", {k: v for k, v in ce[-1].items() if k != "roofline"},
+                      ce[-1]["roofline"]["frac"], file=sys.stderr, flush=True)
+            del Q
+        out["pincell_ce"] = ce
         # k-eigenvalue: the lattice with synthetic fission, 1e6 particles per
         # cycle, 24 cycles (6 inactive), default knobs
         E = mcx.Problem(inputs.with_fission(inputs.cfg2_lattice(1)))
@@ -426,7 +531,7 @@ def main():
         from oracle import oracle as O
         threads = min(16, os.cpu_count() or 1)
         reps, cpu_s, ref = 0, 0.0, None
-        while cpu_s < 5.0 and reps < 50:
+        while cpu_s < 10.0 and reps < 100:
             t1 = time.perf_counter()
             ref = O.run(d, threads=threads)
             cpu_s += time.perf_counter() - t1

@@ -224,6 +224,15 @@ typedef struct {
                                  filled link's particles run up to this many
                                  events in place before they are packed again
                                  (0 = library default, 8; 1 = one per pass)   */
+    void *workspace;          /* optional caller-owned device memory (on the
+                                 handle's device, 256-byte aligned) of ws_bytes
+                                 bytes for the run's scheduler state and tally
+                                 replicas (mcx_run, mcx_backward); the library
+                                 then allocates no scratch of its own for it.
+                                 Too small (see mcx_workspace_size):
+                                 MCX_E_INVALID_ARG before anything runs.  NULL:
+                                 the handle's own workspace, grown on demand. */
+    size_t ws_bytes;
 } mcx_run_opts;
 
 /* Tally paths (results are the same integers on every path):
@@ -244,7 +253,9 @@ typedef struct {
     uint32_t pad;
 } mcx_digest;
 
-/* totals of the last run (forward or backward pass) */
+/* totals of the last run.  After mcx_backward: the events of its second
+ * replay (pass B), with launches, rounds and kernel_ms summed over both
+ * replays. */
 typedef struct {
     uint64_t sourced, flights, collisions, scatters, absorbs, crossings;
     uint64_t leaks, reflections, cutoffs, killed, pieces, qsum;
@@ -264,6 +275,8 @@ typedef struct {
     uint64_t fissions;        /* k-eigenvalue runs: fissions (all cycles)       */
     uint64_t sites;           /*   and neutrons banked                          */
     uint64_t roulettes;       /* histories ended by weight roulette             */
+    uint64_t cdf_scans;       /* multigroup scatters: transfer-CDF entries read
+                                 to find the outgoing group (k + 1 for group k) */
 } mcx_counters_t;
 
 /* k-eigenvalue power iteration (the multigroup workload of Sec. 4 of the
@@ -329,10 +342,12 @@ mcx_status mcx_backward(mcx_problem_t p, int32_t problem, const double *dL_dT, d
  * are filled; mcx_backward does not apply to it. */
 mcx_status mcx_run_eigen(mcx_problem_t p, const mcx_run_opts *opts, const mcx_eigen_opts *eig);
 
-/* Device scratch (bytes) that mcx_run with these options would allocate
- * for its scheduler state (stack banks and counters, or the async link
- * arena) and tally replicas; 0 for the naive scheduler.  The library grows
- * its own workspace to this size on the first such run and keeps it. */
+/* Device scratch (bytes) that mcx_run, and mcx_backward after it, with
+ * these options need for their scheduler state (stack banks and counters,
+ * or the async link arena) and tally replicas: the smallest opts.workspace
+ * they accept.  0 for the naive scheduler without replicas.  Without a
+ * caller workspace the library grows its own to this size and keeps it.
+ * Allocates and launches nothing. */
 mcx_status mcx_workspace_size(mcx_problem_t p, const mcx_run_opts *opts, size_t *bytes);
 
 mcx_status mcx_counters(mcx_problem_t p, mcx_counters_t *out);

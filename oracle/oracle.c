@@ -687,6 +687,7 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                 for (int32_t k = 0; k < p->n_grp; ++k) {
                     if (c2 < row[k]) { gn = k; break; }
                 }
+                cnt->cdf_scans += (uint64_t)gn + 1;
                 g = gn;
                 orc_isotropic(c3, c4, dir);
             } else {
@@ -874,7 +875,7 @@ int orc_eigen(const orc_problem *p, uint64_t N, int32_t n_cycles, int32_t n_inac
         total.absorbs += local.absorbs; total.crossings += local.crossings; total.leaks += local.leaks;
         total.reflections += local.reflections; total.cutoffs += local.cutoffs; total.killed += local.killed;
         total.pieces += local.pieces; total.fissions += local.fissions; total.sites += local.sites;
-        total.roulettes += local.roulettes;
+        total.roulettes += local.roulettes; total.cdf_scans += local.cdf_scans;
         total.qsum = q_before + acc.qsum_total;
         if (acc.overflow || total.qsum < q_before || total.qsum >= 0x8000000000000000ull) total.overflow = 1;
         /* the bank: each history's neutrons in history order */

@@ -101,6 +101,8 @@ typedef struct {              /* totals over a run (scheduler invariant)   */
     uint64_t overflow;        /* 1 if the total of all q reached 2^63       */
     uint64_t fissions, sites; /* k-eigenvalue runs: fissions, neutrons banked */
     uint64_t roulettes;       /* histories ended by weight roulette          */
+    uint64_t cdf_scans;       /* multigroup scatters: transfer-CDF entries read
+                                 to find the outgoing group (k + 1 for group k) */
 } orc_counts;
 
 /* primitives, exposed for tests */

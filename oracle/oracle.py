@@ -61,7 +61,8 @@ class OrcDigest(C.Structure):
 DIGEST_DTYPE = np.dtype([("qsum", "<i8"), ("flights", "<u4"), ("collisions", "<u4"),
                          ("fate", "<u4"), ("pad", "<u4")])
 COUNT_NAMES = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks",
-               "reflections", "cutoffs", "killed", "pieces", "qsum", "overflow", "fissions", "sites", "roulettes"]
+               "reflections", "cutoffs", "killed", "pieces", "qsum", "overflow", "fissions", "sites", "roulettes",
+               "cdf_scans"]
 
 
 class OrcCounts(C.Structure):

@@ -64,7 +64,10 @@ struct mcx_problem_s {
     unsigned int *h_flag = nullptr;       // pinned
     RunCtl *h_ctl = nullptr;              // pinned
     Workspace ws;
+    hipEvent_t poll[2] = {nullptr, nullptr};   // stack scheduler: batch-of-rounds events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> timer_events;   // reused by LaunchTimer
+    std::vector<unsigned long long> run_prefix;   // [n + 1], reused by every pass
+    std::vector<uint64_t> run_first, run_count;   // [n], reused by mcx_run
     // k-eigenvalue buffers (grown on demand): source banks (ping-pong), per
     // history banked count and fission site, the cycle's sites, scan tiles,
     // a tally for the inactive cycles, device and pinned host totals
@@ -455,6 +458,10 @@ static mcx_status upload(mcx_problem_t h)
     HIP_TRY(h, hipMalloc(&h->d_ctl, sizeof(RunCtl)));
     HIP_TRY(h, hipHostMalloc((void **)&h->h_flag, 64, hipHostMallocDefault));
     HIP_TRY(h, hipHostMalloc((void **)&h->h_ctl, sizeof(RunCtl), hipHostMallocDefault));
+    for (hipEvent_t &ev : h->poll) HIP_TRY(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    h->run_prefix.assign(h->n + 1, 0);
+    h->run_first.assign(h->n, 0);
+    h->run_count.assign(h->n, 0);
     // host image of the problem table (static part)
     char *base = (char *)h->blob;
     h->pd.resize(h->n);
@@ -607,6 +614,8 @@ extern "C" void mcx_destroy_problem(mcx_problem_t h)
         hipEventDestroy(ev.first);
         hipEventDestroy(ev.second);
     }
+    for (hipEvent_t ev : h->poll)
+        if (ev) hipEventDestroy(ev);
     if (h->d_ctl) hipFree(h->d_ctl);
     if (h->d_G) hipFree(h->d_G);
     if (h->d_w) hipFree(h->d_w);
@@ -661,6 +670,7 @@ extern "C" mcx_status mcx_set_xs(mcx_problem_t h, int32_t problem, const double 
 hipError_t mcx::ws_reserve(Workspace &ws, size_t bytes)
 {
     if (ws.bytes >= bytes) return hipSuccess;
+    if (ws.fixed) return hipErrorInvalidValue;   // never reallocated (sizes are checked before)
     if (ws.ptr) {
         hipError_t e = hipFree(ws.ptr);
         if (e != hipSuccess) return e;
@@ -689,6 +699,9 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
         return fail(h, MCX_E_INVALID_ARG, "async_block_waves must be 0, 1, 2 or 4");
     if (o.async_drain_events < 0 || o.async_drain_events > 1024)
         return fail(h, MCX_E_INVALID_ARG, "async_drain_events must be in [0, 1024]");
+    if (o.workspace && ((uintptr_t)o.workspace % 256) != 0)
+        return fail(h, MCX_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (o.workspace && o.ws_bytes == 0) return fail(h, MCX_E_INVALID_ARG, "workspace given with ws_bytes 0");
     if (o.tally_path < MCX_TALLY_PATH_AUTO || o.tally_path > MCX_TALLY_PATH_DIRECT)
         return fail(h, MCX_E_INVALID_ARG, "bad tally_path");
     if (o.tally_path == MCX_TALLY_PATH_LDS && h->hp[0].n_bins > LT_MAX_BINS)
@@ -765,15 +778,52 @@ static LaunchArgs launch_args(mcx_problem_t h, const mcx_run_opts &o, int mode, 
     a.async_block_waves = o.async_block_waves;
     a.async_drain_events = o.async_drain_events;
     a.ws_query = nullptr;
+    a.poll[0] = h->poll[0];
+    a.poll[1] = h->poll[1];
     return a;
 }
 
-// One pass over the run's histories with the given mode.
+static hipError_t launch_sched(const mcx_run_opts &o, const LaunchArgs &a, Workspace &ws, LaunchStats &st,
+                               LaunchTimer &tm, unsigned int *host_flag)
+{
+    if (o.sched == MCX_SCHED_NAIVE) return launch_naive(a, st, tm);
+    if (o.sched == MCX_SCHED_STACK) return launch_stack(a, ws, st, tm, host_flag);
+    return launch_async(a, ws, st, tm);
+}
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Device scratch of one pass: the scheduler's state (stack banks and
+// counters, or the async link arena), then, 256-byte aligned, the tally
+// replicas when the pass adds into them.
+static mcx_status scratch_bytes(mcx_problem_t h, const mcx_run_opts &o, const LaunchArgs &a, int path,
+                                size_t &sched_bytes, size_t &total_bytes)
+{
+    LaunchArgs q = a;
+    size_t need = 0;
+    q.ws_query = &need;
+    LaunchStats st;
+    LaunchTimer tm;
+    Workspace none;
+    hipError_t e = a.total > 0 ? launch_sched(o, q, none, st, tm, h->h_flag) : hipSuccess;
+    if (e != hipSuccess) return hip_fail(h, e, "workspace query");
+    sched_bytes = need;
+    total_bytes = need;
+    if (path == MCX_TALLY_PATH_REPLICAS) total_bytes = align256(need) + (size_t)TREP * (size_t)h->hp[0].n_bins * 8;
+    return MCX_OK;
+}
+
+// One pass over the run's histories with the given mode.  `fixed` (or null)
+// is device scratch that the pass must fit in and never reallocates: the
+// caller's workspace or the library's static scratch; without it the handle's
+// own workspace and replicas grow as needed.
 static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, const std::vector<uint64_t> &first,
-                           const std::vector<uint64_t> &count, void *digest, unsigned int *err_out)
+                           const std::vector<uint64_t> &count, void *digest, unsigned int *err_out,
+                           Workspace *fixed = nullptr)
 {
     hipStream_t stream = (hipStream_t)o.hip_stream;
-    std::vector<unsigned long long> prefix(h->n + 1, 0);
+    std::vector<unsigned long long> &prefix = h->run_prefix;
+    prefix[0] = 0;
     for (int k = 0; k < h->n; ++k) {
         ProbDev &P = h->pd[k];
         P.first = first[k];
@@ -786,7 +836,23 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     unsigned long long total = prefix[h->n];
     const int path = tally_path(h, o, mode);
     const bool use_trep = path == MCX_TALLY_PATH_REPLICAS;
-    if (use_trep) {
+    LaunchArgs a = launch_args(h, o, mode, total, path, digest);
+    Workspace *ws = &h->ws;
+    unsigned long long *trep = nullptr;
+    if (fixed) {
+        size_t sched_b = 0, total_b = 0;
+        mcx_status s = scratch_bytes(h, o, a, path, sched_b, total_b);
+        if (s != MCX_OK) return s;
+        if (total_b > fixed->bytes)
+            return fail(h, MCX_E_INVALID_ARG, "the run needs %zu bytes of device scratch; the workspace holds %zu",
+                        total_b, fixed->bytes);
+        ws = fixed;
+        if (use_trep) trep = (unsigned long long *)((char *)fixed->ptr + align256(sched_b));
+    }
+    if (use_trep && fixed) {
+        HIP_TRY(h, hipMemsetAsync(trep, 0, (size_t)TREP * (size_t)h->hp[0].n_bins * 8, stream));
+        h->pd[0].trep = trep;
+    } else if (use_trep) {
         size_t words = (size_t)TREP * (size_t)h->hp[0].n_bins;
         if (h->trep_words < words) {
             if (h->d_trep) HIP_TRY(h, hipFree(h->d_trep));
@@ -806,8 +872,6 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     ctl.total = total;
     HIP_TRY(h, hipMemcpyAsync(h->d_ctl, &ctl, sizeof ctl, hipMemcpyHostToDevice, stream));
 
-    LaunchArgs a = launch_args(h, o, mode, total, path, digest);
-
     LaunchStats st;
     LaunchTimer tm;
     tm.on = o.time_kernels != 0;
@@ -815,13 +879,11 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     tm.pool = &h->timer_events;
     hipError_t e = hipSuccess;
     if (total > 0) {
-        if (o.sched == MCX_SCHED_NAIVE) e = launch_naive(a, st, tm);
-        else if (o.sched == MCX_SCHED_STACK) e = launch_stack(a, h->ws, st, tm, h->h_flag);
-        else e = launch_async(a, h->ws, st, tm);
+        e = launch_sched(o, a, *ws, st, tm, h->h_flag);
         if (e == hipSuccess && use_trep) {
             int n = (int)h->hp[0].n_bins;
             hipLaunchKernelGGL(trep_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                               h->pd[0].tally, (const unsigned long long *)h->d_trep, n, TREP);
+                               h->pd[0].tally, (const unsigned long long *)h->pd[0].trep, n, TREP);
             e = hipGetLastError();
         }
     }
@@ -862,6 +924,7 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     c.make_work = tot[C_MAKE_WORK];
     c.fissions = tot[C_FISSIONS];
     c.roulettes = tot[C_ROULETTES];
+    c.cdf_scans = tot[C_CDF];
     c.rounds = st.rounds;
     c.launches = st.launches;
     c.kernel_ms = tm.total_ms();
@@ -877,19 +940,16 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     return MCX_OK;
 }
 
-extern "C" mcx_status mcx_run(mcx_problem_t h, const mcx_run_opts *opts)
+// The history range of a forward run: per problem [first, first + count).
+static mcx_status run_range(mcx_problem_t h, const mcx_run_opts &o, std::vector<uint64_t> &first,
+                            std::vector<uint64_t> &count)
 {
-    if (!h || !opts) return MCX_E_INVALID_ARG;
-    const mcx_run_opts &o = *opts;
-    mcx_status s = check_opts(h, o);
-    if (s != MCX_OK) return s;
-    std::vector<uint64_t> first(h->n), count(h->n);
     if (h->n == 1) {
         uint64_t N = h->hp[0].d.n_histories;
         if (o.first_history > N) return fail(h, MCX_E_INVALID_ARG, "first_history beyond n_histories");
         first[0] = o.first_history;
         count[0] = o.n_histories ? o.n_histories : N - o.first_history;
-        if (first[0] + count[0] > N) return fail(h, MCX_E_INVALID_ARG, "history range beyond n_histories");
+        if (count[0] > N - first[0]) return fail(h, MCX_E_INVALID_ARG, "history range beyond n_histories");
     } else {
         if (o.first_history || o.n_histories)
             return fail(h, MCX_E_INVALID_ARG, "history ranges apply to single-problem handles only");
@@ -898,12 +958,22 @@ extern "C" mcx_status mcx_run(mcx_problem_t h, const mcx_run_opts *opts)
             count[k] = h->hp[k].d.n_histories;
         }
     }
+    return MCX_OK;
+}
+
+// A forward run into the handle's tallies; `fixed`: device scratch the run
+// must fit in (never reallocated), or null for the handle's own.
+static mcx_status forward(mcx_problem_t h, const mcx_run_opts &o, Workspace *fixed)
+{
+    std::vector<uint64_t> &first = h->run_first, &count = h->run_count;
+    mcx_status s = run_range(h, o, first, count);
+    if (s != MCX_OK) return s;
     h->tallies_valid = false;
     h->have_forward = false;
     if (!o.accumulate)
         HIP_TRY(h, hipMemsetAsync(h->d_tally, 0, std::max<size_t>(h->total_bins, 1) * 8, (hipStream_t)o.hip_stream));
     unsigned int err = 0;
-    s = run_pass(h, o, MODE_FWD, first, count, o.digest, &err);
+    s = run_pass(h, o, MODE_FWD, first, count, o.digest, &err, fixed);
     if (s != MCX_OK) return s;
     if (err & ERR_OVERFLOW) return fail(h, MCX_E_OVERFLOW, "fixed-point tally total reached 2^63");
     h->tallies_valid = true;
@@ -911,6 +981,26 @@ extern "C" mcx_status mcx_run(mcx_problem_t h, const mcx_run_opts *opts)
     h->last_first = first;
     h->last_count = count;
     return MCX_OK;
+}
+
+// the caller's workspace of a run's options, if it gave one
+static Workspace *caller_ws(const mcx_run_opts &o, Workspace &w)
+{
+    if (!o.workspace) return nullptr;
+    w.ptr = o.workspace;
+    w.bytes = o.ws_bytes;
+    w.fixed = true;
+    return &w;
+}
+
+extern "C" mcx_status mcx_run(mcx_problem_t h, const mcx_run_opts *opts)
+{
+    if (!h || !opts) return MCX_E_INVALID_ARG;
+    const mcx_run_opts &o = *opts;
+    mcx_status s = check_opts(h, o);
+    if (s != MCX_OK) return s;
+    Workspace w;
+    return forward(h, o, caller_ws(o, w));
 }
 
 // grow a device buffer to at least `count` elements (contents not kept)
@@ -954,6 +1044,7 @@ extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, c
     if (eig->n_cycles < 1 || eig->n_inactive < 0 || eig->n_inactive > eig->n_cycles)
         return fail(h, MCX_E_INVALID_ARG, "need n_cycles >= 1 and 0 <= n_inactive <= n_cycles");
     if (!eig->k_cycle || !eig->n_source) return fail(h, MCX_E_INVALID_ARG, "null k_cycle or n_source");
+    if (o.workspace) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs use the library's own workspace");
     o.digest = nullptr;
     o.first_history = 0;
     o.n_histories = 0;
@@ -1015,6 +1106,7 @@ extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, c
         sum.refills += pc.refills; sum.make_work += pc.make_work; sum.rounds += pc.rounds;
         sum.launches += pc.launches; sum.kernel_ms += pc.kernel_ms; sum.fissions += pc.fissions;
         sum.roulettes += pc.roulettes;
+        sum.cdf_scans += pc.cdf_scans;
         sum.grid_blocks = pc.grid_blocks; sum.block_threads = pc.block_threads; sum.lds_bytes = pc.lds_bytes;
         qsum += pc.qsum;
         // the bank: each history's neutrons, in history order
@@ -1117,9 +1209,13 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
         h->pd[k].gscale = 1.0;
     }
     unsigned int err = 0;
-    s = run_pass(h, o, MODE_REPLAY_A, first, count, nullptr, &err);
+    Workspace w;
+    Workspace *fixed = caller_ws(o, w);
+    s = run_pass(h, o, MODE_REPLAY_A, first, count, nullptr, &err, fixed);
     if (s != MCX_OK) return s;
     if (err & ERR_BOUND) return fail(h, MCX_E_OVERFLOW, "score-function bound does not fit 64 bits");
+    const double ms_a = h->counters.kernel_ms;
+    const uint64_t launches_a = h->counters.launches, rounds_a = h->counters.rounds;
     std::vector<unsigned long long> acc(h->gacc_words);
     HIP_TRY(h, hipMemcpy(acc.data(), h->d_gacc, h->gacc_words * 8, hipMemcpyDeviceToHost));
     if (h->n == 1) acc[h->gacc_off[0]] += h->passa_u;   // single-problem runs sum U per wavefront
@@ -1128,8 +1224,11 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
         scale[k] = 62 - bit_length(acc[h->gacc_off[k]]);
         h->pd[k].gscale = std::ldexp(1.0, scale[k]);
     }
-    s = run_pass(h, o, MODE_REPLAY_B, first, count, nullptr, &err);
+    s = run_pass(h, o, MODE_REPLAY_B, first, count, nullptr, &err, fixed);
     if (s != MCX_OK) return s;
+    h->counters.kernel_ms += ms_a;
+    h->counters.launches += launches_a;
+    h->counters.rounds += rounds_a;
     HIP_TRY(h, hipMemcpy(acc.data(), h->d_gacc, h->gacc_words * 8, hipMemcpyDeviceToHost));
     // gradients: grad Sigma_t = (-SL + SA/Sigma_a) 2^-s / N, grad Sigma_s = (SS/Sigma_s - SA/Sigma_a) 2^-s / N
     std::vector<double> gt, gs;
@@ -1161,28 +1260,25 @@ extern "C" mcx_status mcx_workspace_size(mcx_problem_t h, const mcx_run_opts *op
     const mcx_run_opts &o = *opts;
     mcx_status s = check_opts(h, o);
     if (s != MCX_OK) return s;
+    std::vector<uint64_t> first(h->n), count(h->n);
+    s = run_range(h, o, first, count);
+    if (s != MCX_OK) return s;
     unsigned long long total = 0;
-    if (h->n == 1) {
-        uint64_t N = h->hp[0].d.n_histories;
-        if (o.first_history > N) return fail(h, MCX_E_INVALID_ARG, "first_history beyond n_histories");
-        total = o.n_histories ? o.n_histories : N - o.first_history;
-    } else {
-        for (int k = 0; k < h->n; ++k) total += h->hp[k].d.n_histories;
-    }
-    const int path = tally_path(h, o, MODE_FWD);
-    LaunchArgs a = launch_args(h, o, MODE_FWD, total, path, o.digest);
+    for (int k = 0; k < h->n; ++k) total += count[k];
+    // forward, and the backward's two replays where the handle has them
+    bool replays = h->emode == MCX_MG;
+    for (int k = 0; k < h->n; ++k)
+        if (h->hp[k].d.implicit_capture) replays = false;
     size_t need = 0;
-    a.ws_query = &need;
-    LaunchStats st;
-    LaunchTimer tm;
-    hipError_t e = hipSuccess;
-    if (total > 0) {
-        if (o.sched == MCX_SCHED_NAIVE) e = launch_naive(a, st, tm);
-        else if (o.sched == MCX_SCHED_STACK) e = launch_stack(a, h->ws, st, tm, h->h_flag);
-        else e = launch_async(a, h->ws, st, tm);
+    for (int mode : {MODE_FWD, MODE_REPLAY_A, MODE_REPLAY_B}) {
+        if (mode != MODE_FWD && !replays) continue;
+        const int path = tally_path(h, o, mode);
+        LaunchArgs a = launch_args(h, o, mode, total, path, mode == MODE_FWD ? o.digest : nullptr);
+        size_t sched_b = 0, b = 0;
+        s = scratch_bytes(h, o, a, path, sched_b, b);
+        if (s != MCX_OK) return s;
+        need = std::max(need, b);
     }
-    if (e != hipSuccess) return hip_fail(h, e, "workspace query");
-    if (path == MCX_TALLY_PATH_REPLICAS) need += (size_t)TREP * (size_t)h->hp[0].n_bins * 8;
     *bytes = need;
     return MCX_OK;
 }

@@ -82,6 +82,8 @@ struct LaunchArgs {
     int async_drain_events;                // async: events per pass on a drained wavefront's partial link (0 = default)
     size_t *ws_query;                      // non-null: only report the workspace bytes the launch
                                            // needs (nothing is allocated or launched)
+    hipEvent_t poll[2];                    // stack: two events (timing off) owned by the handle,
+                                           // recorded behind each batch of rounds
 };
 
 // Default wavefronts per asynchronous block.  Measured on MI355X (1e6
@@ -97,10 +99,13 @@ struct LaunchStats {
     int grid_blocks = 0, block_threads = 0, lds_bytes = 0;
 };
 
-// Device scratch owned by a problem handle, grown on demand.
+// Device scratch of a run: owned by the problem handle and grown on demand,
+// or, when `fixed`, memory of a given size that is never reallocated (a
+// caller's workspace or the library's static scratch).
 struct Workspace {
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool fixed = false;
 };
 
 hipError_t ws_reserve(Workspace &ws, size_t bytes);

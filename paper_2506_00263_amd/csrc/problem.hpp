@@ -104,7 +104,7 @@ constexpr long long TREP_MAX_BINS = 1ll << 24;
 enum Counter : int {
     C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,
     C_CUTOFFS, C_KILLED, C_PIECES, C_EVENTS, C_LANE_SLOTS, C_DISPATCHES, C_SPILLS, C_REFILLS, C_MAKE_WORK,
-    C_FISSIONS, C_ROULETTES, C_COMPLETED, C_QSUM, C_PASSA_U, C_NUM
+    C_FISSIONS, C_ROULETTES, C_COMPLETED, C_QSUM, C_PASSA_U, C_CDF, C_NUM
 };
 constexpr int C_WAVE = C_COMPLETED;   // entries counted per wavefront (32-bit)
 

@@ -348,14 +348,7 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     // event; the host queues the next batch before it waits for the
     // previous batch's words, so the device never idles on a poll.  A batch
     // queued past the last round costs only its early exits.
-    hipEvent_t polled[2];
-    e = hipEventCreateWithFlags(&polled[0], hipEventDisableTiming);
-    if (e != hipSuccess) return e;
-    e = hipEventCreateWithFlags(&polled[1], hipEventDisableTiming);
-    if (e != hipSuccess) {
-        hipEventDestroy(polled[0]);
-        return e;
-    }
+    const hipEvent_t *polled = a.poll;
     int round = 0;
     const int batch = 8;
     auto queue_batch = [&](int slot) -> hipError_t {
@@ -394,8 +387,6 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
         }
     }
     hipError_t e2 = hipStreamSynchronize(a.stream);
-    hipEventDestroy(polled[0]);
-    hipEventDestroy(polled[1]);
     if (e != hipSuccess) return e;
     if (e2 != hipSuccess) return e2;
     return hipSuccess;

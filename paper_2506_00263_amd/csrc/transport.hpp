@@ -100,6 +100,7 @@ struct Lane {
     uint32_t pieces;
     uint32_t err;
     uint32_t rep;            // this wavefront's tally replica (wavefront id mod TREP)
+    uint32_t cdf;            // transfer-CDF entries read by multigroup scatters
 };
 
 // Everything an event needs besides the particle.
@@ -861,6 +862,7 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
                 break;
             }
         }
+        ln.cdf += (uint32_t)gn + 1u;
         p.gc = (p.gc & ~0xffu) | (uint32_t)gn;
         isotropic(xi3, xi4, p);
     } else {
@@ -1085,12 +1087,14 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
     unsigned long long q = ln.q;
     uint32_t err = ln.err;
     unsigned long long pieces = ln.pieces;
+    unsigned long long cdf = ln.cdf;
     unsigned long long u = ln.u;
     for (int off = 32; off > 0; off >>= 1) {
         unsigned long long oq = __shfl_xor(q, off);
         unsigned long long ou = __shfl_xor(u, off);
         uint32_t oe = __shfl_xor(err, off);
         unsigned long long op = __shfl_xor(pieces, off);
+        unsigned long long oc = __shfl_xor(cdf, off);
         unsigned long long nq = q + oq;
         if (nq < q) err |= ERR_OVERFLOW;
         q = nq;
@@ -1099,6 +1103,7 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
         u = nu;
         err |= oe;
         pieces += op;
+        cdf += oc;
     }
     if (__lane_id() == 0) {
         const unsigned int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -1119,6 +1124,7 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
         for (int i = 0; i < C_WAVE; ++i)
             if (wc.c[i]) atomicAdd(&S[i], (unsigned long long)wc.c[i]);
         if (pieces) atomicAdd(&S[C_PIECES], pieces);
+        if (cdf) atomicAdd(&S[C_CDF], cdf);
     }
 }
 

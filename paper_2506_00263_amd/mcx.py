@@ -63,6 +63,7 @@ class RunOpts(C.Structure):
         ("time_kernels", C.c_int32), ("force_spill", C.c_int32), ("consolidate", C.c_int32),
         ("stack_tail_events", C.c_int32), ("stack_min_events", C.c_int32), ("tally_path", C.c_int32),
         ("async_block_waves", C.c_int32), ("async_drain_events", C.c_int32),
+        ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
     ]
 
 
@@ -75,7 +76,7 @@ class Counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in COUNTER_NAMES] + [
         ("kernel_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
         ("lds_bytes", C.c_int32), ("pad", C.c_int32), ("fissions", C.c_uint64), ("sites", C.c_uint64),
-        ("roulettes", C.c_uint64)]
+        ("roulettes", C.c_uint64), ("cdf_scans", C.c_uint64)]
 
 
 class EigenOpts(C.Structure):
@@ -222,7 +223,7 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
              stack_threshold=0, stash_links=0, arena_links=0, waves_per_cu=0, block_size=0, stream=None,
              digest=None, time_kernels=False, force_spill=0, consolidate=0, stack_tail_events=0,
              stack_min_events=0, tally_path="auto", async_block_waves=0,
-             async_drain_events=0) -> RunOpts:
+             async_drain_events=0, workspace=None) -> RunOpts:
     o = RunOpts()
     o.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     o.decomp = DECOMP[decomp] if isinstance(decomp, str) else int(decomp)
@@ -245,6 +246,10 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
     o.tally_path = TALLY_PATH[tally_path] if isinstance(tally_path, str) else int(tally_path)
     o.async_block_waves = int(async_block_waves)
     o.async_drain_events = int(async_drain_events)
+    # caller-owned device scratch: a device tensor (its bytes) or None
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.ws_bytes = workspace.numel() * workspace.element_size()
     # async stash donation: None/"default" = library default, True/"on", False/"off"
     if isinstance(consolidate, bool):
         o.consolidate = 1 if consolidate else 2
@@ -310,7 +315,8 @@ class Problem:
         return self
 
     def workspace_size(self, **kw) -> int:
-        """Device scratch bytes a run with these options would allocate."""
+        """Device scratch bytes a run (and a backward after it) with these
+        options needs: the smallest `workspace` they accept."""
         o = run_opts(**kw)
         n = C.c_size_t(0)
         self._check(lib().mcx_workspace_size(self.h, C.byref(o), C.byref(n)))
@@ -363,6 +369,6 @@ class Problem:
         out = {n: int(getattr(c, n)) for n in COUNTER_NAMES}
         out.update(kernel_ms=c.kernel_ms, grid_blocks=c.grid_blocks, block_threads=c.block_threads,
                    lds_bytes=c.lds_bytes, fissions=int(c.fissions), sites=int(c.sites),
-                   roulettes=int(c.roulettes))
+                   roulettes=int(c.roulettes), cdf_scans=int(c.cdf_scans))
         return out
 

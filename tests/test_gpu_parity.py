@@ -13,7 +13,7 @@ from paper_2506_00263_amd import inputs
 pytestmark = pytest.mark.gpu
 
 INVARIANT = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks", "reflections",
-             "cutoffs", "killed", "pieces", "qsum", "overflow"]
+             "cutoffs", "killed", "pieces", "qsum", "overflow", "cdf_scans"]
 SCHEDS = [("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"), ("async", "split")]
 
 
@@ -426,14 +426,16 @@ def test_async_default_shape(mcx, cfg2):
 
 def test_workspace_size(mcx, cfg2):
     # the query allocates and launches nothing and follows the layouts: one
-    # more async arena link costs one 64-particle link (64 x 64 bytes for the
-    # fused multigroup forward) plus its two 4-byte header words
+    # more async arena link costs one 64-particle link plus its two 4-byte
+    # header words; the size covers a run and the backward after it, so the
+    # largest particle is that of the backward's first replay (fused
+    # multigroup: 8 doubles and 4 words, 80 bytes)
     d, ref = cfg2
     P = mcx.Problem(d)
     assert P.workspace_size(sched="naive") == 0
     a1 = P.workspace_size(sched="async", arena_links=1000)
     a2 = P.workspace_size(sched="async", arena_links=2000)
-    assert a2 - a1 == 1000 * (64 * 64 + 8)
+    assert a2 - a1 == 1000 * (64 * 80 + 8)
     s1 = P.workspace_size(sched="stack", stack_capacity=100_000)
     s2 = P.workspace_size(sched="stack", stack_capacity=200_000)
     assert 0 < s1 < s2

@@ -16,7 +16,7 @@ from paper_2506_00263_amd import inputs
 pytestmark = pytest.mark.gpu
 
 INVARIANT = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks", "reflections",
-             "cutoffs", "killed", "pieces", "qsum", "overflow"]
+             "cutoffs", "killed", "pieces", "qsum", "overflow", "cdf_scans"]
 SCHEDS = [("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"), ("async", "split")]
 CE_SPEED = 1.383e6   # cm/s per sqrt(eV): a neutron's speed
 

@@ -15,7 +15,7 @@ from paper_2506_00263_amd import inputs
 pytestmark = pytest.mark.gpu
 
 INVARIANT = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks", "reflections",
-             "cutoffs", "killed", "pieces", "qsum", "overflow", "roulettes"]
+             "cutoffs", "killed", "pieces", "qsum", "overflow", "cdf_scans", "roulettes"]
 SCHEDS = [("naive", "fused"), ("stack", "fused"), ("stack", "split"), ("async", "fused"), ("async", "split")]
 
 

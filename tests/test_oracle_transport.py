@@ -92,6 +92,51 @@ def test_infinite_medium_multigroup(oracle):
     assert np.all(np.abs(mean - phi) < 4 * se + 1e-12), (mean, phi, se)
 
 
+def test_cdf_scans_in_group_scatter(oracle):
+    """Transfer rows that keep every scatter in its group (the CDF jumps to 1
+    at the incoming group): finding group g reads entries 0..g, so each
+    scatter from source group g0 reads exactly g0 + 1 entries."""
+    G, g0 = 5, 3
+    st = np.linspace(0.6, 1.4, G)
+    ss = 0.7 * st
+    cdf = np.zeros((G, G))
+    for g in range(G):
+        cdf[g, g:] = 1.0
+    d = _inf_medium(st[None, :], ss[None, :], cdf=cdf[None], n=3000)
+    d["src_group"] = g0
+    c = oracle.run(d)["counts"]
+    assert c["scatters"] > 1000
+    assert c["cdf_scans"] == (g0 + 1) * c["scatters"]
+    # one group: one entry per scatter
+    c1 = oracle.run(_inf_medium([[1.0]], [[0.8]], n=2000))["counts"]
+    assert c1["cdf_scans"] == c1["scatters"] > 0
+
+
+def test_cdf_scans_multigroup_mean(oracle):
+    """Expected entries read per history in a multigroup infinite medium:
+    sum over g of (scatters out of g) times sum_k (k+1) P[g,k], with the
+    scatters out of g equal to Sigma_s,g phi_g and phi from the linear solve
+    (diag Sigma_t - M^T) phi = e_0."""
+    rng = np.random.default_rng(33)
+    G = 5
+    st = rng.uniform(0.5, 1.5, G)
+    ss = st * rng.uniform(0.5, 0.85, G)
+    P = np.zeros((G, G))
+    for g in range(G):
+        w = rng.uniform(0.1, 1.0, G)
+        P[g] = w / w.sum()
+    cdf = np.cumsum(P, axis=1)
+    cdf[:, -1] = 1.0
+    d = _inf_medium(st[None, :], ss[None, :], cdf=cdf[None], n=40000)
+    M = ss[:, None] * P
+    phi = np.linalg.solve(np.diag(st) - M.T, np.eye(G)[0])
+    expect = float(np.sum(ss * phi * (P @ (np.arange(G) + 1.0))))
+    batches = 10
+    per = d["n_histories"] // batches
+    est = np.array([oracle.run(d, b * per, (b + 1) * per)["counts"]["cdf_scans"] / per for b in range(batches)])
+    assert _z(est.mean(), expect, est.std(ddof=1) / math.sqrt(batches)) < 4, (est.mean(), expect)
+
+
 def test_sum_of_bins_equals_total(oracle):
     d = inputs.cfg1_box(5000)
     r = oracle.run(d, digest=True)
