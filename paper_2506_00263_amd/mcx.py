@@ -265,6 +265,9 @@ class Problem:
         if isinstance(descs, dict):
             descs = [descs]
         self.descs = list(descs)
+        # bumped by every call that replaces what mcx_backward would replay
+        # (a forward run, new cross sections): autograd checks it
+        self.generation = 0
         self._keep = []
         arr = (ProblemDesc * len(self.descs))(*[_desc(d, self._keep) for d in self.descs])
         h = C.c_void_p()
@@ -300,6 +303,7 @@ class Problem:
         return dict(n_bins=nb.value, n_mat=nm.value, n_grp=ng.value, n_histories=nh.value)
 
     def set_xs(self, problem: int, sigma_t, sigma_s):
+        self.generation += 1
         if hasattr(sigma_t, "data_ptr"):
             where = DEVICE if sigma_t.is_cuda else HOST
             self._check(lib().mcx_set_xs(self.h, problem, _ptr(sigma_t.contiguous()), _ptr(sigma_s.contiguous()),
@@ -311,6 +315,7 @@ class Problem:
 
     def run(self, **kw):
         o = run_opts(**kw)
+        self.generation += 1
         self._check(lib().mcx_run(self.h, C.byref(o)))
         return self
 
@@ -325,6 +330,7 @@ class Problem:
     def run_eigen(self, n_particles: int, n_cycles: int, n_inactive: int, **kw) -> dict:
         """k-eigenvalue power iteration: returns k and the source size of every
         cycle; the tallies then hold the active cycles' sum."""
+        self.generation += 1
         o = run_opts(**kw)
         k = np.zeros(n_cycles, np.float64)
         ns = np.zeros(n_cycles, np.uint64)

@@ -60,3 +60,26 @@ def test_autotune_invariant(torch_gpu, oracle):
         best = autotune.tune(P, sched=sched, decomp=decomp, use_cache=False, reps=1)
         P.run(sched=sched, decomp=decomp, **best)
         assert np.array_equal(P.tallies(), oracle.run(d)["tally"])
+
+
+def test_backward_after_another_forward(torch_gpu, oracle):
+    # two forwards on one handle (the second with other cross sections and
+    # another history range), then backward through the first graph: its
+    # gradient must be the first forward's
+    torch = torch_gpu
+    from paper_2506_00263_amd import autotune, mcx
+    from paper_2506_00263_amd.autograd import transport
+    d = inputs.lattice_mg(n_histories=6000)
+    P = mcx.Problem(d)
+    st = torch.tensor(d["sigma_t"], dtype=torch.float64, device="cuda").view(7, 7).requires_grad_(True)
+    ss = torch.tensor(d["sigma_s"], dtype=torch.float64, device="cuda").view(7, 7).requires_grad_(True)
+    T1 = transport(st, ss, P, sched="async")
+    T2 = transport(st.detach() * 1.05, ss.detach() * 0.95, P, sched="stack", first=1000, n=2000)
+    autotune.tune(P, sched="async", use_cache=False, reps=1)       # calibration runs on the handle
+    w = torch.tensor(np.random.default_rng(8).normal(size=T1.numel()), dtype=torch.float64, device="cuda")
+    (w * T1).sum().backward()
+    rb = oracle.backward(d, w.cpu().numpy())
+    assert np.array_equal(st.grad.cpu().numpy().ravel(), rb["grad_sigma_t"])
+    assert np.array_equal(ss.grad.cpu().numpy().ravel(), rb["grad_sigma_s"])
+    assert np.array_equal(P.tallies(), oracle.run(d)["tally"])    # the first forward again
+    del T2
