@@ -317,6 +317,25 @@ mcx_status mcx_set_xs(mcx_problem_t p, int32_t problem, const double *sigma_t, c
  * tallies).  Synchronises the run's stream before returning. */
 mcx_status mcx_run(mcx_problem_t p, const mcx_run_opts *opts);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mcx_run
+ * with the run's scheduler state (stack banks and counters, or the async
+ * link arena) and tally replicas in a fixed device array of the library,
+ * MCX_NOALLOC_SCRATCH_BYTES per device, held from the first mcx_create_problem
+ * on that device until the process ends.  It calls no hipMalloc, hipFree or
+ * other allocating routine; the handle (mcx_create_problem) owns the
+ * tallies and problem tables as for mcx_run.  Same results as mcx_run.
+ * A run whose scratch exceeds the array returns MCX_E_INVALID_ARG before
+ * anything runs.  The async link arena depends on the launch shape, not on
+ * the history count (tens of MB at the default shape); the stack scheme's
+ * banks scale with its capacity and resident wavefronts and by default do
+ * not fit: give stack_capacity and waves_per_cu (e.g. 262144 and 1 for fused
+ * events).  opts.workspace must be NULL and opts.time_kernels 0.  Every call on one device shares that device's array
+ * (each run initialises what it reads): calls that overlap on one device,
+ * from any handle or stream, race. */
+#define MCX_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+mcx_status mcx_run_noalloc(mcx_problem_t p, const mcx_run_opts *opts);
+
 /* Copy problem `problem`'s raw int64 tally (n = its bin count) to out. */
 mcx_status mcx_tallies(mcx_problem_t p, int32_t problem, int64_t *out, int64_t n, int32_t where);
 

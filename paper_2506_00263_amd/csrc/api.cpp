@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,19 @@
 using namespace mcx;
 
 static_assert(sizeof(mcx_digest) == 24, "digest layout");
+
+// Device scratch of mcx_run_noalloc: a fixed array in this code object, so
+// runs through that entry point need no device allocation.  Every device the
+// library runs on holds its own copy until the process ends.  In host code
+// the array's name is not a device address: kernels and copies use the
+// per-device address that hipGetSymbolAddress returns (scratch_setup).
+static __device__ __align__(256) unsigned char scratch[MCX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_addr[SCRATCH_MAX_DEVICES];   // device address of `scratch`, per device
+}  // namespace
 
 namespace {
 
@@ -87,6 +101,7 @@ struct mcx_problem_s {
     bool have_forward = false;
     std::vector<uint64_t> last_first, last_count;
     unsigned long long passa_u = 0;       // single-problem pass A bound (summed stripes)
+    void *scratch = nullptr;              // this device's copy of the static scratch
     mcx_counters_t counters{};
     std::string err;
 };
@@ -568,6 +583,24 @@ static mcx_status upload(mcx_problem_t h)
     return MCX_OK;
 }
 
+// Once per device, with that device current: the device address of the
+// static scratch.
+static mcx_status scratch_setup(mcx_problem_t h)
+{
+    if (h->device < 0 || h->device >= SCRATCH_MAX_DEVICES)
+        return fail(h, MCX_E_DEVICE, "device %d: at most %d devices", h->device, SCRATCH_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[h->device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(h, e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(h, MCX_E_DEVICE, "hipGetSymbolAddress(scratch) gave a null address");
+        scratch_addr[h->device] = ptr;
+    }
+    h->scratch = scratch_addr[h->device];
+    return MCX_OK;
+}
+
 extern "C" mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t n_problems, mcx_problem_t *out)
 {
     if (!out) return MCX_E_INVALID_ARG;
@@ -593,6 +626,7 @@ extern "C" mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t 
         if (e != hipSuccess) s = hip_fail(h, e, "hipGetDeviceProperties");
         else h->num_cus = prop.multiProcessorCount;
     }
+    if (s == MCX_OK) s = scratch_setup(h);
     if (s == MCX_OK) s = upload(h);
     if (s != MCX_OK) {
         mcx_destroy_problem(h);
@@ -968,6 +1002,18 @@ static mcx_status forward(mcx_problem_t h, const mcx_run_opts &o, Workspace *fix
     std::vector<uint64_t> &first = h->run_first, &count = h->run_count;
     mcx_status s = run_range(h, o, first, count);
     if (s != MCX_OK) return s;
+    if (fixed) {
+        // refuse a run that does not fit before anything changes
+        unsigned long long total = 0;
+        for (int k = 0; k < h->n; ++k) total += count[k];
+        const int path = tally_path(h, o, MODE_FWD);
+        size_t sched_b = 0, need = 0;
+        s = scratch_bytes(h, o, launch_args(h, o, MODE_FWD, total, path, o.digest), path, sched_b, need);
+        if (s != MCX_OK) return s;
+        if (need > fixed->bytes)
+            return fail(h, MCX_E_INVALID_ARG, "the run needs %zu bytes of device scratch; the workspace holds %zu",
+                        need, fixed->bytes);
+    }
     h->tallies_valid = false;
     h->have_forward = false;
     if (!o.accumulate)
@@ -1001,6 +1047,22 @@ extern "C" mcx_status mcx_run(mcx_problem_t h, const mcx_run_opts *opts)
     if (s != MCX_OK) return s;
     Workspace w;
     return forward(h, o, caller_ws(o, w));
+}
+
+extern "C" mcx_status mcx_run_noalloc(mcx_problem_t h, const mcx_run_opts *opts)
+{
+    if (!h || !opts) return MCX_E_INVALID_ARG;
+    const mcx_run_opts &o = *opts;
+    mcx_status s = check_opts(h, o);
+    if (s != MCX_OK) return s;
+    if (o.workspace) return fail(h, MCX_E_INVALID_ARG, "mcx_run_noalloc runs in the library's fixed scratch: workspace must be NULL");
+    if (o.time_kernels) return fail(h, MCX_E_INVALID_ARG, "mcx_run_noalloc does not time launches (time_kernels must be 0)");
+    if (!h->scratch) return fail(h, MCX_E_DEVICE, "no device scratch on this device");
+    Workspace w;
+    w.ptr = h->scratch;
+    w.bytes = MCX_NOALLOC_SCRATCH_BYTES;
+    w.fixed = true;
+    return forward(h, o, &w);
 }
 
 // grow a device buffer to at least `count` elements (contents not kept)

@@ -101,6 +101,7 @@ def lib():
         L.mcx_create_problem.argtypes = [P(ProblemDesc), C.c_int32, P(C.c_void_p)]
         L.mcx_set_xs.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32]
         L.mcx_run.argtypes = [C.c_void_p, P(RunOpts)]
+        L.mcx_run_noalloc.argtypes = [C.c_void_p, P(RunOpts)]
         L.mcx_tallies.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32]
         L.mcx_backward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(RunOpts)]
         L.mcx_counters.argtypes = [C.c_void_p, P(Counters)]
@@ -317,6 +318,14 @@ class Problem:
         o = run_opts(**kw)
         self.generation += 1
         self._check(lib().mcx_run(self.h, C.byref(o)))
+        return self
+
+    def run_noalloc(self, **kw):
+        """mcx_run_noalloc: the run's device scratch is the library's fixed
+        array (no device allocation)."""
+        o = run_opts(**kw)
+        self.generation += 1
+        self._check(lib().mcx_run_noalloc(self.h, C.byref(o)))
         return self
 
     def workspace_size(self, **kw) -> int:
