@@ -100,9 +100,12 @@ enum { MCX_FATE_LEAK = 0, MCX_FATE_ABSORB = 1, MCX_FATE_CUTOFF = 2, MCX_FATE_KIL
  *  Direction isotropic if src_isotropic, else src_dir.  Group src_group
  *  (MG) or energy e_source (CE).
  * Tally: MESH track length on the tensor mesh mesh_x/y/z (edges, mesh_n[a]+1
- *  each), bins [g][iz][iy][ix]; ENERGY track length per flight into the bin
- *  [e_edges[k], e_edges[k+1]) holding the particle energy.  Raw values are
- *  int64 sum of rint(length * 2^tally_scale_log2).
+ *  each, containing the box), bins [g][iz][iy][ix]; ENERGY track length per
+ *  flight into the bin [e_edges[k], e_edges[k+1]) holding the particle energy
+ *  (the last bin holds its upper edge; continuous energy: the edges contain
+ *  [e_min, e_source]).  Raw values are int64 sum of rint(length *
+ *  2^tally_scale_log2).  A mesh or energy edges not containing these are
+ *  rejected (MCX_E_INVALID_ARG).
  * Random numbers: Philox4x32-10 keyed by (seed, problem_id), indexed by
  *  (history, flight, slot); identical on every scheduler.
  */

@@ -120,6 +120,22 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def _check_tally_covers(d: dict) -> None:
+    """A mesh tally's edges must contain the geometry's box and a
+    continuous-energy tally's edges [e_min, e_source]; otherwise track outside
+    them would have no bin (the last energy bin holds its upper edge).  Such
+    problems are not accepted."""
+    if int(d["tally_kind"]) == 0:
+        for a, name in enumerate(("mesh_x", "mesh_y", "mesh_z")):
+            e = np.asarray(d[name], np.float64)
+            if not (e[0] <= d["box_lo"][a] and e[-1] >= d["box_hi"][a]):
+                raise ValueError(f"mesh edges {name} do not contain the box")
+    elif int(d["energy_mode"]) == 1:
+        e = np.asarray(d["e_edges"], np.float64)
+        if not (e[0] <= d["e_min"] and d["e_source"] <= e[-1]):
+            raise ValueError("energy edges do not contain [e_min, e_source]")
+
+
 class Problem:
     """A problem description marshalled for the oracle.  Keeps references to
     every array it points into."""
@@ -127,6 +143,7 @@ class Problem:
     def __init__(self, d: dict):
         self.d = d
         keep = {}
+        _check_tally_covers(d)
 
         def arr(name, dtype):
             a = np.ascontiguousarray(np.asarray(d[name], dtype=dtype))

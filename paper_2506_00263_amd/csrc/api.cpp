@@ -53,6 +53,7 @@ struct HostProblem {
 struct mcx_problem_s {
     int device = 0;
     int num_cus = 256;
+    int wall_clock_khz = 0;
     int n = 0;
     int geom = 0, emode = 0, tally_kind = 0;
     std::vector<HostProblem> hp;
@@ -323,6 +324,11 @@ static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int
         if (!sorted_strict(hp.mx.data(), d.mesh_n[0] + 1) || !sorted_strict(hp.my.data(), d.mesh_n[1] + 1) ||
             !sorted_strict(hp.mz.data(), d.mesh_n[2] + 1))
             return fail(h, MCX_E_INVALID_ARG, "problem %d: mesh edges must increase", k);
+        // the mesh must contain the box: track outside it would have no bin
+        const std::vector<double> *edges[3] = {&hp.mx, &hp.my, &hp.mz};
+        for (int a = 0; a < 3; ++a)
+            if (!(edges[a]->front() <= d.box_lo[a] && edges[a]->back() >= d.box_hi[a]))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: mesh edges must contain the box", k);
         hp.n_bins = (int64_t)d.mesh_n[0] * d.mesh_n[1] * d.mesh_n[2] * (d.energy_mode == MCX_MG ? d.n_grp : 1);
         hp.eedges = {0.0, 1.0};
     } else if (d.tally_kind == MCX_TALLY_ENERGY) {
@@ -330,6 +336,11 @@ static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int
         hp.eedges = copy_of(d.e_edges, d.n_ebins + 1);
         if (!sorted_strict(hp.eedges.data(), d.n_ebins + 1))
             return fail(h, MCX_E_INVALID_ARG, "problem %d: energy edges must increase", k);
+        // energies stay in [e_min, e_source] (elastic scattering only loses
+        // energy; histories end below e_min): the edges must contain them
+        // (the last bin holds its upper edge)
+        if (d.energy_mode == MCX_CE && !(hp.eedges.front() <= d.e_min && d.e_source <= hp.eedges.back()))
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: energy edges must contain [e_min, e_source]", k);
         hp.n_bins = d.n_ebins;
         hp.mx = hp.my = hp.mz = {0.0, 1.0};
     } else {
@@ -625,6 +636,9 @@ extern "C" mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t 
         if (e == hipSuccess) e = hipGetDeviceProperties(&prop, h->device);
         if (e != hipSuccess) s = hip_fail(h, e, "hipGetDeviceProperties");
         else h->num_cus = prop.multiProcessorCount;
+        if (e == hipSuccess && hipDeviceGetAttribute(&h->wall_clock_khz, hipDeviceAttributeWallClockRate, h->device) !=
+                                   hipSuccess)
+            h->wall_clock_khz = 0;   // launchers then assume 100 MHz
     }
     if (s == MCX_OK) s = scratch_setup(h);
     if (s == MCX_OK) s = upload(h);
@@ -814,6 +828,7 @@ static LaunchArgs launch_args(mcx_problem_t h, const mcx_run_opts &o, int mode, 
     a.ws_query = nullptr;
     a.poll[0] = h->poll[0];
     a.poll[1] = h->poll[1];
+    a.wall_clock_khz = h->wall_clock_khz;
     return a;
 }
 

@@ -84,6 +84,7 @@ struct LaunchArgs {
                                            // needs (nothing is allocated or launched)
     hipEvent_t poll[2];                    // stack: two events (timing off) owned by the handle,
                                            // recorded behind each batch of rounds
+    int wall_clock_khz;                    // rate of the device's constant-rate clock
 };
 
 // Default wavefronts per asynchronous block.  Measured on MI355X (1e6
@@ -93,6 +94,11 @@ struct LaunchArgs {
 // and changed the rest by a few percent either way.
 constexpr int ASYNC_BLOCK_WAVES = 4;
 constexpr int ASYNC_DRAIN_EVENTS = 8;
+// Budget of one bounded wait in the asynchronous scheduler (a queue claimed
+// by others, no empty arena link, links in flight): far beyond any transient
+// contention (a queue is held for well under a microsecond), short enough
+// that an exhausted arena is reported promptly.
+constexpr int ASYNC_WAIT_MS = 20;
 
 struct LaunchStats {
     unsigned long long launches = 0, rounds = 0;

@@ -46,7 +46,7 @@ struct AsyncArgs {
     uint32_t *fill;              // number of filled links in the arena
     int n_arena, n_queues;
     int lacc_words;
-    int spin_limit;
+    unsigned long long wait_ticks;   // budget of one bounded wait, in constant-rate clock ticks
     int force_spill;             // testing: spill every k-th filled link
     int consolidate;             // drained sparse stashes are handed to the arena and merged
     int tl_bytes;                // packed tables copied to LDS (single problem)
@@ -92,6 +92,49 @@ __device__ __forceinline__ void lane0_store(uint32_t *p, uint32_t v)
     if (__lane_id() == 0) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Bounded waits.  A wait (for an unclaimed queue, an empty arena link, or
+// links in flight) gives up once the arena's count of filled links has not
+// changed for A.wait_ticks of the constant-rate clock (no wavefront anywhere
+// spilled or refilled, so nothing can free what the wait needs), or at once
+// when the run has already failed for capacity: the wavefront that fails
+// first publishes it in the run's error word, so an exhausted arena is
+// reported within milliseconds while a slow but moving arena is waited for.
+__device__ __forceinline__ bool run_failed(const AsyncArgs &A)
+{
+    uint32_t e = 0;
+    if (__lane_id() == 0) e = __hip_atomic_load(&A.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (first_lane_u32(e) & ERR_CAPACITY) != 0u;
+}
+
+// One bounded wait: its clock start and the fill count last seen (wave-uniform).
+struct Wait {
+    unsigned long long t0 = 0;
+    uint32_t seen = 0;
+    bool started = false;
+};
+
+// keep waiting: the run has not failed and the fill count changed within the budget
+__device__ __forceinline__ bool wait_on(const AsyncArgs &A, Wait &w)
+{
+    if (run_failed(A)) return false;
+    const unsigned long long now = wall_clock64();
+    const uint32_t f = lane0_load(A.fill);
+    if (!w.started || f != w.seen) {
+        w.started = true;
+        w.t0 = now;
+        w.seen = f;
+        return true;
+    }
+    return now - w.t0 < A.wait_ticks;
+}
+
+// record a capacity failure and publish it to every wavefront at once
+__device__ __forceinline__ void fail_capacity(const AsyncArgs &A, uint32_t &err)
+{
+    if (!(err & ERR_CAPACITY) && __lane_id() == 0) atomicOr(&A.ctl->error, ERR_CAPACITY);
+    err |= ERR_CAPACITY;
+}
+
 // Pop one link from one of the 64 queues in `slots` (one queue per lane, so a
 // single vector load inspects all of them).  Returns NIL if none had a link.
 __device__ __forceinline__ uint32_t arena_pop(const AsyncArgs &A, unsigned long long *slots, uint32_t start)
@@ -122,12 +165,12 @@ __device__ __forceinline__ uint32_t arena_pop(const AsyncArgs &A, unsigned long 
     return NIL;
 }
 
-// Append link a to one of the 64 queues of `slots`; bounded retries while
-// all are claimed.
+// Append link a to one of the 64 queues of `slots`; a bounded wait while
+// all are claimed (the clock is read only once a pass has failed).
 __device__ __forceinline__ bool arena_push(const AsyncArgs &A, unsigned long long *slots, uint32_t start, uint32_t a)
 {
     lane0_store(&A.next[a], NIL);
-    for (int spin = 0; spin < A.spin_limit; ++spin) {
+    for (Wait w;;) {
         for (int i = 0; i < 64; ++i) {
             int s = (int)((start + (uint32_t)i) & 63u);
             unsigned long long v = q_exchange(&slots[s], Q_CLAIMED);
@@ -144,9 +187,9 @@ __device__ __forceinline__ bool arena_push(const AsyncArgs &A, unsigned long lon
             q_exchange(&slots[s], nv);
             return true;
         }
+        if (!wait_on(A, w)) return false;
         __builtin_amdgcn_s_sleep(4);
     }
-    return false;
 }
 
 // filled links currently in the arena (may lag a push in flight; the
@@ -194,10 +237,10 @@ struct AsyncWave {
     // move ready link v to the global arena
     __device__ __forceinline__ bool spill(int v)
     {
-        uint32_t a = NIL;
-        for (int spin = 0; spin < A.spin_limit && a == NIL; ++spin) {
+        uint32_t a = arena_pop(A, A.qempty, qstart);
+        for (Wait w; a == NIL && wait_on(A, w);) {
+            __builtin_amdgcn_s_sleep(4);
             a = arena_pop(A, A.qempty, qstart);
-            if (a == NIL) __builtin_amdgcn_s_sleep(4);
         }
         if (a == NIL) return false;
         copy_slot(alink(a), __lane_id(), link(v), __lane_id(), nd, nu);
@@ -213,12 +256,12 @@ struct AsyncWave {
     {
         if (S.freem == 0) {
             if (S.readym == 0) {
-                err |= ERR_CAPACITY;
+                fail_capacity(A, err);
                 return -1;
             }
             int v = __ffs(S.readym) - 1;
             if (!spill(v)) {
-                err |= ERR_CAPACITY;
+                fail_capacity(A, err);
                 return -1;
             }
             S.readym &= ~(1u << v);
@@ -267,7 +310,7 @@ struct AsyncWave {
                     S.freem |= 1u << pl;
                     wc.c[C_SPILLS] += 1;
                 } else {
-                    err |= ERR_CAPACITY;
+                    fail_capacity(A, err);
                 }
             }
             if (n > take) {
@@ -297,7 +340,7 @@ struct AsyncWave {
         uint32_t h = lane0_load(&A.hdr[a]);
         copy_slot(link(l), __lane_id(), alink(a), __lane_id(), nd, nu);
         wc.c[C_REFILLS] += 1;
-        if (!arena_push(A, A.qempty, qstart, a)) err |= ERR_CAPACITY;
+        if (!arena_push(A, A.qempty, qstart, a)) fail_capacity(A, err);
         int ev = (int)(h & 0xffu), c = (int)(h >> 8);
         if (!A.consolidate || c == 64) {
             S.set_ev(l, ev);
@@ -377,7 +420,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
     W.S.part = 0xFFFFFFFFu;
     bool src_done = false;
     bool may_donate = true;
-    int idle = 0;
+    Wait idle;                                      // the current idle spell's wait
     bool drained = false;                           // link l is a partial one of a drained stash
     unsigned long long res_next = 0, res_end = 0;   // reserved source ids
     for (;;) {
@@ -390,6 +433,10 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
             // make_work: 64 new histories, reserved 256 at a time from the
             // shared source counter (one atomic per four calls)
             if (res_next >= res_end) {
+                if (run_failed(A)) {                // a failed run sources nothing more
+                    src_done = true;
+                    continue;
+                }
                 unsigned long long b = 0;
                 if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 256ull);
                 b = first_lane_u64(b);
@@ -415,6 +462,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
             W.template deposit<LAY, E>(act, EV_STEP, p, dig, wc, ln.err);
             continue;
         } else if (W.template refill<LAY, E>(dig, wc, ln.err)) {
+            idle = Wait{};
             continue;
         } else {
             // drained: run the fullest partial link; a sparse stash is donated
@@ -440,7 +488,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
                     drained = true;
                 } else {
                     // links may still be in flight to the arena; wait a bounded time
-                    if (arena_fill(A) != 0 && !(ln.err & ERR_CAPACITY) && ++idle < A.spin_limit) {
+                    if (arena_fill(A) != 0 && !(ln.err & ERR_CAPACITY) && wait_on(A, idle)) {
                         __builtin_amdgcn_s_sleep(8);
                         continue;
                     }
@@ -461,7 +509,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
                             W.S.freem |= 1u << pl;
                             wc.c[C_SPILLS] += 1;
                         } else {
-                            ln.err |= ERR_CAPACITY;
+                            fail_capacity(A, ln.err);
                         }
                     }
                     if (ln.err & ERR_CAPACITY) may_donate = false;   // keep what could not be donated
@@ -469,8 +517,8 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
                 }
                 if (W.last_with_work(A.ctl)) {
                     may_donate = false;
-                    if (++idle < A.spin_limit) continue;
-                    ln.err |= ERR_CAPACITY;   // arena count never drained: report, do not spin
+                    if (wait_on(A, idle)) continue;
+                    fail_capacity(A, ln.err);   // arena count never drained: report, do not spin
                 }
                 break;
             }
@@ -480,6 +528,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
         // run up to drain_events events in place (their histories draw from
         // their own keyed streams, so results do not change), which saves
         // the unpack and pack of every event on the longest histories.
+        idle = Wait{};                              // the wait budget is per idle spell
         int ev = W.S.ev(l);
         int c = W.S.cnt(l);
         bool act = lane < c;
@@ -617,7 +666,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.n_arena = n_arena;
     A.n_queues = Q;
     A.lacc_words = a.lacc_words;
-    A.spin_limit = 1 << 20;
+    A.wait_ticks = (unsigned long long)(a.wall_clock_khz > 0 ? a.wall_clock_khz : 100000) * ASYNC_WAIT_MS;
     A.force_spill = a.force_spill;
     A.consolidate = a.consolidate == 1 ? 1 : 0;   // off unless asked for
     A.tl_bytes = tl_bytes;

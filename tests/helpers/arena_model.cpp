@@ -5,9 +5,18 @@
 // counters of remaining events; the model checks that every particle finishes
 // exactly once, for many workers running concurrently on host threads.
 //
+// Bounded waits: every wait (for a queue, an empty link, links in flight)
+// gives up once the arena's fill count has not changed for a wall-clock
+// budget (no worker anywhere spilled or refilled: nothing can free what the
+// wait needs), or at once when the run has already failed for capacity (a
+// worker that fails publishes it at once), so an exhausted arena is reported
+// within milliseconds while a slow but moving arena is waited for; a failed
+// run stops sourcing.
+//
 // Build: g++ -O1 -std=c++17 -pthread [-fsanitize=thread] arena_model.cpp
-// Run:   ./a.out <workers> <particles> <links> <force_spill> <consolidate> <seed>
+// Run:   ./a.out <workers> <particles> <links> <force_spill> <consolidate> <seed> [arena_links] [budget_ms]
 #include <atomic>
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
@@ -31,8 +40,37 @@ struct Particle {
     int32_t left;   // events still to run
 };
 
+using Clock = std::chrono::steady_clock;
+
 struct Arena {
     int n;
+    std::atomic<uint32_t> failed{0};             // the run has failed for capacity
+    Clock::duration budget = std::chrono::milliseconds(20);
+    // keep waiting: the run has not failed and the fill count changed within
+    // the budget (w holds the start of the wait and the count last seen)
+    struct Wait {
+        Clock::time_point t0{};
+        uint32_t seen = 0;
+        bool started = false;
+    };
+    bool wait_on(Wait &w) const
+    {
+        if (failed.load(std::memory_order_relaxed) != 0) return false;
+        Clock::time_point now = Clock::now();
+        uint32_t f = fill.load(std::memory_order_relaxed);
+        if (!w.started || f != w.seen) {
+            w.started = true;
+            w.t0 = now;
+            w.seen = f;
+            return true;
+        }
+        return now - w.t0 < budget;
+    }
+    void fail()
+    {
+        err.fetch_add(1);
+        failed.store(1, std::memory_order_relaxed);
+    }
     std::vector<std::vector<Particle>> data;   // link contents
     std::vector<std::atomic<uint32_t>> hdr, next;
     std::atomic<uint64_t> qfull[Q], qempty[Q];
@@ -71,7 +109,7 @@ struct Arena {
     bool push(std::atomic<uint64_t> *slots, uint32_t start, uint32_t a)
     {
         next[a].store(NIL, std::memory_order_relaxed);
-        for (int spin = 0; spin < (1 << 20); ++spin) {
+        for (Wait w; wait_on(w);) {
             for (int i = 0; i < Q; ++i) {
                 int s = (int)((start + i) % Q);
                 uint64_t v = slots[s].exchange(Q_CLAIMED, std::memory_order_acq_rel);
@@ -119,7 +157,7 @@ struct Worker {
     bool spill(int v)
     {
         uint32_t a = NIL;
-        for (int spin = 0; spin < (1 << 20) && a == NIL; ++spin) {
+        for (Arena::Wait w; a == NIL && A.wait_on(w);) {
             a = A.pop(A.qempty, start);
             if (a == NIL) std::this_thread::yield();
         }
@@ -136,9 +174,9 @@ struct Worker {
     int alloc()
     {
         if (freem == 0) {
-            if (readym == 0) { A.err.fetch_add(1); return -1; }
+            if (readym == 0) { A.fail(); return -1; }
             int v = __builtin_ctz(readym);
-            if (!spill(v)) { A.err.fetch_add(1); return -1; }
+            if (!spill(v)) { A.fail(); return -1; }
             readym &= ~(1u << v);
             freem |= 1u << v;
         }
@@ -170,7 +208,7 @@ struct Worker {
         part[k] = -1;
         if (force_spill > 0 && ++tick % (uint32_t)force_spill == 0) {
             if (spill(pl)) { readym &= ~(1u << pl); freem |= 1u << pl; }
-            else A.err.fetch_add(1);
+            else A.fail();
         }
         if (n > take) {
             int p2 = alloc();
@@ -212,7 +250,7 @@ struct Worker {
         int ev = (int)(h & 0xff), c = (int)(h >> 8);
         std::vector<Particle> ps(A.data[a].begin(), A.data[a].begin() + c);
         A.refills.fetch_add(1);
-        if (!A.push(A.qempty, start, a)) A.err.fetch_add(1);
+        if (!A.push(A.qempty, start, a)) A.fail();
         if (!consolidate || c == SLOTS) {
             int l = __builtin_ctz(freem);
             freem &= ~(1u << l);
@@ -238,7 +276,7 @@ struct Worker {
     void main_loop()
     {
         bool src_done = false, may_donate = true;
-        long idle = 0;
+        Arena::Wait idle;                   // the current idle spell's wait
         std::uniform_int_distribution<int> len(1, 40);
         for (;;) {
             int l = -1;
@@ -246,6 +284,7 @@ struct Worker {
                 l = __builtin_ctz(readym);
                 readym &= ~(1u << l);
             } else if (!src_done) {
+                if (A.failed.load(std::memory_order_relaxed)) { src_done = true; continue; }
                 uint64_t b = A.cursor.fetch_add(SLOTS);
                 if (b >= total) { src_done = true; continue; }
                 std::vector<Particle> ps;
@@ -254,6 +293,7 @@ struct Worker {
                 deposit(0, ps);
                 continue;
             } else if (refill()) {
+                idle = Arena::Wait{};
                 continue;
             } else {
                 int best = -1, bc = 0, tot = 0;
@@ -268,7 +308,7 @@ struct Worker {
                         l = part[best];
                         part[best] = -1;
                     } else {
-                        if (A.fill.load() != 0 && ++idle < (1L << 22)) {
+                        if (A.fill.load() != 0 && A.wait_on(idle)) {
                             std::this_thread::yield();
                             continue;
                         }
@@ -283,18 +323,19 @@ struct Worker {
                             int pl = part[k];
                             if (pl < 0) continue;
                             if (spill(pl)) { part[k] = -1; freem |= 1u << pl; }
-                            else { A.err.fetch_add(1); may_donate = false; }
+                            else { A.fail(); may_donate = false; }
                         }
                         if (!may_donate) continue;
                     }
                     if (last_with_work()) {
                         may_donate = false;
-                        if (++idle < (1L << 22)) continue;
-                        A.err.fetch_add(1);
+                        if (A.wait_on(idle)) continue;
+                        A.fail();
                     }
                     break;
                 }
             }
+            idle = Arena::Wait{};           // the wait budget is per idle spell
             run_link(l);
         }
         if (!consolidate) A.active.fetch_sub(1);
@@ -311,7 +352,11 @@ int main(int argc, char **argv)
     int force = argc > 4 ? atoi(argv[4]) : 0;
     int cons = argc > 5 ? atoi(argv[5]) : 0;
     uint32_t seed = argc > 6 ? (uint32_t)atoi(argv[6]) : 1;
-    Arena A(workers * (E + 2) + 1024);
+    int arena_links = argc > 7 ? atoi(argv[7]) : workers * (E + 2) + 1024;
+    int budget_ms = argc > 8 ? atoi(argv[8]) : 20;
+    Arena A(arena_links);
+    A.budget = std::chrono::milliseconds(budget_ms);
+    Clock::time_point t_start = Clock::now();
     A.active.store((uint32_t)workers);
     std::vector<int> done(particles, 0);
     std::vector<std::thread> th;
@@ -320,16 +365,17 @@ int main(int argc, char **argv)
         ws.push_back(new Worker(A, particles, links, force, cons, (uint32_t)w * 2654435761u, done, seed + w));
     for (int w = 0; w < workers; ++w) th.emplace_back([&, w] { ws[w]->main_loop(); });
     for (auto &t : th) t.join();
+    double ms = std::chrono::duration<double, std::milli>(Clock::now() - t_start).count();
     uint64_t missing = 0, twice = 0;
     for (uint64_t i = 0; i < particles; ++i) {
         if (done[i] == 0) ++missing;
         if (done[i] > 1) ++twice;
     }
     printf("workers=%d particles=%llu links=%d force=%d consolidate=%d spills=%llu refills=%llu fill=%u "
-           "missing=%llu twice=%llu err=%llu\n",
+           "missing=%llu twice=%llu err=%llu failed=%u ms=%.1f\n",
            workers, (unsigned long long)particles, links, force, cons, (unsigned long long)A.spills.load(),
            (unsigned long long)A.refills.load(), A.fill.load(), (unsigned long long)missing,
-           (unsigned long long)twice, (unsigned long long)A.err.load());
+           (unsigned long long)twice, (unsigned long long)A.err.load(), A.failed.load(), ms);
     for (auto *w : ws) delete w;
     return (missing || twice || A.err.load()) ? 1 : 0;
 }

@@ -26,7 +26,8 @@ def _pin(radius=1.0, height=3.0, pitch=None):
     # centre the single pin at the origin
     h = pitch / 2
     d.update(xplanes=np.array([-h, h]), yplanes=np.array([-h, h]), cx=np.array([0.0]), cy=np.array([0.0]),
-             box_lo=np.array([-h, -h, 0.0]), box_hi=np.array([h, h, height]))
+             box_lo=np.array([-h, -h, 0.0]), box_hi=np.array([h, h, height]),
+             mesh_x=np.array([-h, h]), mesh_y=np.array([-h, h]), mesh_z=np.array([0.0, height]))
     return d
 
 
@@ -76,6 +77,7 @@ def test_cylinder_distance_against_quadratic(oracle):
     rng = np.random.default_rng(11)
     d = _pin(radius=1.0, height=1e6, pitch=10.0)
     d["box_lo"][2], d["box_hi"][2] = -1e6, 1e6
+    d["mesh_z"] = np.array([-1e6, 1e6])
     P = oracle.Problem(d)
     dirs = _unit(rng, 4000)
     pts = rng.uniform(-4.5, 4.5, size=(4000, 3))
