@@ -316,6 +316,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--sched", default="async")
     ap.add_argument("--decomp", default="fused")
+    ap.add_argument("--workload", default="lattice", choices=["lattice", "pincell"],
+                    help="lattice: the multigroup pin lattice (the benchmark); pincell: the continuous-energy pin "
+                         "cell (for profiling its kernels; implies --no-extras)")
+    ap.add_argument("--lookup", default="hash", choices=["hash", "binary"], help="pincell: cross-section lookup")
+    ap.add_argument("--ebins", type=int, default=100, help="pincell: energy bins")
+    ap.add_argument("--histories", type=int, default=0, help="histories (0: 1e6)")
     ap.add_argument("--no-extras", action="store_true", help="time only the headline configuration")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--sweep", action="store_true",
@@ -345,22 +351,33 @@ def main():
             ap.error(f"unknown sweep parts {bad}; known: {SWEEP_PARTS}")
         print(json.dumps(sweep(parts)))
         return
-    d = inputs.cfg2_lattice(N_HIST)
+    n_hist = args.histories or N_HIST
+    run_kw = {}
+    if args.workload == "pincell":
+        d = inputs.cfg3_pincell(n_ebins=args.ebins, n_histories=n_hist)
+        run_kw = {"lookup": args.lookup}
+        args.no_extras = True
+        args.no_cpu = True
+        workload = (f"continuous-energy pin cell, 3 species x 1e5-point tables, {args.lookup} lookup, "
+                    f"{n_hist:.0e} histories, {args.ebins} energy bins")
+    else:
+        d = inputs.cfg2_lattice(n_hist)
+        workload = f"multigroup 17x17 pin lattice, 7 materials x 7 groups, {n_hist:.0e} histories, 51x51x20x7 mesh tally"
     P = mcx.Problem(d)
     stream = torch.cuda.current_stream()
 
     # headline: warmup, then exactly `steps` timed steps (no per-launch
     # events and no host reads inside the timed region)
     for _ in range(args.warmup):
-        P.run(sched=args.sched, decomp=args.decomp, stream=stream)
+        P.run(sched=args.sched, decomp=args.decomp, stream=stream, **run_kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        P.run(sched=args.sched, decomp=args.decomp, stream=stream)
+        P.run(sched=args.sched, decomp=args.decomp, stream=stream, **run_kw)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1e3 * wall / args.steps
-    value = N_HIST / (wall / args.steps)
+    value = n_hist / (wall / args.steps)
     c = P.counters()
     tally = P.tallies()
 
@@ -369,29 +386,31 @@ def main():
     # the same number of steps right after the timed region
     kernel_ms, launches = 0.0, 0
     for _ in range(args.steps):
-        P.run(sched=args.sched, decomp=args.decomp, stream=stream, time_kernels=True)
+        P.run(sched=args.sched, decomp=args.decomp, stream=stream, time_kernels=True, **run_kw)
         ck = P.counters()
         kernel_ms += ck["kernel_ms"]
         launches += main_launches(ck, args.sched)
     torch.cuda.synchronize()
     kern = {"async": "async_kernel", "stack": "stack_round", "naive": "naive_kernel"}[args.sched]
-    roofline = roofline_block(algorithmic_bytes(c) / max(1, launches // args.steps), kernel_ms / max(1, launches),
-                              kern, measured_traffic(kern))
+    roofline = roofline_block(algorithmic_bytes(c, d, args.lookup) / max(1, launches // args.steps),
+                              kernel_ms / max(1, launches), kern,
+                              measured_traffic(kern) if args.workload == "lattice" else None)
 
     out = {
         "metric": "particle histories/sec on 1 GPU (stack vs async TDR); backward/forward time ratio",
         "value": value, "unit": "histories/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "multigroup 17x17 pin lattice, 7 materials x 7 groups, 1e6 histories, "
-                               "51x51x20x7 mesh tally", "histories": N_HIST,
-                   "scheduler": args.sched, "decomposition": args.decomp},
+        "config": {"workload": workload, "histories": n_hist, "scheduler": args.sched, "decomposition": args.decomp},
         "roofline": roofline,
         "counters": {k: c[k] for k in ("flights", "collisions", "cdf_scans", "crossings", "pieces", "events", "lane_slots",
-                                       "dispatches", "spills", "refills", "rounds", "grid_blocks",
+                                       "dispatches", "spills", "refills", "rounds", "launches", "grid_blocks",
                                        "block_threads", "lds_bytes")},
         "active_lane_frac": c["events"] / max(1, c["lane_slots"]),
     }
+    if args.sched == "stack":
+        # input population of each remapping round of the last timed run
+        out["stack_rounds"] = [int(v) for v in P.stack_rounds()]
 
     if not args.no_extras:
         from paper_2506_00263_amd import autotune

@@ -374,6 +374,13 @@ mcx_status mcx_workspace_size(mcx_problem_t p, const mcx_run_opts *opts, size_t 
 
 mcx_status mcx_counters(mcx_problem_t p, mcx_counters_t *out);
 
+/* Stack scheduler (paper Sec. 3.1: one launch per remapping round): the
+ * input population (particles popped) of each round of the last pass, for
+ * its first 512 rounds.  Writes min(max_rounds, *n_rounds) entries to
+ * particles (host memory) and the number of recorded rounds to *n_rounds
+ * (0 after a run of another scheduler). */
+mcx_status mcx_stack_rounds(mcx_problem_t p, uint32_t *particles, int32_t max_rounds, int32_t *n_rounds);
+
 /* Sizes of problem `problem`: tally bins, materials, groups, histories. */
 mcx_status mcx_problem_info(mcx_problem_t p, int32_t problem, int64_t *n_bins, int32_t *n_mat, int32_t *n_grp,
                             uint64_t *n_histories);

@@ -102,6 +102,7 @@ struct mcx_problem_s {
     bool have_forward = false;
     std::vector<uint64_t> last_first, last_count;
     unsigned long long passa_u = 0;       // single-problem pass A bound (summed stripes)
+    std::vector<uint32_t> round_in;       // stack: input particles of each round of the last pass
     void *scratch = nullptr;              // this device's copy of the static scratch
     mcx_counters_t counters{};
     std::string err;
@@ -486,6 +487,7 @@ static mcx_status upload(mcx_problem_t h)
     HIP_TRY(h, hipHostMalloc((void **)&h->h_ctl, sizeof(RunCtl), hipHostMallocDefault));
     for (hipEvent_t &ev : h->poll) HIP_TRY(h, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
     h->run_prefix.assign(h->n + 1, 0);
+    h->round_in.reserve(STACK_ROUND_LOG);
     h->run_first.assign(h->n, 0);
     h->run_count.assign(h->n, 0);
     // host image of the problem table (static part)
@@ -981,6 +983,9 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     c.block_threads = st.block_threads;
     c.lds_bytes = st.lds_bytes;
     h->passa_u = tot[C_PASSA_U];
+    h->round_in.clear();
+    if (o.sched == MCX_SCHED_STACK)
+        h->round_in.assign(ctl.round_in, ctl.round_in + std::min<unsigned long long>(st.rounds, STACK_ROUND_LOG));
     *err_out = ctl.error;
     if (ctl.error & ERR_CAPACITY) return fail(h, MCX_E_CAPACITY, "scheduler capacity exhausted (stack or link arena)");
     if (tot[C_SOURCED] != total || tot[C_COMPLETED] != total)
@@ -1357,6 +1362,15 @@ extern "C" mcx_status mcx_workspace_size(mcx_problem_t h, const mcx_run_opts *op
         need = std::max(need, b);
     }
     *bytes = need;
+    return MCX_OK;
+}
+
+extern "C" mcx_status mcx_stack_rounds(mcx_problem_t h, uint32_t *particles, int32_t max_rounds, int32_t *n_rounds)
+{
+    if (!h || !n_rounds || max_rounds < 0 || (max_rounds > 0 && !particles)) return MCX_E_INVALID_ARG;
+    const int32_t n = (int32_t)std::min<size_t>(h->round_in.size(), (size_t)max_rounds);
+    for (int32_t r = 0; r < n; ++r) particles[r] = h->round_in[r];
+    *n_rounds = (int32_t)h->round_in.size();
     return MCX_OK;
 }
 

@@ -116,6 +116,8 @@ struct CtlStripe {
     unsigned long long c[32];        // Counter entries, padded to 256 bytes
 };
 
+constexpr int STACK_ROUND_LOG = 512;   // stack rounds whose input population is recorded
+
 // Per-run control block in device memory.
 struct RunCtl {
     unsigned long long src_cursor;   // next flattened history id to source
@@ -126,6 +128,7 @@ struct RunCtl {
     unsigned int pad0;
     unsigned long long pad[12];
     CtlStripe stripe[CTL_STRIPES];
+    unsigned int round_in[STACK_ROUND_LOG];   // stack: input particles of each round (first rounds)
 };
 
 enum : unsigned int { ERR_CAPACITY = 1u, ERR_OVERFLOW = 2u, ERR_BOUND = 4u };

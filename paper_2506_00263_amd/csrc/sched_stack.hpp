@@ -54,6 +54,7 @@ struct StackArgs {
     int tail_events;            // most events a popped particle runs in place in the tail
     int min_events;             // events a popped particle runs at least
     int tl_bytes;               // packed tables copied to LDS (single problem)
+    unsigned long long static_share;   // > 0: round 0 sources wavefront w's ids [w s, (w+1) s)
 };
 
 __device__ __forceinline__ unsigned int *stripe_ctr(const StackArgs &A, int set, int E, int e, int s)
@@ -104,19 +105,20 @@ __device__ __forceinline__ void push(const StackArgs &A, char *bank, int set, in
 }
 
 // wave-uniform view of one event's input stripes: chunk counts and prefixes
+// for chunks of 2^cs_log2 particles (a divisor of the 64-particle tile)
 struct StripeView {
     unsigned int n_lane;         // this lane's stripe size (clamped)
     unsigned int excl, incl;     // exclusive / inclusive chunk prefix of this lane's stripe
     unsigned int chunks;         // total chunks of the event
 };
 
-__device__ __forceinline__ StripeView stripe_view(const StackArgs &A, int set, int E, int e)
+__device__ __forceinline__ StripeView stripe_view(const StackArgs &A, int set, int E, int e, int cs_log2)
 {
     const int lane = __lane_id();
     unsigned int n = __hip_atomic_load(stripe_ctr(A, set, E, e, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned int cap = (lane == NSTRIPE - 1) ? (unsigned int)A.ocap : (unsigned int)A.scap;
     n = n < cap ? n : cap;
-    unsigned int c = (n + 63u) >> 6;
+    unsigned int c = (n + (1u << cs_log2) - 1u) >> cs_log2;
     unsigned int incl = c;
     for (int off = 1; off < 64; off <<= 1) {
         unsigned int o = __shfl_up(incl, off);
@@ -130,15 +132,19 @@ __device__ __forceinline__ StripeView stripe_view(const StackArgs &A, int set, i
     return v;
 }
 
-// total 64-particle input chunks of one event (wave-uniform)
-__device__ __forceinline__ unsigned int event_chunks(const StackArgs &A, int set, int E, int e)
+// total 64-particle input chunks of one event, and its particles (wave-uniform)
+__device__ __forceinline__ unsigned int event_chunks(const StackArgs &A, int set, int E, int e, unsigned int &parts)
 {
     const int lane = __lane_id();
     unsigned int n = __hip_atomic_load(stripe_ctr(A, set, E, e, lane), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     unsigned int cap = (lane == NSTRIPE - 1) ? (unsigned int)A.ocap : (unsigned int)A.scap;
     n = n < cap ? n : cap;
     unsigned int c = (n + 63u) >> 6;
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    for (int off = 32; off > 0; off >>= 1) {
+        c += __shfl_xor(c, off);
+        n += __shfl_xor(n, off);
+    }
+    parts = n;
     return c;
 }
 
@@ -194,28 +200,46 @@ stack_round(StackArgs A, int round, const ProbDev *__restrict__ probs)
     // grows as the population shrinks (up to tail_events).  Every history
     // draws from its own keyed streams, so results do not change.
     int K = A.min_events;
+    int cs_log2 = 6;                 // particles per popped chunk: 64, fewer in the tail
     {
-        unsigned int all = 0;
+        unsigned int all = 0, parts = 0;
 #pragma unroll
-        for (int e = 0; e < E; ++e) all += event_chunks(A, set_in, E, e);
+        for (int e = 0; e < E; ++e) {
+            unsigned int pe = 0;
+            all += event_chunks(A, set_in, E, e, pe);
+            parts += pe;
+        }
+        // the round's input population, kept for the first rounds
+        if (blockIdx.x == 0 && threadIdx.x == 0 && round < STACK_ROUND_LOG) A.ctl->round_in[round] = parts;
         if (all < n_waves) {
             unsigned int q = n_waves / (all ? all : 1u);
             int kt = (int)(q < (unsigned int)A.tail_events ? q : (unsigned int)A.tail_events);
             K = kt > K ? kt : K;
+        }
+        // Tail: fewer live particles than 64 per wavefront.  Whole tiles would
+        // leave most wavefronts idle while each busy one runs its events over
+        // 64 diverging lanes; chunks of the smallest power of two that spreads
+        // the particles over all wavefronts shorten each event (every
+        // wavefront derives the same size from the same read-only inputs, so
+        // the chunks still partition the stacks).
+        if (parts < 64u * n_waves) {
+            const unsigned int per = (parts + n_waves - 1u) / n_waves;
+            cs_log2 = 0;
+            while ((1u << cs_log2) < per) ++cs_log2;
         }
     }
     // pop: the input stacks are read-only during a round, so the 64-particle
     // chunks are dealt to wavefronts in a fixed order (no pop atomics)
 #pragma unroll 1
     for (int e = 0; e < E; ++e) {
-        StripeView v = stripe_view(A, set_in, E, e);
+        StripeView v = stripe_view(A, set_in, E, e, cs_log2);
         for (unsigned int c = wave; c < v.chunks; c += n_waves) {
             uint64_t in_stripe = __ballot(c < v.incl);
             int s = __ffsll((unsigned long long)in_stripe) - 1;
             unsigned int excl = __shfl(v.excl, s);
             unsigned int ns = __shfl(v.n_lane, s);
-            unsigned int base = (c - excl) * 64u;
-            bool act = base + (unsigned int)lane < ns;
+            unsigned int base = (c - excl) << cs_log2;
+            bool act = (unsigned int)lane < (1u << cs_log2) && base + (unsigned int)lane < ns;
             Part p;
             if (act) get<LAY>(stripe_soa(A, bin, e, s, LAY::nd(dig)), (long)(base + lane), p, dig);
             int ne = EV_DEAD, cur = e;
@@ -233,9 +257,33 @@ stack_round(StackArgs A, int round, const ProbDev *__restrict__ probs)
             push<LAY, E>(A, bout, set_out, home, act, ne, p, dig, ln.err);
         }
     }
-    // make_work: source new histories (256 per claim) until the fullest
+    // make_work.  When the stacks hold every history and the threshold cannot
+    // stop the source, round 0 sources all of them: wavefront w takes its own
+    // contiguous share of the ids, with no claims on the shared cursor (a few
+    // thousand claims on one word serialise at the memory-side atomic unit).
+    if (A.static_share > 0) {
+        if (round == 0) {
+            const unsigned long long b0 = (unsigned long long)wave * A.static_share;
+            const unsigned long long e0 = b0 + A.static_share < A.total ? b0 + A.static_share : A.total;
+            for (unsigned long long b = b0; b < e0; b += 64ull) {
+                unsigned long long gid = b + lane;
+                bool act = gid < e0;
+                Part p;
+                if (act) {
+                    int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
+                    const ProbDev &P = probs[pi];
+                    source<GEOM, MODE>(P, tabs_for<BATCH>(P, tl), p, (uint32_t)(P.first + (gid - P.gbase)),
+                                       (uint32_t)pi);
+                }
+                wc.outcomes(act, O_SOURCE);
+                wc.c[C_MAKE_WORK] += 1;
+                push<LAY, E>(A, bout, set_out, home, act, EV_STEP, p, dig, ln.err);
+            }
+        }
+    }
+    // otherwise: source new histories (256 per claim) until the fullest
     // output stack passes the threshold or the source is exhausted
-    for (;;) {
+    for (; A.static_share == 0;) {
         unsigned long long cur = __hip_atomic_load(&A.ctl->src_cursor, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (cur >= A.total) break;
         unsigned long long fullest = 0;
@@ -337,6 +385,11 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.tail_events = a.stack_tail_events > 0 ? a.stack_tail_events : 16;
     A.min_events = a.stack_min_events > 0 ? a.stack_min_events : 1;
     A.tl_bytes = BATCH ? 0 : a.tl_bytes;
+    // every history fits and the threshold would not stop the source: round 0
+    // sources them all, each wavefront its own share (a multiple of 64)
+    A.static_share = 0;
+    if (thr >= (long)a.total && cap >= (long)a.total + slack)
+        A.static_share = ((a.total + (unsigned long long)waves - 1) / (unsigned long long)waves + 63) / 64 * 64;
     e = hipMemsetAsync(A.sizes, 0, ctr_bytes, a.stream);
     if (e != hipSuccess) return e;
     size_t lds = lds_need;

@@ -423,25 +423,46 @@ __device__ __forceinline__ void add_lds(unsigned long long *p, unsigned long lon
     __hip_atomic_fetch_add((lu64 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// lt: this block's LDS copy of the bins (a small tally: every flight would hit
-// the same few global words, and the device serialises atomics per address),
-// or null to add into the global tally directly
+// Where a flight's tally pieces go, read from the problem record once per
+// flight rather than per piece (inside the mesh walk every such read is a
+// scalar load the piece would wait for): this block's LDS copy of the bins
+// (a small tally: every flight would hit the same few global words, and the
+// device serialises atomics per address), or the global tally, or for a
+// large energy-bin tally this wavefront's replica (particles of a round or
+// wavefront have similar energies and hit the same few bins, so the adds are
+// spread over replicas); the fixed-point scale; pass A's dL/dT.
+struct Sink {
+    unsigned long long *lt;
+    unsigned long long *g;
+    double tscale;
+    const double *w;
+};
+
 template <int MODE>
-__device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long bin, double len,
-                                      unsigned long long *lt = nullptr)
+__device__ __forceinline__ Sink sink_of(const ProbDev &P, const Lane &ln, unsigned long long *lt)
+{
+    Sink k;
+    k.lt = lt;
+    k.g = nullptr;
+    k.tscale = 0.0;
+    k.w = nullptr;
+    if (MODE == MODE_FWD) {
+        k.g = P.trep ? P.trep + (size_t)ln.rep * (size_t)P.n_bins : P.tally;
+        k.tscale = P.tscale;
+    } else if (MODE == MODE_REPLAY_A) {
+        k.w = gptr(P.w);
+    }
+    return k;
+}
+
+template <int MODE>
+__device__ __forceinline__ void score(const Sink &k, Lane &ln, Part &p, long bin, double len)
 {
     if (MODE == MODE_FWD) {
-        long long q = (long long)to_fixed(len, P.tscale);
+        long long q = (long long)to_fixed(len, k.tscale);
         if (q != 0) {
-            if (lt) {
-                add_lds(lt + bin, (unsigned long long)q);
-            } else {
-                // a large energy-bin tally: particles of a round or wavefront
-                // have similar energies and hit the same few bins, so the adds
-                // are spread over replicas
-                unsigned long long *dst = P.trep ? P.trep + (size_t)ln.rep * (size_t)P.n_bins : P.tally;
-                add_global(dst + bin, (unsigned long long)q);
-            }
+            if (k.lt) add_lds(k.lt + bin, (unsigned long long)q);
+            else add_global(k.g + bin, (unsigned long long)q);
             p.hq += q;
             unsigned long long before = ln.q;
             ln.q = before + (unsigned long long)q;
@@ -449,7 +470,7 @@ __device__ __forceinline__ void score(const ProbDev &P, Lane &ln, Part &p, long 
             ln.pieces += 1;
         }
     } else if (MODE == MODE_REPLAY_A) {
-        p.G = p.G + (gptr(P.w)[bin] * len);
+        p.G = p.G + (k.w[bin] * len);
     }
 }
 
@@ -479,30 +500,30 @@ __device__ __forceinline__ int time_bin(double t, double dt, int n)
 // particle's time t0 + s / v passes a bin edge: the edge closing bin k lies
 // at s = ((k + 1) tw - t0) v; the last time bin takes the rest.
 template <int MODE, int EXT>
-__device__ __forceinline__ void score_piece(const ProbDev &P, Lane &ln, Part &p, TSplit &ts, long bin, double a,
-                                            double b, unsigned long long *lt)
+__device__ __forceinline__ void score_piece(const ProbDev &P, const Sink &sk, Lane &ln, Part &p, TSplit &ts, long bin,
+                                            double a, double b)
 {
     if (!EXT) {
-        score<MODE>(P, ln, p, bin, b - a, lt);
+        score<MODE>(sk, ln, p, bin, b - a);
         return;
     }
     if (P.n_tbins <= 0) {
-        score<MODE>(P, ln, p, bin, (b - a) * p.wgt, lt);
+        score<MODE>(sk, ln, p, bin, (b - a) * p.wgt);
         return;
     }
     for (;;) {
         const int k = ts.k;
         const long kb = (long)k * P.nbase + bin;
         if (k + 1 >= P.n_tbins) {
-            score<MODE>(P, ln, p, kb, (b - a) * p.wgt, lt);
+            score<MODE>(sk, ln, p, kb, (b - a) * p.wgt);
             return;
         }
         double se = (((double)(k + 1) * P.tw) - ts.t0) * ts.v;
         if (se >= b) {
-            score<MODE>(P, ln, p, kb, (b - a) * p.wgt, lt);
+            score<MODE>(sk, ln, p, kb, (b - a) * p.wgt);
             return;
         }
-        score<MODE>(P, ln, p, kb, (se - a) * p.wgt, lt);
+        score<MODE>(sk, ln, p, kb, (se - a) * p.wgt);
         a = se;
         ts.k = k + 1;
     }
@@ -521,8 +542,8 @@ __device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, do
 // position: visit the mesh cells the segment crosses; every crossing
 // parameter is measured from the flight start; ties go x, y, z.
 template <int MODE, int EXT, class TB>
-__device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &ln, Part &p, double d, int g,
-                                          TSplit &ts, unsigned long long *lt)
+__device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, const Sink &sk, Lane &ln, Part &p, double d,
+                                          int g, TSplit &ts)
 {
     const int n0 = P.mesh_n[0], n1 = P.mesh_n[1], n2 = P.mesh_n[2];
     const double *mx = T.mx(), *my = T.my(), *mz = T.mz();
@@ -540,7 +561,7 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, Lane &l
         if (t2 < tm) { tm = t2; a = 2; }
         double tend = (tm < d) ? tm : d;
         long bin = (((long)g * n2 + i2) * n1 + i1) * n0 + i0;
-        score_piece<MODE, EXT>(P, ln, p, ts, bin, tprev, tend, lt);
+        score_piece<MODE, EXT>(P, sk, ln, p, ts, bin, tprev, tend);
         if (tm >= d) break;
         if (a == 0) {
             i0 += (p.u > 0.0) ? 1 : -1;
@@ -584,8 +605,9 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         pass_b_add<MODE>(P, cx, 0, m * P.n_grp + g, (long long)to_fixed(p.G * d, P.gscale));
         return;
     }
+    const Sink sk = sink_of<MODE>(P, ln, cx.ltally);
     if (P.tally_kind == 0) {
-        walk_mesh<MODE, EXT>(P, T, ln, p, d, g, ts, cx.ltally);
+        walk_mesh<MODE, EXT>(P, T, sk, ln, p, d, g, ts);
     } else {
         int k;
         if (P.ebin_inv != 0.0) {
@@ -596,7 +618,7 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         } else {
             k = edge_index(gptr(P.eedges), P.n_ebins, p.e, 1.0);
         }
-        score_piece<MODE, EXT>(P, ln, p, ts, k, 0.0, d, cx.ltally);
+        score_piece<MODE, EXT>(P, sk, ln, p, ts, k, 0.0, d);
     }
     if (MODE == MODE_REPLAY_A) p.L = p.L + d;
 }

@@ -105,6 +105,7 @@ def lib():
         L.mcx_tallies.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64, C.c_int32]
         L.mcx_backward.argtypes = [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, P(RunOpts)]
         L.mcx_counters.argtypes = [C.c_void_p, P(Counters)]
+        L.mcx_stack_rounds.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, P(C.c_int32)]
         L.mcx_run_eigen.argtypes = [C.c_void_p, P(RunOpts), P(EigenOpts)]
         L.mcx_workspace_size.argtypes = [C.c_void_p, P(RunOpts), P(C.c_size_t)]
         L.mcx_problem_info.argtypes = [C.c_void_p, C.c_int32, P(C.c_int64), P(C.c_int32), P(C.c_int32),
@@ -377,6 +378,14 @@ class Problem:
         w = np.ascontiguousarray(dl_dt, np.float64)
         self._check(lib().mcx_backward(self.h, problem, _ptr(w), _ptr(gt), _ptr(gs), HOST, C.byref(o)))
         return gt, gs
+
+    def stack_rounds(self) -> np.ndarray:
+        """Input particles of each remapping round of the last stack pass."""
+        n = C.c_int32(0)
+        self._check(lib().mcx_stack_rounds(self.h, None, 0, C.byref(n)))
+        out = np.zeros(n.value, np.uint32)
+        self._check(lib().mcx_stack_rounds(self.h, _ptr(out), n.value, C.byref(n)))
+        return out
 
     def counters(self) -> dict:
         c = Counters()

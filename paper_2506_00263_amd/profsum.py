@@ -12,7 +12,14 @@ traffic per launch used by bench.py's roofline record.  Byte counters are
 scaled by what the same counter reads for the final 1 GiB device-to-device
 copy of the run (a kernel of known traffic).
 
+The kernel-trace run's standard output (bench.py's JSON line) is kept as
+<dir>/trace_<sched>/bench.json; for the stack scheduler, whose every
+remapping round is a launch, the summary then lists each round of the last
+run: its input population (from bench.py) and its duration (from the
+trace).
+
 Usage: python -m paper_2506_00263_amd.profsum <dir> <out_dir> [--workload NAME] [--decomp split]
+           [--bench-args "..."]
 """
 from __future__ import annotations
 
@@ -84,7 +91,32 @@ def kernel_stats(d: str, sched: str):
     return None
 
 
-def summarise(d: str, out_dir: str, workload: str, decomp: str = "fused") -> dict:
+def launch_durations(d: str, sched: str):
+    """Durations (ns) of the scheduler kernel's dispatches in start order."""
+    rows = _csv(os.path.join(d, f"trace_{sched}", "**", "*kernel_trace.csv"))
+    ds = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+          for r in rows if KERNELS[sched] in r["Kernel_Name"]]
+    return [dur for _, dur in sorted(ds)]
+
+
+def round_table(d: str, sched: str):
+    """Per-round rows (round, input particles, duration us) of the last run
+    of a stack trace, or None."""
+    try:
+        with open(os.path.join(d, f"trace_{sched}", "bench.json")) as fh:
+            bench = json.loads(fh.read().strip().splitlines()[-1])
+    except (OSError, ValueError, IndexError):
+        return None
+    rounds = bench.get("stack_rounds")
+    n = bench.get("counters", {}).get("launches")
+    durs = launch_durations(d, sched)
+    if not rounds or not n or len(durs) < n:
+        return None
+    last = durs[-n:]
+    return [(r, rounds[r] if r < len(rounds) else 0, last[r] / 1e3) for r in range(n)]
+
+
+def summarise(d: str, out_dir: str, workload: str, decomp: str = "fused", bench_args: str = "") -> dict:
     src = build.source_hash()
     traffic = {}
     for sched, kern in KERNELS.items():
@@ -104,12 +136,17 @@ def summarise(d: str, out_dir: str, workload: str, decomp: str = "fused") -> dic
         lines.append("")
         lines.append("```")
         dflag = "" if decomp == "fused" else f" --decomp {decomp}"
+        bflag = f" {bench_args}" if bench_args else ""
         lines.append(f"rocprofv3 --kernel-trace --stats -d <dir>/trace_{sched} -o run --output-format csv -- "
-                     f"python3 bench.py --sched {sched}{dflag} --steps 5 --warmup 1 --no-extras --no-cpu")
+                     f"python3 bench.py --sched {sched}{dflag}{bflag} --steps 5 --warmup 1 --no-extras --no-cpu"
+                     f" > <dir>/trace_{sched}/bench.json")
         for p, cs in PASSES.items():
             lines.append(f"rocprofv3 --pmc {' '.join(cs)} -d <dir>/{p}_{sched} -o run --output-format csv -- "
-                         f"python3 bench.py --sched {sched}{dflag} --steps 1 --warmup 1 --no-extras --no-cpu --copy-mib 1024")
-        lines.append(f"python3 -m paper_2506_00263_amd.profsum <dir> profiles{dflag}")
+                         f"python3 bench.py --sched {sched}{dflag}{bflag} --steps 1 --warmup 1 --no-extras --no-cpu "
+                         f"--copy-mib 1024")
+        wflag = f" --workload {workload}"
+        aflag = f" --bench-args '{bench_args}'" if bench_args else ""
+        lines.append(f"python3 -m paper_2506_00263_amd.profsum <dir> profiles{dflag}{wflag}{aflag}")
         lines.append("```")
         lines.append("")
         if st:
@@ -145,14 +182,31 @@ def summarise(d: str, out_dir: str, workload: str, decomp: str = "fused") -> dic
             for c in PASSES["sq2"]:
                 lines.append(f"| {c} | {b[c]:.4g} |")
         lines.append("")
+        rt = round_table(d, sched) if sched == "stack" else None
+        if rt:
+            lines.append("Remapping rounds of the last run (input particles from bench.py's `stack_rounds`, "
+                         "duration from the kernel trace; rounds past the last one are queued launches that "
+                         "exit at once):")
+            lines.append("")
+            lines.append("| round | input particles | duration (us) |")
+            lines.append("|---|---|---|")
+            for r, n_in, us in rt:
+                lines.append(f"| {r} | {n_in} | {us:.1f} |")
+            tot = sum(us for _, _, us in rt)
+            big = sum(us for _, n_in, us in rt if n_in >= 100_000)
+            lines.append("")
+            lines.append(f"Total {tot:.1f} us over {len(rt)} launches; rounds with at least 1e5 input particles "
+                         f"{big:.1f} us, the rest {tot - big:.1f} us.")
+            lines.append("")
         os.makedirs(out_dir, exist_ok=True)
         with open(os.path.join(out_dir, f"{kern}_{workload.replace(' ', '_')}.md"), "w") as fh:
             fh.write("\n".join(lines))
         if rd is not None and wr is not None:
             traffic[kern] = {"bytes_per_launch": rd + wr, "read": rd, "write": wr, "source_hash": src,
                              "workload": workload, "read_scale": rf, "write_scale": rw}
-    # the default (fused) figures are the ones bench.py reports
-    tname = "traffic.json" if decomp == "fused" else f"traffic_{decomp}.json"
+    # the default (fused lattice) figures are the ones bench.py reports
+    tname = {"lattice_1e6": "traffic.json", "lattice_1e6_split": "traffic_split.json"}.get(
+        workload, f"traffic_{workload}.json")
     with open(os.path.join(out_dir, tname), "w") as fh:
         json.dump(traffic, fh, indent=1, sort_keys=True)
     return traffic
@@ -164,9 +218,10 @@ def main():
     ap.add_argument("out")
     ap.add_argument("--workload", default=None)
     ap.add_argument("--decomp", default="fused", choices=["fused", "split"])
+    ap.add_argument("--bench-args", default="", help="extra bench.py arguments the profiled runs used")
     a = ap.parse_args()
     wl = a.workload or ("lattice_1e6" if a.decomp == "fused" else f"lattice_1e6_{a.decomp}")
-    print(json.dumps(summarise(a.dir, a.out, wl, a.decomp), indent=1))
+    print(json.dumps(summarise(a.dir, a.out, wl, a.decomp, a.bench_args), indent=1))
 
 
 if __name__ == "__main__":

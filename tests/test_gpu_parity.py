@@ -100,6 +100,26 @@ def test_ce_jittered_grid_hash(mcx, oracle):
         assert np.array_equal(P.tallies(), ref["tally"])
 
 
+def test_ce_four_species_split(mcx, oracle):
+    # four species, split events on both remapping schedulers: the collision
+    # event repeats the lookup's search for every species
+    d = inputs.pincell_ce(n_ebins=200, n_histories=1000, grid_len=5000)
+    n = d["grid_len"]
+    eg, sa, ss = (np.asarray(d[k]).reshape(3, n) for k in ("e_grid", "sig_a", "sig_s"))
+    d.update(n_species=4, e_grid=np.concatenate([eg.ravel(), eg[0]]),
+             sig_a=np.concatenate([sa.ravel(), 0.5 * sa[1]]), sig_s=np.concatenate([ss.ravel(), 2.0 * ss[2]]),
+             awr=np.append(d["awr"], 55.0),
+             density=np.array([[*np.asarray(d["density"]).reshape(2, 3)[0], 0.01],
+                               [*np.asarray(d["density"]).reshape(2, 3)[1], 0.005]]).ravel())
+    ref = oracle.run(d)
+    P = mcx.Problem(d)
+    for sched in ("async", "stack"):
+        for lookup in ("binary", "hash"):
+            P.run(sched=sched, decomp="split", lookup=lookup)
+            assert np.array_equal(P.tallies(), ref["tally"]), (sched, lookup)
+            _check_counts(P.counters(), ref["counts"])
+
+
 def test_batch_cfg5(mcx, oracle):
     probs = inputs.cfg5_batch(n_problems=40, hist_scale=0.03)
     refs = [oracle.run(d) for d in probs]
