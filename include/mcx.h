@@ -207,7 +207,7 @@ typedef struct {
     int32_t stack_tail_events;/* stack: when the live particles no longer fill
                                  the resident wavefronts, a popped particle
                                  runs up to this many events before it is
-                                 pushed (0 = default 16, 1 = one per round)   */
+                                 pushed (0 = default 64, 1 = one per round)   */
     int32_t stack_min_events; /* stack: events a popped particle runs before it
                                  is pushed again, at least (0 = default 1:
                                  remap after every event)                     */
@@ -227,6 +227,15 @@ typedef struct {
                                  filled link's particles run up to this many
                                  events in place before they are packed again
                                  (0 = library default, 8; 1 = one per pass)   */
+    int32_t async_shared_stash;/* async: 1 = the wavefronts of a block share one
+                                 stash of work links through lock-free
+                                 transactions (paper Sec. 5.2: one stash used
+                                 by several warps for higher occupancy);
+                                 stash_links then sizes the block's pool
+                                 (0 = one link per event, one per wavefront
+                                 and two more; at most 32).  0 = library
+                                 default (one stash per wavefront), 2 = one
+                                 stash per wavefront                         */
     void *workspace;          /* optional caller-owned device memory (on the
                                  handle's device, 256-byte aligned) of ws_bytes
                                  bytes for the run's scheduler state and tally
@@ -305,19 +314,28 @@ typedef struct {
 } mcx_eigen_opts;
 
 /* Create a handle for n_problems independent problems (a batch runs all of
- * them in one launch).  All problems of a batch must share geometry kind,
+ * them in one launch).  The problems are those of the paper's Sec. 4 (a
+ * multigroup lattice and a continuous-energy pin cell, with mesh, energy and
+ * time tallies) and simpler boxes for checks.  All problems of a batch must share geometry kind,
  * energy mode and tally kind.  Invalid descriptors are rejected with no side
  * effect.  Uses the current HIP device. */
 mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t n_problems, mcx_problem_t *out);
 
 /* Replace the multigroup Sigma_t, Sigma_s [n_mat*n_grp] of one problem
- * (transfer probabilities stay).  Both must satisfy 0 <= Sigma_s <= Sigma_t,
+ * (transfer probabilities stay): the parameters of the differentiable run
+ * (no passage of the paper; see mcx_backward).  Both must satisfy 0 <= Sigma_s <= Sigma_t,
  * Sigma_t > 0. */
 mcx_status mcx_set_xs(mcx_problem_t p, int32_t problem, const double *sigma_t, const double *sigma_s,
                       int32_t where);
 
 /* Run histories through the selected scheduler (forward transport with
- * tallies).  Synchronises the run's stream before returning. */
+ * tallies): the event loop of the paper's Sec. 4 (monolithic or decomposed
+ * events) under thread-data remapping (Sec. 2), stack-based (Sec. 3.1) or
+ * asynchronous (Sec. 3.2), with histories generated on demand from an atomic
+ * counter and keyed random numbers (Sec. 3).  Synchronises the run's stream
+ * before returning.  Errors: MCX_E_INVALID_ARG (bad options, history range
+ * or workspace; nothing runs), MCX_E_CAPACITY (stack or link arena full),
+ * MCX_E_OVERFLOW, MCX_E_DEVICE; on any error the tallies read MCX_E_STATE. */
 mcx_status mcx_run(mcx_problem_t p, const mcx_run_opts *opts);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -339,10 +357,13 @@ mcx_status mcx_run(mcx_problem_t p, const mcx_run_opts *opts);
 #define MCX_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 mcx_status mcx_run_noalloc(mcx_problem_t p, const mcx_run_opts *opts);
 
-/* Copy problem `problem`'s raw int64 tally (n = its bin count) to out. */
+/* Copy problem `problem`'s raw int64 tally (n = its bin count) to out: the
+ * track-length tallies of the paper's Sec. 4 (mesh, or energy bins with an
+ * optional time dimension).  MCX_E_STATE without a successful run. */
 mcx_status mcx_tallies(mcx_problem_t p, int32_t problem, int64_t *out, int64_t n, int32_t where);
 
-/* Score-function (likelihood-ratio) backward of the last forward run: for
+/* Score-function (likelihood-ratio) backward of the last forward run (the
+ * paper has no derivatives; this is the differentiable extension): for
  * T_b = raw_b 2^-S / N (per problem, N = histories run), given dL/dT_b,
  * returns grad Sigma_t and grad Sigma_s [n_mat*n_grp] of
  * sum_b dL/dT_b dE[T_b]/d theta, estimated by replaying every history from
@@ -358,20 +379,25 @@ mcx_status mcx_tallies(mcx_problem_t p, int32_t problem, int64_t *out, int64_t n
 mcx_status mcx_backward(mcx_problem_t p, int32_t problem, const double *dL_dT, double *grad_sigma_t,
                         double *grad_sigma_s, int32_t where, const mcx_run_opts *opts);
 
-/* Run a k-eigenvalue calculation (see mcx_eigen_opts) through the scheduler
- * and tuning of opts (its range, accumulate and digest fields are ignored).
+/* Run a k-eigenvalue calculation (see mcx_eigen_opts; the C5G7 power
+ * iteration with splitting-roulette population control of the paper's
+ * Sec. 4) through the scheduler and tuning of opts (its range, accumulate and digest fields are ignored).
  * On success the tallies hold the active cycles' sum and k_cycle, n_source
  * are filled; mcx_backward does not apply to it. */
 mcx_status mcx_run_eigen(mcx_problem_t p, const mcx_run_opts *opts, const mcx_eigen_opts *eig);
 
 /* Device scratch (bytes) that mcx_run, and mcx_backward after it, with
  * these options need for their scheduler state (stack banks and counters,
- * or the async link arena) and tally replicas: the smallest opts.workspace
+ * Sec. 3.1 of the paper; or the async scheduler's global link arena, its
+ * reservoir for spilled work links, Sec. 3.2) and tally replicas: the smallest opts.workspace
  * they accept.  0 for the naive scheduler without replicas.  Without a
  * caller workspace the library grows its own to this size and keeps it.
  * Allocates and launches nothing. */
 mcx_status mcx_workspace_size(mcx_problem_t p, const mcx_run_opts *opts, size_t *bytes);
 
+/* Totals of the last run (see mcx_counters_t): events, lane slots and
+ * launches measure the remapping itself (the paper's Sec. 5.1 calls for
+ * profiling to find what limits it). */
 mcx_status mcx_counters(mcx_problem_t p, mcx_counters_t *out);
 
 /* Stack scheduler (paper Sec. 3.1: one launch per remapping round): the
@@ -381,11 +407,16 @@ mcx_status mcx_counters(mcx_problem_t p, mcx_counters_t *out);
  * (0 after a run of another scheduler). */
 mcx_status mcx_stack_rounds(mcx_problem_t p, uint32_t *particles, int32_t max_rounds, int32_t *n_rounds);
 
-/* Sizes of problem `problem`: tally bins, materials, groups, histories. */
+/* Sizes of problem `problem`: tally bins, materials, groups, histories
+ * (bookkeeping, no passage). */
 mcx_status mcx_problem_info(mcx_problem_t p, int32_t problem, int64_t *n_bins, int32_t *n_mat, int32_t *n_grp,
                             uint64_t *n_histories);
 
+/* Free the handle and everything the library allocated for it (never caller
+ * memory).  NULL is a no-op. */
 void mcx_destroy_problem(mcx_problem_t p);
+/* Static text of a status; the handle's last error message (owned by the
+ * handle, valid until its next call). */
 const char *mcx_status_str(mcx_status s);
 const char *mcx_last_error(mcx_problem_t p);
 

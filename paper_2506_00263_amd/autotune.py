@@ -1,9 +1,11 @@
 """Autotuner for the remapping schedulers.
 
 Grid search over the tuning knobs of a scheduler (async: wavefronts per
-block, resident wavefronts per CU and stash links; stack: events a popped particle runs
-before it is pushed again, at least and in the tail; naive: block size) on a
-calibration run, timed with HIP events inside the library.  Knobs never
+block, resident wavefronts per CU, stash links and events a drained
+wavefront runs in place; stack: events a popped particle runs before it is
+pushed again, at least and in the tail, the make_work threshold and resident
+wavefronts per CU; naive: block size) on a calibration run, timed with HIP
+events inside the library.  Knobs never
 change results: every candidate's tally is checked against the first
 candidate's.  The best choice is cached per (problem class, scheduler,
 decomposition, device).
@@ -21,19 +23,26 @@ from . import mcx
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_autotune_cache.json")
 
 
-def candidates(sched: str, decomp: str) -> list:
+def candidates(sched: str, decomp: str, histories: int = 0) -> list:
     """Knob settings tried for one scheduler (0 = library default); the
-    first, with no knob set, is the library's own default choice."""
+    first, with no knob set, is the library's own default choice.  Stack
+    thresholds are fractions of the run's histories (the default stack
+    capacity holds them all, so no candidate can run out of room)."""
     events = 4 if decomp == "split" else 1
     out = [dict()]
     if sched == "async":
         for wpb in (4, 2, 1):
-            for wpc in (0, 8):
+            for wpc in (0, 4, 8):
                 for links in sorted({events + 1, events + 2, events + 3}):
                     out.append(dict(async_block_waves=wpb, waves_per_cu=wpc, stash_links=links))
+        out += [dict(async_drain_events=k) for k in (1, 4, 16, 64)]
         return out
     if sched == "stack":
-        return out + [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 256)]
+        out += [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 64, 256)]
+        out += [dict(waves_per_cu=w) for w in (4, 8)]
+        if histories >= 4096:
+            out += [dict(stack_threshold=max(256, histories // f)) for f in (2, 8, 32)]
+        return out
     return out + [dict(block_size=b) for b in (64, 128, 256)]
 
 
@@ -74,7 +83,8 @@ def tune(P: "mcx.Problem", sched: str = "async", decomp: str = "fused", lookup: 
         run_kw.update(first=0, n=min(calib_histories, P.descs[0]["n_histories"]))
     results = []
     ref = None
-    for cand in candidates(sched, decomp):
+    hist = run_kw.get("n") or sum(int(d["n_histories"]) for d in P.descs)
+    for cand in candidates(sched, decomp, hist):
         times = []
         for _ in range(reps + 1):
             P.run(time_kernels=True, **run_kw, **cand)

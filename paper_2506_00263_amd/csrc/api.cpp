@@ -747,6 +747,8 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
     if (o.async_block_waves != 0 && o.async_block_waves != 1 && o.async_block_waves != 2 &&
         o.async_block_waves != 4)
         return fail(h, MCX_E_INVALID_ARG, "async_block_waves must be 0, 1, 2 or 4");
+    if (o.async_shared_stash < 0 || o.async_shared_stash > 2)
+        return fail(h, MCX_E_INVALID_ARG, "async_shared_stash must be 0, 1 or 2");
     if (o.async_drain_events < 0 || o.async_drain_events > 1024)
         return fail(h, MCX_E_INVALID_ARG, "async_drain_events must be in [0, 1024]");
     if (o.workspace && ((uintptr_t)o.workspace % 256) != 0)
@@ -827,6 +829,7 @@ static LaunchArgs launch_args(mcx_problem_t h, const mcx_run_opts &o, int mode, 
     a.stack_min_events = o.stack_min_events;
     a.async_block_waves = o.async_block_waves;
     a.async_drain_events = o.async_drain_events;
+    a.async_shared = o.async_shared_stash;
     a.ws_query = nullptr;
     a.poll[0] = h->poll[0];
     a.poll[1] = h->poll[1];

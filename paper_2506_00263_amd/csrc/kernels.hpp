@@ -80,6 +80,7 @@ struct LaunchArgs {
     int stack_min_events;                  // stack: events per pop at least (0 = default 1)
     int async_block_waves;                 // async: wavefronts per block, 1, 2 or 4 (0 = ASYNC_BLOCK_WAVES)
     int async_drain_events;                // async: events per pass on a drained wavefront's partial link (0 = default)
+    int async_shared;                      // async: 1 = the block's wavefronts share one stash (0, 2: one each)
     size_t *ws_query;                      // non-null: only report the workspace bytes the launch
                                            // needs (nothing is allocated or launched)
     hipEvent_t poll[2];                    // stack: two events (timing off) owned by the handle,

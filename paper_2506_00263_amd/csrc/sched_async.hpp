@@ -559,6 +559,407 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Block-shared stash (the paper's Sec. 5.2 remedy for the stash's occupancy
+// cost: lock-free stash transactions let several warps use one stash).  The
+// wavefronts of a block share one pool of work links in LDS:
+//  free, ready   bit masks of links; a wavefront claims a bit with an atomic
+//                AND whose returned old value shows it was still set;
+//  part[k]       the link being filled with particles of event k, tagged
+//                (tag << 8 | link), or SH_NONE;
+//  resv[l]       (tag << 16) | slots reserved: a depositor reserves slots with
+//                a compare-and-swap that requires the tag it read in part[k]
+//                and fewer than 64 reserved, so a reservation can never land
+//                on a link that has since been recycled;
+//  wrt[l]        slots written; the writer that completes the 64th slot
+//                publishes the link as ready, the one that reserves it takes
+//                the link out of part[k];
+//  busy          wavefronts of the block holding particles outside the pool.
+// A drained wavefront closes a partial link (takes it out of part[k], then
+// adds 64 to its reservation), waits for the reserved slots to be written and
+// runs it: the partial links of all the block's wavefronts merge.  A block's
+// wavefronts leave once its pool is empty, none of them holds particles and
+// the arena has nothing left.  The pool needs no per-wavefront slack (one
+// partial link per event plus a few), so a block of several wavefronts takes
+// far less LDS than as many private stashes.
+constexpr uint32_t SH_NONE = 0xFFFFFFFFu;
+constexpr int SH_MAX_LINKS = 32;
+
+struct SharedCtl {
+    uint32_t freem, readym, busy, pad;
+    uint32_t part[4];
+    uint32_t resv[SH_MAX_LINKS], wrt[SH_MAX_LINKS], ev[SH_MAX_LINKS];
+};
+
+typedef __attribute__((address_space(3))) uint32_t lu32;
+
+__device__ __forceinline__ uint32_t sh_load(uint32_t *p)
+{
+    uint32_t v = 0;
+    if (__lane_id() == 0) v = __hip_atomic_load((lu32 *)p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return first_lane_u32(v);
+}
+
+__device__ __forceinline__ void sh_store(uint32_t *p, uint32_t v)
+{
+    if (__lane_id() == 0) __hip_atomic_store((lu32 *)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ uint32_t sh_add(uint32_t *p, uint32_t v)
+{
+    // all lanes' earlier LDS writes (link slots) complete before the count moves
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t old = 0;
+    if (__lane_id() == 0) old = __hip_atomic_fetch_add((lu32 *)p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return first_lane_u32(old);
+}
+
+__device__ __forceinline__ void sh_or(uint32_t *p, uint32_t v)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (__lane_id() == 0) __hip_atomic_fetch_or((lu32 *)p, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ bool sh_cas(uint32_t *p, uint32_t expect, uint32_t want)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    uint32_t ok = 0;
+    if (__lane_id() == 0)
+        ok = __hip_atomic_compare_exchange_strong((lu32 *)p, &expect, want, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP)
+                 ? 1u
+                 : 0u;
+    return first_lane_u32(ok) != 0u;
+}
+
+// claim one set bit of a mask; -1 if none
+__device__ __forceinline__ int sh_claim(uint32_t *mask)
+{
+    int r = -1;
+    if (__lane_id() == 0) {
+        for (;;) {
+            uint32_t v = __hip_atomic_load((lu32 *)mask, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (v == 0u) break;
+            int l = __ffs(v) - 1;
+            uint32_t old = __hip_atomic_fetch_and((lu32 *)mask, ~(1u << l), __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old & (1u << l)) {
+                r = l;
+                break;
+            }
+        }
+    }
+    r = (int)first_lane_u32((uint32_t)r);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");   // every lane then reads the link
+    return r;
+}
+
+struct SharedWave {
+    const AsyncArgs &A;
+    char *links;                 // the block's pool
+    SharedCtl *C;
+    int nd, nu;
+    uint32_t qstart;
+    uint32_t tick;               // published links so far (forced spills)
+    __device__ SoA link(int l) const { return SoA{links + (long)l * A.link_bytes, 64, nd}; }
+    __device__ SoA alink(uint32_t a) const { return SoA{A.arena + (long)a * A.link_bytes, 64, nd}; }
+
+    // copy full link v of the pool to the global arena
+    __device__ __forceinline__ bool spill(int v)
+    {
+        uint32_t a = arena_pop(A, A.qempty, qstart);
+        for (Wait w; a == NIL && wait_on(A, w);) {
+            __builtin_amdgcn_s_sleep(4);
+            a = arena_pop(A, A.qempty, qstart);
+        }
+        if (a == NIL) return false;
+        copy_slot(alink(a), __lane_id(), link(v), __lane_id(), nd, nu);
+        lane0_store(&A.hdr[a], sh_load(&C->ev[v]) | (64u << 8));
+        __threadfence();                              // release the link data
+        if (!arena_push(A, A.qfull, qstart, a)) return false;
+        if (__lane_id() == 0) atomicAdd(A.fill, 1u);
+        return true;
+    }
+
+    // a link of the pool for this wavefront: a free one, else a ready one
+    // spilled to the arena; -1 on failure (recorded)
+    __device__ __forceinline__ int alloc(WaveCount &wc, uint32_t &err)
+    {
+        for (Wait w;;) {
+            int l = sh_claim(&C->freem);
+            if (l >= 0) return l;
+            int v = sh_claim(&C->readym);
+            if (v >= 0) {
+                if (spill(v)) {
+                    wc.c[C_SPILLS] += 1;
+                    return v;
+                }
+                fail_capacity(A, err);
+                return -1;
+            }
+            // every link is a partial or held by another wavefront for a moment
+            if (!wait_on(A, w)) {
+                fail_capacity(A, err);
+                return -1;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+    }
+
+    // the link of event k is complete: publish it (or, forced, spill it)
+    __device__ __forceinline__ void publish(int l, WaveCount &wc, uint32_t &err)
+    {
+        if (A.force_spill > 0 && ++tick % (uint32_t)A.force_spill == 0) {
+            if (spill(l)) {
+                wc.c[C_SPILLS] += 1;
+                sh_or(&C->freem, 1u << l);
+            } else {
+                fail_capacity(A, err);
+            }
+            return;
+        }
+        sh_or(&C->readym, 1u << l);
+    }
+
+    // add this wavefront's particles to the shared partial links of their next events
+    template <class LAY, int E>
+    __device__ __forceinline__ void deposit(bool act, int ne, const Part &p, bool dig, WaveCount &wc, uint32_t &err)
+    {
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            bool mine = act && ne == k;
+            Wait w;
+            for (;;) {
+                uint64_t mask = __ballot(mine);
+                if (mask == 0) break;
+                const uint32_t n = (uint32_t)__popcll(mask);
+                const uint32_t pk = sh_load(&C->part[k]);
+                if (pk == SH_NONE) {
+                    int l = alloc(wc, err);
+                    if (l < 0) break;                 // particles dropped: the run has failed
+                    const uint32_t tag = ((sh_load(&C->resv[l]) >> 16) + 1u) & 0xFFFFu;
+                    sh_store(&C->resv[l], tag << 16);
+                    sh_store(&C->wrt[l], 0u);
+                    sh_store(&C->ev[l], (uint32_t)k);
+                    if (!sh_cas(&C->part[k], SH_NONE, (tag << 8) | (uint32_t)l)) sh_or(&C->freem, 1u << l);
+                    continue;
+                }
+                const int l = (int)(pk & 0xFFu);
+                const uint32_t tag = pk >> 8;
+                const uint32_t r = sh_load(&C->resv[l]);
+                if ((r >> 16) != tag || (r & 0xFFFFu) >= 64u) {
+                    // recycled or full: its filler or a closer takes it out of part[k]
+                    if (!wait_on(A, w)) {
+                        fail_capacity(A, err);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                const uint32_t f = r & 0xFFFFu;
+                const uint32_t take = n < 64u - f ? n : 64u - f;
+                if (!sh_cas(&C->resv[l], r, r + take)) continue;
+                const uint32_t rank = lane_rank(mask);
+                const bool put_now = mine && rank < take;
+                if (put_now) put<LAY>(link(l), (long)(f + rank), p, dig);
+                mine = mine && !put_now;
+                if (f + take == 64u) sh_cas(&C->part[k], pk, SH_NONE);
+                if (sh_add(&C->wrt[l], take) + take == 64u) publish(l, wc, err);
+            }
+        }
+    }
+
+    // close a partial link of some event and return it (its particle count
+    // in c), or -1 if none
+    __device__ __forceinline__ int steal(int E, uint32_t &c)
+    {
+        for (int k = 0; k < E; ++k) {
+            const uint32_t pk = sh_load(&C->part[k]);
+            if (pk == SH_NONE) continue;
+            if (!sh_cas(&C->part[k], pk, SH_NONE)) continue;
+            const int l = (int)(pk & 0xFFu);
+            const uint32_t tag = pk >> 8;
+            uint32_t count = 64u;
+            for (;;) {
+                const uint32_t r = sh_load(&C->resv[l]);
+                if ((r >> 16) != tag || (r & 0xFFFFu) >= 64u) break;   // filled meanwhile: published by its writer
+                if (sh_cas(&C->resv[l], r, r + 64u)) {
+                    count = r & 0xFFFFu;
+                    break;
+                }
+            }
+            if (count >= 64u) continue;
+            // reservations are written without waiting on anything
+            while (sh_load(&C->wrt[l]) != count) __builtin_amdgcn_s_sleep(1);
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+            c = count;
+            return l;
+        }
+        return -1;
+    }
+};
+
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BATCH ? (SPLIT ? 3 : 4) : 2)))
+async_shared_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
+{
+    using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
+    constexpr int E = SPLIT ? 4 : 1;
+    extern __shared__ __attribute__((aligned(16))) char lds[];
+    const bool dig = A.digest != nullptr;
+    const int NL = A.links;                                        // links in the block's pool
+    const int wib = (int)(threadIdx.x >> 6);
+    const unsigned int gw = blockIdx.x * (unsigned int)A.wpb + (unsigned int)wib;
+    const size_t pool_bytes = (size_t)NL * A.link_bytes;
+    SharedCtl *C = (SharedCtl *)(lds + pool_bytes);
+    const size_t head = pool_bytes + sizeof(SharedCtl);
+    unsigned long long *lacc = (unsigned long long *)(lds + head);
+    char *tl = lds + tabs_lds_offset(head + (size_t)A.lacc_words * 8);
+    if constexpr (!BATCH) tabs_to_lds(probs[0], tl);
+    EvCtx cx{probs, A.digest, (MODE == MODE_REPLAY_B && A.lacc_words > 0) ? lacc : nullptr, BATCH ? 0 : 1,
+             (MODE == MODE_FWD && A.lacc_words > 0) ? lacc : nullptr};
+    if (A.lacc_words > 0) lacc_zero(lacc, A.lacc_words);
+    if (threadIdx.x == 0) {
+        C->freem = NL >= 32 ? 0xFFFFFFFFu : ((1u << NL) - 1u);
+        C->readym = 0u;
+        C->busy = 0u;
+        for (int k = 0; k < 4; ++k) C->part[k] = SH_NONE;
+        for (int l = 0; l < SH_MAX_LINKS; ++l) {
+            C->resv[l] = 0u;
+            C->wrt[l] = 0u;
+            C->ev[l] = 0u;
+        }
+    }
+    __syncthreads();
+    Lane ln{0, 0, 0, 0, (uint32_t)(gw % TREP)};
+    WaveCount wc;
+    wc.zero();
+    const int lane = __lane_id();
+    SharedWave W{A, lds, C, LAY::nd(dig), LAY::nu(dig), gw * 2654435761u, 0u};
+    bool src_done = false;
+    Wait idle;
+    unsigned long long res_next = 0, res_end = 0;   // reserved source ids
+    for (;;) {
+        sh_add(&C->busy, 1u);
+        // what to run: a ready link, new histories, an arena link, a closed partial
+        bool have = false, fresh = false, drained = false;
+        int ev = 0, cnt = 0;
+        Part p;
+        bool act = false;
+        const int l = sh_claim(&C->readym);
+        if (l >= 0) {
+            ev = (int)sh_load(&C->ev[l]);
+            act = true;
+            get<LAY>(W.link(l), lane, p, dig);
+            sh_or(&C->freem, 1u << l);
+            have = true;
+        } else if (!src_done) {
+            if (res_next >= res_end) {
+                if (run_failed(A)) {
+                    src_done = true;
+                } else {
+                    unsigned long long b = 0;
+                    if (lane == 0) b = atomicAdd(&A.ctl->src_cursor, 256ull);
+                    b = first_lane_u64(b);
+                    if (b >= A.total) {
+                        src_done = true;
+                    } else {
+                        res_next = b;
+                        res_end = b + 256ull < A.total ? b + 256ull : A.total;
+                    }
+                }
+            }
+            if (!src_done) {
+                unsigned long long b = res_next;
+                res_next += 64ull;
+                unsigned long long gid = b + lane;
+                act = gid < res_end;
+                if (act) {
+                    int pi = BATCH ? find_problem(A.prefix, A.n_probs, gid) : 0;
+                    const ProbDev &P = probs[pi];
+                    source<GEOM, MODE>(P, tabs_for<BATCH>(P, tl), p, (uint32_t)(P.first + (gid - P.gbase)), (uint32_t)pi);
+                }
+                wc.outcomes(act, O_SOURCE);
+                wc.c[C_MAKE_WORK] += 1;
+                fresh = true;
+                have = true;
+            }
+        }
+        if (!have && arena_fill(A) != 0) {
+            uint32_t a = arena_pop(A, A.qfull, W.qstart);
+            if (a != NIL) {
+                if (lane == 0) atomicSub(A.fill, 1u);
+                uint32_t h = lane0_load(&A.hdr[a]);
+                ev = (int)(h & 0xFFu);
+                cnt = (int)(h >> 8);
+                act = lane < cnt;
+                if (act) get<LAY>(W.alink(a), lane, p, dig);
+                wc.c[C_REFILLS] += 1;
+                if (!arena_push(A, A.qempty, W.qstart, a)) fail_capacity(A, ln.err);
+                have = true;
+            }
+        }
+        if (!have) {
+            uint32_t c = 0;
+            const int sl = W.steal(E, c);
+            if (sl >= 0) {
+                ev = (int)sh_load(&C->ev[sl]);
+                act = lane < (int)c;
+                if (act) get<LAY>(W.link(sl), lane, p, dig);
+                sh_or(&C->freem, 1u << sl);
+                have = true;
+                drained = true;
+            }
+        }
+        if (!have) {
+            sh_add(&C->busy, 0xFFFFFFFFu);
+            // leave once the pool is empty, no wavefront of the block holds
+            // particles and the arena has nothing left; wait a bounded time
+            // while it does
+            bool empty = sh_load(&C->readym) == 0u && sh_load(&C->busy) == 0u;
+#pragma unroll
+            for (int k = 0; k < E; ++k)
+                if (sh_load(&C->part[k]) != SH_NONE) empty = false;
+            if (empty && arena_fill(A) == 0) break;
+            if (run_failed(A)) break;
+            if (!wait_on(A, idle)) {
+                if (arena_fill(A) != 0) fail_capacity(A, ln.err);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(8);
+            continue;
+        }
+        idle = Wait{};
+        int ne = EV_STEP;
+        if (!fresh) {
+            // run the event on the particles; a drained wavefront's closed
+            // partial link runs up to drain_events events in place
+            ne = EV_DEAD;
+            const int K = drained ? A.drain_events : 1;
+            int cur = ev;
+            bool live = act;
+            for (int i = 0;;) {
+                uint32_t out = 0;
+                if (live) ne = run_event_in<GEOM, EMODE, MODE, SPLIT, EXT, BATCH>(cur, probs, tl, cx, ln, p, out);
+                wc.dispatch(live);
+                wc.outcomes(live, out);
+                if (++i >= K) break;
+                live = live && ne != EV_DEAD;
+                if (__ballot(live) == 0) break;
+                cur = ne;
+            }
+        }
+        W.template deposit<LAY, E>(act, ne, p, dig, wc, ln.err);
+        sh_add(&C->busy, 0xFFFFFFFFu);
+    }
+    flush_wave(A.ctl, wc, ln, probs, BATCH ? 0 : 1, MODE);
+    if (A.lacc_words > 0) {
+        __syncthreads();
+        if (cx.lacc) lacc_flush(lacc, probs[0]);
+        if (cx.ltally) ltally_flush(lacc, probs[0], A.lacc_words);
+    }
+}
+
 static __global__ void arena_init(AsyncArgs A, unsigned int waves)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -577,12 +978,48 @@ static __global__ void arena_init(AsyncArgs A, unsigned int waves)
     }
 }
 
+// Launch shape of the block-shared stash: wpb wavefronts per block (default
+// 4) sharing a pool of NL links (default one partial link per event, one per
+// wavefront and two more, at most 32).
+struct SharedShape {
+    int wpb, links, per_cu;
+    size_t lds;
+};
+
+template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
+static hipError_t shared_shape(const LaunchArgs &a, SharedShape &sh)
+{
+    using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
+    constexpr int E = SPLIT ? 4 : 1;
+    const int link_bytes = 64 * LAY::bytes(a.digest != nullptr);
+    const int tl_bytes = BATCH ? 0 : a.tl_bytes;
+    int wpb = a.async_block_waves > 0 ? a.async_block_waves : ASYNC_BLOCK_WAVES;
+    if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
+    auto kern = async_shared_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>;
+    for (;;) {
+        int nl = a.stash_links > 0 ? a.stash_links : E + wpb + 2;
+        nl = std::max(E + 1, std::min(nl, SH_MAX_LINKS));
+        const size_t lds = tabs_lds_offset((size_t)nl * link_bytes + sizeof(SharedCtl) + (size_t)a.lacc_words * 8) +
+                           (size_t)tl_bytes;
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
+        if (e != hipSuccess) return e;
+        if (per_cu >= 1 || wpb == 1) {
+            if (per_cu < 1) return hipErrorInvalidConfiguration;
+            sh = SharedShape{wpb, nl, per_cu, lds};
+            return hipSuccess;
+        }
+        wpb >>= 1;
+    }
+}
+
 template <int GEOM, int EMODE, int MODE, int SPLIT, bool BATCH, int EXT>
 static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, LaunchTimer &tm)
 {
     using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
     const bool dig = a.digest != nullptr;
+    const bool shared = a.async_shared == 1;
     // one partial link per event plus one: a stash with no free link then
     // always holds a ready link to spill.  Split events default to one more,
     // which keeps spills rare.
@@ -593,13 +1030,23 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     const int tl_bytes = BATCH ? 0 : a.tl_bytes;
     int wpb = a.async_block_waves > 0 ? a.async_block_waves : ASYNC_BLOCK_WAVES;
     if (wpb != 1 && wpb != 2 && wpb != 4) return hipErrorInvalidValue;
-    auto kern = async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>;
+    auto kern = shared ? async_shared_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>
+                       : async_kernel<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>;
     // when the block's LDS would not fit: first the smallest default stash
     // (one link per event plus one), then fewer wavefronts per block
     size_t lds = 0;
     int per_cu = 0;
     hipError_t e = hipSuccess;
-    for (;;) {
+    if (shared) {
+        SharedShape sh{};
+        e = shared_shape<GEOM, EMODE, MODE, SPLIT, BATCH, EXT>(a, sh);
+        if (e != hipSuccess) return e;
+        wpb = sh.wpb;
+        L = sh.links;
+        lds = sh.lds;
+        per_cu = sh.per_cu;
+    }
+    for (; !shared;) {
         lds = tabs_lds_offset((size_t)wpb * L * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * wpb, lds);
         if (e != hipSuccess) return e;
@@ -620,7 +1067,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     // sharing them stay ahead, and fused events are register limited, so
     // there the default stands.
     auto capped = [&](int w) { return (a.waves_per_cu > 0 && a.waves_per_cu < w) ? a.waves_per_cu : w; };
-    if (a.async_block_waves == 0 && a.stash_links == 0 && wpb == 4) {
+    if (!shared && a.async_block_waves == 0 && a.stash_links == 0 && wpb == 4) {
         const int L2 = E + 1;
         const size_t lds2 = tabs_lds_offset((size_t)2 * L2 * link_bytes + (size_t)a.lacc_words * 8) + (size_t)tl_bytes;
         int per_cu2 = 0;
