@@ -234,8 +234,10 @@ typedef struct {
                                  stash_links then sizes the block's pool
                                  (0 = one link per event, one per wavefront
                                  and two more; at most 32).  0 = library
-                                 default (one stash per wavefront), 2 = one
-                                 stash per wavefront                         */
+                                 default: shared for split events on runs of
+                                 at least 5e5 histories unless stash_links or
+                                 consolidate is set, else one stash per
+                                 wavefront; 2 = one stash per wavefront      */
     void *workspace;          /* optional caller-owned device memory (on the
                                  handle's device, 256-byte aligned) of ws_bytes
                                  bytes for the run's scheduler state and tally

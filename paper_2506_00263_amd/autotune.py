@@ -1,8 +1,8 @@
 """Autotuner for the remapping schedulers.
 
 Grid search over the tuning knobs of a scheduler (async: wavefronts per
-block, resident wavefronts per CU, stash links and events a drained
-wavefront runs in place; stack: events a popped particle runs before it is
+block, resident wavefronts per CU, stash links, events a drained wavefront
+runs in place, and a stash per wavefront or one per block; stack: events a popped particle runs before it is
 pushed again, at least and in the tail, the make_work threshold and resident
 wavefronts per CU; naive: block size) on a calibration run, timed with HIP
 events inside the library.  Knobs never
@@ -36,6 +36,10 @@ def candidates(sched: str, decomp: str, histories: int = 0) -> list:
                 for links in sorted({events + 1, events + 2, events + 3}):
                     out.append(dict(async_block_waves=wpb, waves_per_cu=wpc, stash_links=links))
         out += [dict(async_drain_events=k) for k in (1, 4, 16, 64)]
+        for shared in (1, 2):
+            for wpb in (4, 2):
+                for links in (0, events + wpb + 1, events + 2 * wpb + 2):
+                    out.append(dict(async_shared_stash=shared, async_block_waves=wpb, stash_links=links))
         return out
     if sched == "stack":
         out += [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 64, 256)]

@@ -100,6 +100,13 @@ constexpr int ASYNC_DRAIN_EVENTS = 8;
 // contention (a queue is held for well under a microsecond), short enough
 // that an exhausted arena is reported promptly.
 constexpr int ASYNC_WAIT_MS = 20;
+// Split events use the block-shared stash by default from this many histories
+// per launch.  Measured on MI355X (private stash of 2 wavefronts per block
+// against a shared one of 4): lattice 1e6 2.39 -> 2.22 ms, 1e7 14.7 -> 12.4,
+// box 1e6 0.77 -> 0.66, continuous-energy pin cell 1e6 120 -> 107, the
+// 256-problem batch 15.5 -> 12.1; slower at 1e5 (1.42 -> 1.65); fused events,
+// register-bound, gain no wavefronts and run a few percent slower.
+constexpr unsigned long long ASYNC_SHARED_MIN_HISTORIES = 500000;
 
 struct LaunchStats {
     unsigned long long launches = 0, rounds = 0;

@@ -840,8 +840,12 @@ async_shared_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
     Wait idle;
     unsigned long long res_next = 0, res_end = 0;   // reserved source ids
     for (;;) {
-        sh_add(&C->busy, 1u);
-        // what to run: a ready link, new histories, an arena link, a closed partial
+        // what to run: a ready link, new histories, an arena link, a closed
+        // partial.  busy counts the wavefronts holding particles, raised once
+        // work is taken: an idle wavefront looking for work must not keep the
+        // others from seeing the block drained (a wavefront holding particles
+        // re-checks the pool before it leaves, so the count only keeps idle
+        // wavefronts waiting while new work may still appear).
         bool have = false, fresh = false, drained = false;
         int ev = 0, cnt = 0;
         Part p;
@@ -912,7 +916,6 @@ async_shared_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
             }
         }
         if (!have) {
-            sh_add(&C->busy, 0xFFFFFFFFu);
             // leave once the pool is empty, no wavefront of the block holds
             // particles and the arena has nothing left; wait a bounded time
             // while it does
@@ -930,6 +933,7 @@ async_shared_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
             continue;
         }
         idle = Wait{};
+        sh_add(&C->busy, 1u);
         int ne = EV_STEP;
         if (!fresh) {
             // run the event on the particles; a drained wavefront's closed
@@ -1019,7 +1023,12 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     using LAY = Layout<EMODE, MODE, SPLIT, EXT>;
     constexpr int E = SPLIT ? 4 : 1;
     const bool dig = a.digest != nullptr;
-    const bool shared = a.async_shared == 1;
+    // the block-shared stash: asked for, or by default for split events on
+    // large runs (see ASYNC_SHARED_MIN_HISTORIES) unless a per-wavefront
+    // stash size or stash donation is asked for
+    const bool shared = a.async_shared == 1 ||
+                        (a.async_shared == 0 && SPLIT && a.stash_links == 0 && a.consolidate != 1 &&
+                         a.total >= ASYNC_SHARED_MIN_HISTORIES);
     // one partial link per event plus one: a stash with no free link then
     // always holds a ready link to spill.  Split events default to one more,
     // which keeps spills rare.
