@@ -521,13 +521,82 @@ typedef struct {
     double *fpos;             /* out: its fission site, 3 per history        */
 } orc_cycle;
 
+/* a generation of a weight-window run: where its histories start and where
+   the copies they split off go */
+typedef struct {
+    int32_t gen;
+    const orc_site *src;      /* NULL in generation 0                          */
+    orc_site *bank;
+    uint64_t cap, n;
+    int full;
+} orc_gen;
+
+/* cell of a point on the uniform weight-window grid */
+static int64_t orc_ww_cell(const orc_problem *p, const double pos[3])
+{
+    int64_t c = 0;
+    for (int a = 2; a >= 0; --a) {
+        int32_t n = p->ww_n[a];
+        double tt = (pos[a] - p->box_lo[a]) * ((double)n / (p->box_hi[a] - p->box_lo[a]));
+        int32_t i = 0;
+        if (tt > 0.0) i = (tt < (double)n) ? (int32_t)tt : n - 1;
+        c = c * n + i;
+    }
+    return c;
+}
+
+/* the weight-window closeout; returns 1 if the history ends (roulette) */
+static int orc_ww_closeout(const orc_problem *p, orc_acc *acc, orc_gen *gn, double xi5, const double pos[3],
+                           const double dir[3], double e, double t, int32_t g, const int32_t cell[3])
+{
+    double lo = p->ww_lo[orc_ww_cell(p, pos)];
+    if (!(lo > 0.0)) return 0;
+    double surv = p->ww_surv * lo;
+    double w = acc->wt;
+    if (w > p->ww_ratio * lo) {
+        double q = w / surv;
+        int32_t n = (q < (double)p->ww_max_split) ? (int32_t)q : p->ww_max_split;
+        if (n < 2) n = 2;
+        double wn = w / (double)n;
+        acc->wt = wn;
+        for (int32_t k = 1; k < n; ++k) {
+            if (!gn || gn->n >= gn->cap) {
+                if (gn) gn->full = 1;
+                continue;
+            }
+            orc_site *st = &gn->bank[gn->n++];
+            for (int a = 0; a < 3; ++a) {
+                st->pos[a] = pos[a];
+                st->dir[a] = dir[a];
+                st->cell[a] = cell[a];
+            }
+            st->e = e;
+            st->w = wn;
+            st->t = t;
+            st->g = g;
+            acc->cnt->splits += 1;
+        }
+        return 0;
+    }
+    if (w < lo) {
+        if ((xi5 * surv) < w) {
+            acc->wt = surv;
+            return 0;
+        }
+        return 1;
+    }
+    return 0;
+}
+
 static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad *gr,
-                        orc_digest *dig, const orc_cycle *cy)
+                        orc_digest *dig, const orc_cycle *cy, orc_gen *gn)
 {
     orc_counts *cnt = acc->cnt;
     uint64_t seed = p->seed;
     uint32_t pid = p->problem_id;
-    uint32_t stream = cy ? cy->stream : 0;
+    uint32_t stream = gn ? (uint32_t)gn->gen : (cy ? cy->stream : 0);
+    const int ww = p->ww_n[0] > 0;
+    const orc_site *from = (gn && gn->src) ? &gn->src[h] : NULL;
     double pos[3], dir[3];
     int32_t cell[3];
     int32_t g = p->src_group;
@@ -567,6 +636,16 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
         dir[0] = p->src_dir[0]; dir[1] = p->src_dir[1]; dir[2] = p->src_dir[2];
     }
     orc_locate(p, pos, dir, cell);
+    if (from) {
+        /* a split copy: the state it was banked with (no source draws used) */
+        for (int a = 0; a < 3; ++a) {
+            pos[a] = from->pos[a];
+            dir[a] = from->dir[a];
+            cell[a] = from->cell[a];
+        }
+        g = from->g;
+        e = from->e;
+    }
     if (cy && cy->bank) {
         const double *row = p->chi + (int64_t)orc_material(p, cell) * p->n_grp;
         g = p->n_grp - 1;
@@ -586,7 +665,8 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                          : (int64_t)p->n_ebins;
     }
     acc->hq = 0;
-    acc->wt = 1.0;
+    acc->wt = from ? from->w : 1.0;
+    if (from) t = from->t;
     acc->G = 0.0;
     acc->L = 0.0;
     acc->nfl = 0;
@@ -715,8 +795,16 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                 }
                 e = enew;
             }
-            /* closeout: weight roulette below the cutoff (slot 5) */
-            if (p->implicit_capture && acc->wt < p->w_cutoff) {
+            /* closeout: weight windows, or without them the weight roulette
+               below the cutoff (slot 5) */
+            if (ww) {
+                double c5 = orc_uniform(seed, pid, h, st32, 5, stream);
+                if (orc_ww_closeout(p, acc, gn, c5, pos, dir, e, t, g, cell)) {
+                    fate = ORC_FATE_ROULETTE;
+                    cnt->roulettes += 1;
+                    break;
+                }
+            } else if (p->implicit_capture && acc->wt < p->w_cutoff) {
                 double c5 = orc_uniform(seed, pid, h, st32, 5, stream);
                 if ((c5 * p->w_survival) < acc->wt) {
                     acc->wt = p->w_survival;
@@ -767,6 +855,15 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                 cnt->reflections += 1;
                 dir[face >> 1] = -dir[face >> 1];
             }
+            /* closeout of the crossing: weight windows (slot 5) */
+            if (ww) {
+                double c5 = orc_uniform(seed, pid, h, st32, 5, stream);
+                if (orc_ww_closeout(p, acc, gn, c5, pos, dir, e, t, g, cell)) {
+                    fate = ORC_FATE_ROULETTE;
+                    cnt->roulettes += 1;
+                    break;
+                }
+            }
         }
         step = step + 1;
     }
@@ -782,6 +879,7 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
 int orc_run(const orc_problem *p, uint64_t h0, uint64_t h1, int64_t *tally,
             orc_digest *digest, orc_counts *counts)
 {
+    if (p->ww_n[0] > 0) return 4;        /* weight windows: generations (orc_run_gen) */
     orc_counts local;
     memset(&local, 0, sizeof local);
     orc_acc acc;
@@ -790,10 +888,31 @@ int orc_run(const orc_problem *p, uint64_t h0, uint64_t h1, int64_t *tally,
     acc.tally = tally;
     acc.cnt = &local;
     for (uint64_t h = h0; h < h1; ++h)
-        orc_history(p, (uint32_t)h, &acc, NULL, digest ? &digest[h - h0] : NULL, NULL);
+        orc_history(p, (uint32_t)h, &acc, NULL, digest ? &digest[h - h0] : NULL, NULL, NULL);
     local.qsum = acc.qsum_total;
     local.overflow = (uint64_t)acc.overflow;
     if (counts) *counts = local;
+    return acc.overflow ? 1 : 0;
+}
+
+int orc_run_gen(const orc_problem *p, int32_t gen, const orc_site *src, uint64_t h0, uint64_t h1, int64_t *tally,
+                orc_digest *digest, orc_counts *counts, orc_site *bank, uint64_t bank_cap, uint64_t *bank_n)
+{
+    orc_counts local;
+    memset(&local, 0, sizeof local);
+    orc_acc acc;
+    memset(&acc, 0, sizeof acc);
+    acc.mode = 0;
+    acc.tally = tally;
+    acc.cnt = &local;
+    orc_gen gn = {gen, gen > 0 ? src : NULL, bank, bank_cap, 0, 0};
+    for (uint64_t h = h0; h < h1; ++h)
+        orc_history(p, (uint32_t)h, &acc, NULL, digest ? &digest[h - h0] : NULL, NULL, &gn);
+    local.qsum = acc.qsum_total;
+    local.overflow = (uint64_t)acc.overflow;
+    if (counts) *counts = local;
+    *bank_n = gn.n;
+    if (gn.full) return 3;
     return acc.overflow ? 1 : 0;
 }
 
@@ -810,7 +929,7 @@ int orc_replay_a(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w
     uint64_t u = 0;
     int bad = 0;
     for (uint64_t h = h0; h < h1; ++h) {
-        orc_history(p, (uint32_t)h, &acc, NULL, NULL, NULL);
+        orc_history(p, (uint32_t)h, &acc, NULL, NULL, NULL, NULL);
         G[h - h0] = acc.G;
         double bound = ceil(fabs(acc.G) * (acc.L + (double)acc.nfl));
         if (!(bound < 0x1p63)) { bad = 1; continue; }
@@ -836,7 +955,7 @@ int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *G
     gr.h0 = h0;
     gr.scale = ldexp(1.0, s);
     gr.SL = SL; gr.SA = SA; gr.SS = SS;
-    for (uint64_t h = h0; h < h1; ++h) orc_history(p, (uint32_t)h, &acc, &gr, NULL, NULL);
+    for (uint64_t h = h0; h < h1; ++h) orc_history(p, (uint32_t)h, &acc, &gr, NULL, NULL, NULL);
     return 0;
 }
 
@@ -867,7 +986,7 @@ int orc_eigen(const orc_problem *p, uint64_t N, int32_t n_cycles, int32_t n_inac
         acc.mode = 0;
         acc.tally = (c >= n_inactive) ? tally : scratch;
         acc.cnt = &local;
-        for (uint64_t h = 0; h < Nc; ++h) orc_history(p, (uint32_t)h, &acc, NULL, NULL, &cy);
+        for (uint64_t h = 0; h < Nc; ++h) orc_history(p, (uint32_t)h, &acc, NULL, NULL, &cy, NULL);
         /* totals over cycles; the overflow rule applies to the sum over all of them */
         uint64_t q_before = total.qsum;
         total.sourced += local.sourced; total.flights += local.flights;
@@ -875,7 +994,7 @@ int orc_eigen(const orc_problem *p, uint64_t N, int32_t n_cycles, int32_t n_inac
         total.absorbs += local.absorbs; total.crossings += local.crossings; total.leaks += local.leaks;
         total.reflections += local.reflections; total.cutoffs += local.cutoffs; total.killed += local.killed;
         total.pieces += local.pieces; total.fissions += local.fissions; total.sites += local.sites;
-        total.roulettes += local.roulettes; total.cdf_scans += local.cdf_scans;
+        total.roulettes += local.roulettes; total.cdf_scans += local.cdf_scans; total.splits += local.splits;
         total.qsum = q_before + acc.qsum_total;
         if (acc.overflow || total.qsum < q_before || total.qsum >= 0x8000000000000000ull) total.overflow = 1;
         /* the bank: each history's neutrons in history order */

@@ -82,7 +82,35 @@ typedef struct {
        ROULETTE).  Every tally piece scores length times weight. */
     int32_t implicit_capture;
     double w_cutoff, w_survival;
+    /* spatial weight windows, applied by the closeout that ends every
+       collision leaving the particle alive and every surface crossing that
+       does not leak (weights and weight windows for the next flight).
+       ww_n[0] > 0: a uniform grid of ww_n[0] x ww_n[1] x ww_n[2] cells over
+       the box; the cell of a point has ix = the integer part of
+       (x - box_lo) * (ww_n / (box_hi - box_lo)), clamped to the grid, and
+       index c = (iz * ww_n[1] + iy) * ww_n[0] + ix.  ww_lo[c] is the lower
+       bound of the window of cell c (0: no window there), ww_ratio * ww_lo
+       the upper bound, ww_surv * ww_lo the survival weight.  A weight above
+       the upper bound is split into n = floor(w / survival), clamped to
+       [2, ww_max_split], copies of weight w / n: the particle continues as
+       the first and the others are banked, in order, as histories of the
+       next generation; a weight below the lower bound plays roulette (slot 5):
+       it survives with probability w / survival at the survival weight, else
+       the history ends (ROULETTE).  With windows, implicit capture's global
+       cutoff roulette is off.  Needs a finite box, ww_ratio > ww_surv > 1 and
+       ww_max_split >= 2 (checked by the Python marshalling); forward runs
+       only (orc_run_gen). */
+    int32_t ww_n[3];
+    const double *ww_lo;
+    double ww_ratio, ww_surv;
+    int32_t ww_max_split;
 } orc_problem;
+
+/* a banked split copy: a history of the next generation starts from it */
+typedef struct {
+    double pos[3], dir[3], e, w, t;
+    int32_t g, cell[3];
+} orc_site;
 
 /* what a history ended with */
 enum { ORC_FATE_LEAK = 0, ORC_FATE_ABSORB = 1, ORC_FATE_CUTOFF = 2, ORC_FATE_KILLED = 3, ORC_FATE_ROULETTE = 4 };
@@ -103,6 +131,7 @@ typedef struct {              /* totals over a run (scheduler invariant)   */
     uint64_t roulettes;       /* histories ended by weight roulette          */
     uint64_t cdf_scans;       /* multigroup scatters: transfer-CDF entries read
                                  to find the outgoing group (k + 1 for group k) */
+    uint64_t splits;          /* weight windows: copies banked for the next generation */
 } orc_counts;
 
 /* primitives, exposed for tests */
@@ -127,9 +156,19 @@ void orc_tally_segment(const orc_problem *p, const double pos[3], const double d
                        int32_t g, double *out);
 double orc_ce_xs_hook(const orc_problem *p, int32_t m, double e, double *sa, double *ss);
 
-/* forward: histories [h0, h1) added into tally; digest (optional) indexed h-h0 */
+/* forward: histories [h0, h1) added into tally; digest (optional) indexed h-h0;
+   returns 0, 1 (overflow) or 4 (a problem with weight windows: see orc_run_gen) */
 int orc_run(const orc_problem *p, uint64_t h0, uint64_t h1, int64_t *tally,
             orc_digest *digest, orc_counts *counts);
+
+/* one generation of a run with weight windows: histories [h0, h1) of
+   generation gen (0: the problem's source; gen > 0: history h starts from
+   src[h] and draws from random-number stream gen), tallies added into
+   tally; the copies split off are appended to bank (capacity bank_cap) in
+   history order, *bank_n counting them.  Returns 0, 1 (overflow) or 3
+   (bank full). */
+int orc_run_gen(const orc_problem *p, int32_t gen, const orc_site *src, uint64_t h0, uint64_t h1, int64_t *tally,
+                orc_digest *digest, orc_counts *counts, orc_site *bank, uint64_t bank_cap, uint64_t *bank_n);
 
 /* score-function backward, pass A: G_h = sum over tally pieces of w[bin]*len,
    with L_h (track length) and n_h (flights); U += ceil(|G_h| * (L_h + n_h)) */

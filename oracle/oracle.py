@@ -50,7 +50,14 @@ class OrcProblem(C.Structure):
         ("max_steps", C.c_int64), ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p),
         ("speed_coef", C.c_double), ("sigma_f", C.c_void_p), ("nu", C.c_void_p), ("chi", C.c_void_p),
         ("implicit_capture", C.c_int32), ("w_cutoff", C.c_double), ("w_survival", C.c_double),
+        ("ww_n", C.c_int32 * 3), ("ww_lo", C.c_void_p), ("ww_ratio", C.c_double), ("ww_surv", C.c_double),
+        ("ww_max_split", C.c_int32),
     ]
+
+
+class OrcSite(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("dir", C.c_double * 3), ("e", C.c_double), ("w", C.c_double),
+                ("t", C.c_double), ("g", C.c_int32), ("cell", C.c_int32 * 3)]
 
 
 class OrcDigest(C.Structure):
@@ -62,7 +69,7 @@ DIGEST_DTYPE = np.dtype([("qsum", "<i8"), ("flights", "<u4"), ("collisions", "<u
                          ("fate", "<u4"), ("pad", "<u4")])
 COUNT_NAMES = ["sourced", "flights", "collisions", "scatters", "absorbs", "crossings", "leaks",
                "reflections", "cutoffs", "killed", "pieces", "qsum", "overflow", "fissions", "sites", "roulettes",
-               "cdf_scans"]
+               "cdf_scans", "splits"]
 
 
 class OrcCounts(C.Structure):
@@ -98,6 +105,8 @@ def lib():
             L.orc_ce_index_fast.argtypes = [C.c_void_p, C.c_int32, C.c_double]
             L.orc_ce_index_fast.restype = C.c_int32
             L.orc_edge_index.argtypes = [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_int32]
+            L.orc_run_gen.argtypes = [P(OrcProblem), C.c_int32, C.c_void_p, C.c_uint64, C.c_uint64, C.c_void_p,
+                                      C.c_void_p, P(OrcCounts), C.c_void_p, C.c_uint64, P(C.c_uint64)]
             L.orc_edge_index.restype = C.c_int32
             L.orc_elastic.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, P(C.c_double)]
             L.orc_elastic.restype = C.c_double
@@ -118,6 +127,17 @@ def lib():
 
 def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def _check_windows(d: dict) -> None:
+    """Weight windows need a finite box (their grid spans it)."""
+    if int(d.get("ww_n", [0])[0]) > 0:
+        if not (np.all(np.isfinite(d["box_lo"])) and np.all(np.isfinite(d["box_hi"]))):
+            raise ValueError("weight windows need a finite box")
+        if min(int(v) for v in d["ww_n"]) < 1 or len(d["ww_lo"]) != int(np.prod(d["ww_n"])):
+            raise ValueError("weight windows: ww_n >= 1 per axis and one lower bound per cell")
+        if not (float(d["ww_ratio"]) > float(d["ww_surv"]) > 1.0 and int(d["ww_max_split"]) >= 2):
+            raise ValueError("weight windows: need ww_ratio > ww_surv > 1 and ww_max_split >= 2")
 
 
 def _check_tally_covers(d: dict) -> None:
@@ -144,6 +164,7 @@ class Problem:
         self.d = d
         keep = {}
         _check_tally_covers(d)
+        _check_windows(d)
 
         def arr(name, dtype):
             a = np.ascontiguousarray(np.asarray(d[name], dtype=dtype))
@@ -205,6 +226,12 @@ class Problem:
         s.implicit_capture = int(d.get("implicit_capture", 0))
         s.w_cutoff = float(d.get("w_cutoff", 0.0))
         s.w_survival = float(d.get("w_survival", 0.0))
+        if int(d.get("ww_n", [0])[0]) > 0:
+            s.ww_n[:] = [int(v) for v in d["ww_n"]]
+            s.ww_lo = arr("ww_lo", np.float64)
+            s.ww_ratio = float(d["ww_ratio"])
+            s.ww_surv = float(d["ww_surv"])
+            s.ww_max_split = int(d["ww_max_split"])
         if d.get("sigma_f") is not None:
             s.sigma_f = arr("sigma_f", np.float64)
             s.nu = arr("nu", np.float64)
@@ -236,7 +263,9 @@ def default_threads() -> int:
 def run(d: dict, h0: int = 0, h1: int | None = None, *, digest: bool = False, threads: int | None = None):
     """Forward run of histories [h0, h1).  Returns a dict with the int64
     tally, counters (summed over threads) and, optionally, per-history
-    digests."""
+    digests.  Problems with weight windows run in generations (run_ww)."""
+    if int(d.get("ww_n", [0])[0]) > 0:
+        return run_ww(d, h0, h1, digest=digest, threads=threads)
     P = Problem(d)
     L = lib()
     if h1 is None:
@@ -262,6 +291,84 @@ def run(d: dict, h0: int = 0, h1: int | None = None, *, digest: bool = False, th
     # the overflow rule is on the total of all contributions, not per part
     tot["overflow"] = int(tot["qsum"] >= 2 ** 63 or any(c.overflow for c in counts))
     out = dict(tally=tally, counts=tot)
+    if digest:
+        out["digest"] = dig
+    return out
+
+
+MAX_GENERATIONS = 64
+
+
+def run_ww(d: dict, h0: int = 0, h1: int | None = None, *, digest: bool = False, threads: int | None = None,
+           max_generations: int = MAX_GENERATIONS):
+    """Forward run with weight windows: generation 0 runs histories [h0, h1)
+    from the problem's source; the copies they split off, in history order,
+    are the histories of generation 1 (random-number stream 1), and so on
+    until a generation splits nothing.  Histories of a generation run in
+    threads over contiguous ranges whose banks are joined in range order, so
+    every generation's order is the sequential one.  Returns the summed
+    tally and counters, the history count of every generation and,
+    optionally, generation 0's digests."""
+    P = Problem(d)
+    L = lib()
+    if h1 is None:
+        h1 = d["n_histories"]
+    threads = default_threads() if threads is None else threads
+    tally = np.zeros(P.n_bins, dtype=np.int64)
+    tot = {n: 0 for n in COUNT_NAMES}
+    gens = []
+    dig = np.zeros(h1 - h0, dtype=DIGEST_DTYPE) if digest else None
+    src = None
+    lo, hi = h0, h1
+    any_overflow = False
+    for gen in range(max_generations):
+        gens.append(hi - lo)
+        parts = _ranges(lo, hi, threads)
+        tallies = [np.zeros(P.n_bins, dtype=np.int64) for _ in parts]
+        counts = [OrcCounts() for _ in parts]
+        caps = [max(1024, 4 * (b - a) + 64) for a, b in parts]
+        banks = [(OrcSite * c)() for c in caps]
+        ns = [C.c_uint64(0) for _ in parts]
+        rcs = [0] * len(parts)
+
+        def work(k):
+            a, b = parts[k]
+            dptr = _ptr(dig[a - h0:]) if (digest and gen == 0) else None
+            sp = C.cast(src, C.c_void_p) if src is not None else None
+            for _ in range(40):
+                rcs[k] = L.orc_run_gen(C.byref(P.s), gen, sp, a, b, _ptr(tallies[k]), dptr, C.byref(counts[k]),
+                                       C.cast(banks[k], C.c_void_p), caps[k], C.byref(ns[k]))
+                if rcs[k] != 3:
+                    return
+                # the range split off more copies than its bank holds: run it
+                # again from scratch with a larger bank (it is deterministic)
+                tallies[k][:] = 0
+                caps[k] *= 4
+                banks[k] = (OrcSite * caps[k])()
+
+        _parallel(work, len(parts))
+        if any(r == 3 for r in rcs):
+            raise RuntimeError("oracle: split bank full")
+        any_overflow = any_overflow or any(r == 1 for r in rcs)
+        for t in tallies:
+            tally += t
+        for c in counts:
+            for n in COUNT_NAMES:
+                tot[n] += int(getattr(c, n))
+        m = sum(n.value for n in ns)
+        if m == 0:
+            break
+        nxt = (OrcSite * m)()
+        o = 0
+        for k in range(len(parts)):
+            n = ns[k].value
+            C.memmove(C.addressof(nxt) + o * C.sizeof(OrcSite), banks[k], n * C.sizeof(OrcSite))
+            o += n
+        src, lo, hi = nxt, 0, m
+    else:
+        raise RuntimeError("oracle: more than %d generations of split copies" % max_generations)
+    tot["overflow"] = int(tot["qsum"] >= 2 ** 63 or any_overflow)
+    out = dict(tally=tally, counts=tot, generations=gens)
     if digest:
         out["digest"] = dig
     return out
@@ -340,6 +447,8 @@ def backward(d: dict, w: np.ndarray, threads: int | None = None):
     T = raw * 2^-S / N: returns (grad Sigma_t, grad Sigma_s), each [M*G]."""
     if d.get("implicit_capture", 0):
         raise ValueError("the score-function backward needs analog histories (no implicit capture)")
+    if int(d.get("ww_n", [0])[0]) > 0:
+        raise ValueError("the score-function backward takes no weight windows")
     G, U = replay_a(d, w, threads=threads)
     s = grad_scale(U)
     SL, SA, SS = replay_b(d, G, s, threads=threads)
@@ -357,6 +466,8 @@ def eigen(d: dict, n_particles: int, n_cycles: int, n_inactive: int, bank_cap: i
         raise ValueError("k-eigenvalue runs need fission data")
     if d.get("implicit_capture", 0):
         raise ValueError("k-eigenvalue runs are analog (no implicit capture)")
+    if int(d.get("ww_n", [0])[0]) > 0:
+        raise ValueError("k-eigenvalue runs take no weight windows")
     L = lib()
     tally = np.zeros(P.n_bins, dtype=np.int64)
     k = np.zeros(n_cycles, dtype=np.float64)

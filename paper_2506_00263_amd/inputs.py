@@ -342,6 +342,25 @@ def with_implicit_capture(d: dict, w_cutoff: float = 0.25, w_survival: float = 0
     return d
 
 
+def with_weight_windows(d: dict, n=(4, 4, 4), lo=None, lo_range=(0.05, 0.5), ratio: float = 4.0,
+                        surv: float = 2.0, max_split: int = 8, data_seed: int = DATA_SEED_BASE + 7) -> dict:
+    """A copy of problem d with spatial weight windows: a uniform grid of n
+    cells over the box, lower bounds lo (one per cell, [iz][iy][ix]) or drawn
+    log-uniform in lo_range; upper bound ratio * lo, survival weight surv * lo,
+    at most max_split copies per split.  Data only."""
+    d = dict(d)
+    n = tuple(int(v) for v in n)
+    if lo is None:
+        rng = _rng(data_seed)
+        lo = np.exp(rng.uniform(np.log(lo_range[0]), np.log(lo_range[1]), size=int(np.prod(n))))
+    d["ww_n"] = _i32(n)
+    d["ww_lo"] = _f64(np.asarray(lo, np.float64).ravel())
+    d["ww_ratio"] = float(ratio)
+    d["ww_surv"] = float(surv)
+    d["ww_max_split"] = int(max_split)
+    return d
+
+
 def with_fission(d: dict, fissile=None, sigma_f=None, nu=None, chi=None,
                  data_seed: int = DATA_SEED_BASE + 6) -> dict:
     """A copy of multigroup problem d with fission data for k-eigenvalue runs.
