@@ -174,6 +174,29 @@ typedef struct {
      * backward and k-eigenvalue runs take analog problems). */
     int32_t implicit_capture;
     double w_cutoff, w_survival;
+    /* Spatial weight windows, applied by the closeout that ends every
+     * collision leaving the particle alive and every surface crossing that
+     * does not leak (the paper's closeout event, Sec. 4, "handles weights and
+     * weight windows").  ww_n[0] > 0: a uniform grid of ww_n[0] x ww_n[1] x
+     * ww_n[2] cells over the (finite) box; the cell of a point has ix = the
+     * integer part of (x - box_lo) * (ww_n / (box_hi - box_lo)), clamped to
+     * the grid, index (iz * ww_n[1] + iy) * ww_n[0] + ix.  ww_lo[cell] is the
+     * window's lower bound (0: no window there), ww_ratio * ww_lo its upper
+     * bound and ww_surv * ww_lo the survival weight (need ww_ratio > ww_surv
+     * > 1).  A weight above the window splits into n = floor(w / survival)
+     * copies, clamped to [2, ww_max_split], of weight w / n: the particle
+     * continues as the first, the others become histories of the next
+     * generation, ordered by (parent history, copy), drawing from
+     * random-number stream = generation; the run goes on until a generation
+     * splits nothing (at most 64).  A weight below the window plays roulette
+     * (slot 5): survival weight with probability w / survival, else the
+     * history ends (ROULETTE).  With windows, implicit capture's global
+     * cutoff roulette is off.  Single-problem forward runs (not batches,
+     * mcx_backward, mcx_run_eigen or mcx_run_noalloc). */
+    int32_t ww_n[3];
+    const double *ww_lo;
+    double ww_ratio, ww_surv;
+    int32_t ww_max_split;
 } mcx_problem_desc;
 
 /* Options of one run.  Zero-initialise and set what you need; zero means the
@@ -291,6 +314,8 @@ typedef struct {
     uint64_t roulettes;       /* histories ended by weight roulette             */
     uint64_t cdf_scans;       /* multigroup scatters: transfer-CDF entries read
                                  to find the outgoing group (k + 1 for group k) */
+    uint64_t splits;          /* weight windows: copies split off (all generations) */
+    uint64_t generations;     /* weight windows: generations run (1 without)    */
 } mcx_counters_t;
 
 /* k-eigenvalue power iteration (the multigroup workload of Sec. 4 of the

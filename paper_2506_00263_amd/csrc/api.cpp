@@ -40,6 +40,8 @@ struct HostProblem {
     std::vector<double> xpl, ypl, cxs, cys, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, mx, my, mz, eedges;
     std::vector<double> speed;            // group speeds (time bins, multigroup)
     std::vector<double> sigf, nu, chi;    // fission (k-eigenvalue runs)
+    std::vector<double> wwlo;             // weight-window lower bounds (or {0})
+    bool ww = false;
     bool fission = false;
     std::vector<int32_t> cmat, hash_lo, hash_hi;
     double hash_ln_lo = 0.0, hash_inv = 0.0;
@@ -95,6 +97,16 @@ struct mcx_problem_s {
     uint64_t *d_tsum = nullptr;
     size_t tsum_cap = 0;
     unsigned long long *d_scratch = nullptr;
+    // weight-window generations (grown on demand): staged copies, the next
+    // generation's ordered sources, per history copy counts and offsets, the
+    // staging fill counter
+    SiteRec *d_gstage = nullptr, *d_gsrc = nullptr;
+    size_t g_cap = 0;
+    uint32_t *d_gn = nullptr;
+    size_t gn_cap = 0;
+    uint64_t *d_goff = nullptr;
+    size_t goff_cap = 0;
+    unsigned long long *d_gcount = nullptr;
     uint64_t *d_tot = nullptr;
     uint64_t *h_tot = nullptr;            // pinned
     // state
@@ -375,6 +387,22 @@ static mcx_status import_problem(mcx_problem_t h, const mcx_problem_desc &d, int
     if (d.implicit_capture &&
         !(d.w_cutoff >= 0.0 && d.w_survival > 0.0 && d.w_cutoff <= d.w_survival && std::isfinite(d.w_survival)))
         return fail(h, MCX_E_INVALID_ARG, "problem %d: need 0 <= w_cutoff <= w_survival, w_survival > 0", k);
+    hp.wwlo = {0.0};
+    if (d.ww_n[0] > 0) {
+        for (int a = 0; a < 3; ++a)
+            if (d.ww_n[a] < 1 || d.ww_n[a] > 4096 || !std::isfinite(d.box_lo[a]) || !std::isfinite(d.box_hi[a]))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: weight windows need 1..4096 cells per axis and a finite box", k);
+        if (!d.ww_lo) return fail(h, MCX_E_INVALID_ARG, "problem %d: weight windows need ww_lo", k);
+        if (!(d.ww_ratio > d.ww_surv && d.ww_surv > 1.0 && std::isfinite(d.ww_ratio)) || d.ww_max_split < 2)
+            return fail(h, MCX_E_INVALID_ARG, "problem %d: weight windows need ww_ratio > ww_surv > 1, ww_max_split >= 2", k);
+        const int64_t nw = (int64_t)d.ww_n[0] * d.ww_n[1] * d.ww_n[2];
+        if (nw > (1 << 24)) return fail(h, MCX_E_INVALID_ARG, "problem %d: at most 2^24 weight-window cells", k);
+        hp.wwlo = copy_of(d.ww_lo, nw);
+        for (double v : hp.wwlo)
+            if (!(v >= 0.0 && std::isfinite(v)))
+                return fail(h, MCX_E_INVALID_ARG, "problem %d: weight-window bounds must be finite and >= 0", k);
+        hp.ww = true;
+    }
     hp.nbase = hp.n_bins;
     hp.speed = {1.0};
     if (d.n_tbins < 0 || d.n_tbins > (1 << 20))
@@ -420,7 +448,7 @@ static mcx_status upload(mcx_problem_t h)
     BlobBuilder bb;
     struct Offs {
         size_t xpl, ypl, cxs, cys, cmat, sig_t, sig_s, cdf, egrid, siga, sigs, awr, dens, hlo, hhi, mx, my, mz, ee;
-        size_t speed, sigf, nu, chi;
+        size_t speed, sigf, nu, chi, wwlo;
     };
     std::vector<Offs> off(h->n);
     std::vector<size_t> tl_base(h->n), tl_bytes(h->n);
@@ -458,6 +486,7 @@ static mcx_status upload(mcx_problem_t h)
         o.egrid = bb.add(p.egrid); o.siga = bb.add(p.siga); o.sigs = bb.add(p.sigs); o.awr = bb.add(p.awr);
         o.dens = bb.add(p.dens); o.hlo = bb.add(p.hash_lo); o.hhi = bb.add(p.hash_hi);
         o.ee = bb.add(p.eedges);
+        o.wwlo = bb.add(p.wwlo);
     }
     HIP_TRY(h, hipMalloc(&h->blob, std::max<size_t>(bb.bytes.size(), 256)));
     HIP_TRY(h, hipMemcpy(h->blob, bb.bytes.data(), bb.bytes.size(), hipMemcpyHostToDevice));
@@ -592,6 +621,14 @@ static mcx_status upload(mcx_problem_t h)
         P.implicit = d.implicit_capture ? 1 : 0;
         P.w_cut = d.implicit_capture ? d.w_cutoff : 0.0;
         P.w_surv = d.implicit_capture ? d.w_survival : 1.0;
+        P.ww_lo = (const double *)(base + o.wwlo);
+        for (int a = 0; a < 3; ++a) {
+            P.ww_n[a] = hp.ww ? d.ww_n[a] : 0;
+            P.ww_inv[a] = hp.ww ? (double)d.ww_n[a] / (d.box_hi[a] - d.box_lo[a]) : 0.0;
+        }
+        P.ww_ratio = hp.ww ? d.ww_ratio : 0.0;
+        P.ww_surv = hp.ww ? d.ww_surv : 0.0;
+        P.ww_max_split = hp.ww ? d.ww_max_split : 0;
     }
     return MCX_OK;
 }
@@ -631,6 +668,8 @@ extern "C" mcx_status mcx_create_problem(const mcx_problem_desc *descs, int32_t 
         for (int k = 1; k < n_problems; ++k)
             if (descs[k].geometry != h->geom || descs[k].energy_mode != h->emode || descs[k].tally_kind != h->tally_kind)
                 s = fail(h, MCX_E_INVALID_ARG, "problems of one handle must share geometry, energy mode and tally kind");
+        for (int k = 0; k < n_problems && s == MCX_OK && n_problems > 1; ++k)
+            if (h->hp[k].ww) s = fail(h, MCX_E_INVALID_ARG, "weight windows run as single problems, not in batches");
     }
     if (s == MCX_OK) {
         hipError_t e = hipGetDevice(&h->device);
@@ -680,6 +719,11 @@ extern "C" void mcx_destroy_problem(mcx_problem_t h)
     if (h->d_sites) hipFree(h->d_sites);
     if (h->d_tsum) hipFree(h->d_tsum);
     if (h->d_scratch) hipFree(h->d_scratch);
+    if (h->d_gstage) hipFree(h->d_gstage);
+    if (h->d_gsrc) hipFree(h->d_gsrc);
+    if (h->d_gn) hipFree(h->d_gn);
+    if (h->d_goff) hipFree(h->d_goff);
+    if (h->d_gcount) hipFree(h->d_gcount);
     if (h->d_tot) hipFree(h->d_tot);
     if (h->h_tot) hipHostFree(h->h_tot);
     delete h;
@@ -810,7 +854,7 @@ static LaunchArgs launch_args(mcx_problem_t h, const mcx_run_opts &o, int mode, 
     a.split = o.decomp == MCX_DECOMP_SPLIT ? 1 : 0;
     a.ext = 0;
     for (int k = 0; k < h->n; ++k)
-        if (h->pd[k].n_tbins > 0 || h->pd[k].implicit) a.ext = 1;
+        if (h->pd[k].n_tbins > 0 || h->pd[k].implicit || h->pd[k].ww_n[0] > 0) a.ext = 1;
     a.lacc_words = 0;
     if (h->n == 1 && mode == MODE_REPLAY_B) a.lacc_words = 3 * h->pd[0].n_mat * h->pd[0].n_grp;
     if (path == MCX_TALLY_PATH_LDS) a.lacc_words = (int)h->hp[0].n_bins;
@@ -979,6 +1023,8 @@ static mcx_status run_pass(mcx_problem_t h, const mcx_run_opts &o, int mode, con
     c.fissions = tot[C_FISSIONS];
     c.roulettes = tot[C_ROULETTES];
     c.cdf_scans = tot[C_CDF];
+    c.splits = tot[C_SPLITS];
+    c.generations = 1;
     c.rounds = st.rounds;
     c.launches = st.launches;
     c.kernel_ms = tm.total_ms();
@@ -1018,6 +1064,147 @@ static mcx_status run_range(mcx_problem_t h, const mcx_run_opts &o, std::vector<
     return MCX_OK;
 }
 
+// grow a device buffer to at least `count` elements (contents not kept)
+template <class T>
+static hipError_t grow(T *&ptr, size_t &cap, size_t count)
+{
+    if (cap >= count && ptr) return hipSuccess;
+    if (ptr) {
+        hipError_t e = hipFree(ptr);
+        ptr = nullptr;
+        cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    hipError_t e = hipMalloc((void **)&ptr, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) cap = count;
+    return e;
+}
+
+// device total -> host (on the run's stream)
+static mcx_status read_total(mcx_problem_t h, hipStream_t stream, uint64_t &out)
+{
+    HIP_TRY(h, hipMemcpyAsync(h->h_tot, h->d_tot, 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(h, hipStreamSynchronize(stream));
+    out = *h->h_tot;
+    return MCX_OK;
+}
+
+// add one pass's counters into a run's totals
+static void add_counters(mcx_counters_t &sum, const mcx_counters_t &pc)
+{
+    sum.sourced += pc.sourced; sum.flights += pc.flights; sum.collisions += pc.collisions;
+    sum.scatters += pc.scatters; sum.absorbs += pc.absorbs; sum.crossings += pc.crossings;
+    sum.leaks += pc.leaks; sum.reflections += pc.reflections; sum.cutoffs += pc.cutoffs;
+    sum.killed += pc.killed; sum.pieces += pc.pieces; sum.events += pc.events;
+    sum.lane_slots += pc.lane_slots; sum.dispatches += pc.dispatches; sum.spills += pc.spills;
+    sum.refills += pc.refills; sum.make_work += pc.make_work; sum.rounds += pc.rounds;
+    sum.launches += pc.launches; sum.kernel_ms += pc.kernel_ms; sum.fissions += pc.fissions;
+    sum.roulettes += pc.roulettes; sum.cdf_scans += pc.cdf_scans; sum.splits += pc.splits;
+    sum.grid_blocks = pc.grid_blocks; sum.block_threads = pc.block_threads; sum.lds_bytes = pc.lds_bytes;
+}
+
+constexpr int WW_MAX_GENERATIONS = 64;
+
+// A forward run with weight windows, in generations: generation 0 runs
+// histories [first, first + count) from the problem's source; the copies a
+// generation splits off, in (parent, ordinal) order, are the histories of
+// the next one, on random-number stream = generation; until a generation
+// splits nothing.  Tallies add up over generations, counters too; digests
+// cover generation 0.
+static mcx_status forward_generations(mcx_problem_t h, const mcx_run_opts &o, Workspace *fixed, uint64_t first0,
+                                      uint64_t count0)
+{
+    hipStream_t stream = (hipStream_t)o.hip_stream;
+    ProbDev &P = h->pd[0];
+    const size_t cap = std::max<size_t>(2 * (size_t)count0, 65536);
+    if (h->g_cap < cap) {
+        size_t c0 = 0;
+        HIP_TRY(h, grow(h->d_gstage, c0, cap));
+        c0 = 0;
+        HIP_TRY(h, grow(h->d_gsrc, c0, cap));
+        h->g_cap = cap;
+    }
+    const size_t maxn = std::max<size_t>((size_t)count0, cap);
+    HIP_TRY(h, grow(h->d_gn, h->gn_cap, maxn));
+    HIP_TRY(h, grow(h->d_goff, h->goff_cap, maxn));
+    HIP_TRY(h, grow(h->d_tsum, h->tsum_cap, (size_t)eigen_tiles(maxn) + 1));
+    if (!h->d_gcount) HIP_TRY(h, hipMalloc(&h->d_gcount, 64));
+    if (!h->d_tot) HIP_TRY(h, hipMalloc(&h->d_tot, 64));
+    if (!h->h_tot) HIP_TRY(h, hipHostMalloc((void **)&h->h_tot, 64, hipHostMallocDefault));
+    auto restore = [&]() {
+        P.gsrc = nullptr;
+        P.gout = nullptr;
+        P.gcount = nullptr;
+        P.gcap = 0;
+        P.gn = nullptr;
+        P.stream = 0;
+    };
+    mcx_counters_t sum{};
+    unsigned __int128 qsum = 0;
+    uint64_t first = first0, n = count0;
+    int gen = 0;
+    for (;; ++gen) {
+        if (gen >= WW_MAX_GENERATIONS) {
+            restore();
+            return fail(h, MCX_E_CAPACITY, "weight windows: copies still split off after %d generations",
+                        WW_MAX_GENERATIONS);
+        }
+        HIP_TRY(h, hipMemsetAsync(h->d_gcount, 0, 8, stream));
+        P.gsrc = gen > 0 ? h->d_gsrc : nullptr;
+        P.gout = h->d_gstage;
+        P.gcount = h->d_gcount;
+        P.gcap = cap;
+        P.gn = h->d_gn;
+        P.stream = (uint32_t)gen;
+        std::vector<uint64_t> f{first}, c{n};
+        unsigned int err = 0;
+        mcx_status s = run_pass(h, o, MODE_FWD, f, c, gen == 0 ? o.digest : nullptr, &err, fixed);
+        if (s != MCX_OK) {
+            restore();
+            return s;
+        }
+        add_counters(sum, h->counters);
+        qsum += h->counters.qsum;
+        uint64_t m = 0;
+        HIP_TRY(h, hipMemcpyAsync(h->h_tot, h->d_gcount, 8, hipMemcpyDeviceToHost, stream));
+        HIP_TRY(h, hipStreamSynchronize(stream));
+        m = *h->h_tot;
+        if (m > cap) {
+            restore();
+            return fail(h, MCX_E_CAPACITY, "weight windows: generation %d split off %llu copies (room for %zu)", gen,
+                        (unsigned long long)m, cap);
+        }
+        if (m == 0) break;
+        // the next generation: the copies in (parent, ordinal) order
+        hipError_t e = ww_order_copies(h->d_gn, n, (uint32_t)first, h->d_gstage, m, h->d_tsum, h->d_tot, h->d_goff,
+                                       h->d_gsrc, stream);
+        if (e != hipSuccess) {
+            restore();
+            return hip_fail(h, e, "weight-window copies");
+        }
+        uint64_t chk = 0;
+        s = read_total(h, stream, chk);
+        if (s != MCX_OK) {
+            restore();
+            return s;
+        }
+        if (chk != m) {
+            restore();
+            return fail(h, MCX_E_DEVICE, "internal: generation %d staged %llu copies, counted %llu", gen,
+                        (unsigned long long)m, (unsigned long long)chk);
+        }
+        first = 0;
+        n = m;
+    }
+    restore();
+    sum.qsum = (uint64_t)qsum;
+    sum.overflow = qsum >= ((unsigned __int128)1 << 63) ? 1 : 0;
+    sum.generations = (uint64_t)gen + 1;
+    h->counters = sum;
+    if (sum.overflow) return fail(h, MCX_E_OVERFLOW, "fixed-point tally total reached 2^63");
+    return MCX_OK;
+}
+
 // A forward run into the handle's tallies; `fixed`: device scratch the run
 // must fit in (never reallocated), or null for the handle's own.
 static mcx_status forward(mcx_problem_t h, const mcx_run_opts &o, Workspace *fixed)
@@ -1042,6 +1229,15 @@ static mcx_status forward(mcx_problem_t h, const mcx_run_opts &o, Workspace *fix
     if (!o.accumulate)
         HIP_TRY(h, hipMemsetAsync(h->d_tally, 0, std::max<size_t>(h->total_bins, 1) * 8, (hipStream_t)o.hip_stream));
     unsigned int err = 0;
+    if (h->n == 1 && h->hp[0].ww) {
+        s = forward_generations(h, o, fixed, first[0], count[0]);
+        if (s != MCX_OK) return s;
+        h->tallies_valid = true;
+        h->have_forward = true;
+        h->last_first = first;
+        h->last_count = count;
+        return MCX_OK;
+    }
     s = run_pass(h, o, MODE_FWD, first, count, o.digest, &err, fixed);
     if (s != MCX_OK) return s;
     if (err & ERR_OVERFLOW) return fail(h, MCX_E_OVERFLOW, "fixed-point tally total reached 2^63");
@@ -1080,37 +1276,13 @@ extern "C" mcx_status mcx_run_noalloc(mcx_problem_t h, const mcx_run_opts *opts)
     if (s != MCX_OK) return s;
     if (o.workspace) return fail(h, MCX_E_INVALID_ARG, "mcx_run_noalloc runs in the library's fixed scratch: workspace must be NULL");
     if (o.time_kernels) return fail(h, MCX_E_INVALID_ARG, "mcx_run_noalloc does not time launches (time_kernels must be 0)");
+    if (h->hp[0].ww) return fail(h, MCX_E_INVALID_ARG, "mcx_run_noalloc takes no weight windows (their generations need device memory)");
     if (!h->scratch) return fail(h, MCX_E_DEVICE, "no device scratch on this device");
     Workspace w;
     w.ptr = h->scratch;
     w.bytes = MCX_NOALLOC_SCRATCH_BYTES;
     w.fixed = true;
     return forward(h, o, &w);
-}
-
-// grow a device buffer to at least `count` elements (contents not kept)
-template <class T>
-static hipError_t grow(T *&ptr, size_t &cap, size_t count)
-{
-    if (cap >= count && ptr) return hipSuccess;
-    if (ptr) {
-        hipError_t e = hipFree(ptr);
-        ptr = nullptr;
-        cap = 0;
-        if (e != hipSuccess) return e;
-    }
-    hipError_t e = hipMalloc((void **)&ptr, std::max<size_t>(count, 1) * sizeof(T));
-    if (e == hipSuccess) cap = count;
-    return e;
-}
-
-// device total -> host (on the run's stream)
-static mcx_status read_total(mcx_problem_t h, hipStream_t stream, uint64_t &out)
-{
-    HIP_TRY(h, hipMemcpyAsync(h->h_tot, h->d_tot, 8, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(h, hipStreamSynchronize(stream));
-    out = *h->h_tot;
-    return MCX_OK;
 }
 
 extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, const mcx_eigen_opts *eig)
@@ -1124,6 +1296,7 @@ extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, c
     if (!hp.fission) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs need fission data");
     if (hp.d.n_tbins > 0) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs take no time bins");
     if (hp.d.implicit_capture) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs are analog (no implicit capture)");
+    if (hp.ww) return fail(h, MCX_E_INVALID_ARG, "k-eigenvalue runs take no weight windows");
     const uint64_t N = eig->n_particles;
     if (N < 1 || N > (1ull << 30)) return fail(h, MCX_E_INVALID_ARG, "n_particles must be 1..2^30");
     if (eig->n_cycles < 1 || eig->n_inactive < 0 || eig->n_inactive > eig->n_cycles)
@@ -1229,6 +1402,7 @@ extern "C" mcx_status mcx_run_eigen(mcx_problem_t h, const mcx_run_opts *opts, c
     HIP_TRY(h, hipStreamSynchronize(stream));
     sum.qsum = (uint64_t)qsum;
     sum.overflow = qsum >= ((unsigned __int128)1 << 63) ? 1 : 0;
+    sum.generations = 1;
     h->counters = sum;
     if (sum.overflow) return fail(h, MCX_E_OVERFLOW, "fixed-point tally total reached 2^63");
     h->tallies_valid = true;
@@ -1251,6 +1425,8 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
 {
     if (!h || !opts || !dL_dT || !grad_sigma_t || !grad_sigma_s) return MCX_E_INVALID_ARG;
     if (h->emode != MCX_MG) return fail(h, MCX_E_INVALID_ARG, "the backward needs multigroup problems");
+    for (int k = 0; k < h->n; ++k)
+        if (h->hp[k].ww) return fail(h, MCX_E_INVALID_ARG, "the backward takes no weight windows");
     for (int k = 0; k < h->n; ++k)
         if (h->hp[k].d.implicit_capture)
             return fail(h, MCX_E_INVALID_ARG, "the backward needs analog histories (no implicit capture)");

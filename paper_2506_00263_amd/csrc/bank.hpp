@@ -13,20 +13,19 @@ namespace mcx {
 template <int EMODE, int MODE, int SPLIT, int EXT>
 struct Layout {
     static constexpr bool CE = EMODE == EMODE_CE;
-    static constexpr bool SIG = SPLIT != 0;
     static constexpr bool GG = MODE != MODE_FWD;
     static constexpr bool LL = MODE == MODE_REPLAY_A;
     static constexpr bool TM = EXT != 0;                // particle time and weight
     static constexpr bool DIGEST = MODE == MODE_FWD;   // present only when digests are requested
     static constexpr int D_E = 6;
-    static constexpr int D_SIG = D_E + (CE ? 1 : 0);
-    static constexpr int D_G = D_SIG + (SIG ? 1 : 0);
+    static constexpr int D_G = D_E + (CE ? 1 : 0);
     static constexpr int D_L = D_G + (GG ? 1 : 0);
     static constexpr int D_T = D_L + (LL ? 1 : 0);
     static constexpr int D_W = D_T + (TM ? 1 : 0);
     static constexpr int D_HQ = D_W + (TM ? 1 : 0);
     static constexpr int ND_CORE = D_HQ;                // without the digest field
-    static constexpr int NU_CORE = 4;                   // hid, step, gc, prob (+ ncoll)
+    static constexpr int U_NS = 4;                      // extended state: copies split off so far
+    static constexpr int NU_CORE = 4 + (TM ? 1 : 0);    // hid, step, gc, prob (+ copies) (+ ncoll)
     __host__ __device__ static int nd(bool dig) { return ND_CORE + ((DIGEST && dig) ? 1 : 0); }
     __host__ __device__ static int nu(bool dig) { return NU_CORE + ((DIGEST && dig) ? 1 : 0); }
     __host__ __device__ static int bytes(bool dig) { return nd(dig) * 8 + nu(dig) * 4; }
@@ -77,7 +76,6 @@ __device__ __forceinline__ void put(const R &s, long i, const Part &p, bool dig)
     *dptr(s, i, 4) = p.v;
     *dptr(s, i, 5) = p.w;
     if (LAY::CE) *dptr(s, i, LAY::D_E) = p.e;
-    if (LAY::SIG) *dptr(s, i, LAY::D_SIG) = p.sigt;
     if (LAY::GG) *dptr(s, i, LAY::D_G) = p.G;
     if (LAY::LL) *dptr(s, i, LAY::D_L) = p.L;
     if (LAY::TM) {
@@ -88,9 +86,10 @@ __device__ __forceinline__ void put(const R &s, long i, const Part &p, bool dig)
     *uptr(s, i, 1) = p.step;
     *uptr(s, i, 2) = p.gc;
     *uptr(s, i, 3) = p.prob;
+    if (LAY::TM) *uptr(s, i, LAY::U_NS) = p.nsplit;
     if (LAY::DIGEST && dig) {
         *(long long *)dptr(s, i, LAY::D_HQ) = p.hq;
-        *uptr(s, i, 4) = p.ncoll;
+        *uptr(s, i, LAY::NU_CORE) = p.ncoll;
     }
 }
 
@@ -104,7 +103,7 @@ __device__ __forceinline__ void get(const R &s, long i, Part &p, bool dig)
     p.v = *dptr(s, i, 4);
     p.w = *dptr(s, i, 5);
     p.e = LAY::CE ? *dptr(s, i, LAY::D_E) : 0.0;
-    p.sigt = LAY::SIG ? *dptr(s, i, LAY::D_SIG) : 0.0;
+    p.sigt = 0.0;
     p.G = LAY::GG ? *dptr(s, i, LAY::D_G) : 0.0;
     p.L = LAY::LL ? *dptr(s, i, LAY::D_L) : 0.0;
     p.t = LAY::TM ? *dptr(s, i, LAY::D_T) : 0.0;
@@ -113,11 +112,12 @@ __device__ __forceinline__ void get(const R &s, long i, Part &p, bool dig)
     p.step = *uptr(s, i, 1);
     p.gc = *uptr(s, i, 2);
     p.prob = *uptr(s, i, 3);
+    p.nsplit = LAY::TM ? *uptr(s, i, LAY::U_NS) : 0u;
     p.hq = 0;
     p.ncoll = 0;
     if (LAY::DIGEST && dig) {
         p.hq = *(const long long *)dptr(s, i, LAY::D_HQ);
-        p.ncoll = *uptr(s, i, 4);
+        p.ncoll = *uptr(s, i, LAY::NU_CORE);
     }
 }
 

@@ -189,4 +189,41 @@ hipError_t eigen_scatter_copies(uint32_t key0, uint32_t key1, uint32_t stream, u
 
 uint64_t eigen_tiles(uint64_t n) { return n_tiles(n); }
 
+// ---------------------------------------------------------------------------
+// Generations of weight-window copies.  Every history of a generation staged
+// its copies in any order (whichever wavefront ran it), each with its parent
+// and ordinal, and counted them in gn.  The next generation is those copies
+// in (parent, ordinal) order: parent offsets are an exclusive prefix sum of
+// gn (the same tile scan as the fission bank), and copy (parent, k) lands at
+// offset(parent) + k.
+
+struct StoreOffset {
+    uint64_t *off;
+    __device__ __forceinline__ void operator()(uint64_t i, uint64_t o, uint64_t) const { off[i] = o; }
+};
+
+__global__ void __launch_bounds__(256) ww_scatter_kernel(const SiteRec *stage, uint64_t m, const uint64_t *off,
+                                                         uint32_t first, SiteRec *next)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const SiteRec r = stage[i];
+    next[off[r.parent - first] + r.seq] = r;
+}
+
+hipError_t ww_order_copies(const uint32_t *gn, uint64_t n, uint32_t first, const SiteRec *stage, uint64_t m,
+                           uint64_t *tsum, uint64_t *total, uint64_t *off, SiteRec *next, hipStream_t s)
+{
+    hipError_t e = count_total(SiteCount{gn}, n, tsum, total, s);
+    if (e != hipSuccess) return e;
+    const uint64_t nt = n_tiles(n);
+    if (nt > 0)
+        hipLaunchKernelGGL((tile_apply<SiteCount, StoreOffset>), dim3((unsigned)nt), dim3(SCAN_THREADS), 0, s,
+                           SiteCount{gn}, n, (const uint64_t *)tsum, StoreOffset{off});
+    if (m > 0)
+        hipLaunchKernelGGL(ww_scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, stage, m,
+                           (const uint64_t *)off, first, next);
+    return hipGetLastError();
+}
+
 }  // namespace mcx

@@ -145,4 +145,11 @@ hipError_t eigen_scatter_copies(uint32_t key0, uint32_t key1, uint32_t stream, u
                                 const uint64_t *tsum, const double *sites, double *next, uint64_t cap,
                                 hipStream_t s);
 
+// Weight-window generations (eigen.hip): order the m copies staged by a
+// generation's n histories (first: the generation's first history id;
+// gn[i]: copies of history first + i) into next, by (parent, ordinal).
+// tsum holds eigen_tiles(n) words, off n words; *total receives m.
+hipError_t ww_order_copies(const uint32_t *gn, uint64_t n, uint32_t first, const SiteRec *stage, uint64_t m,
+                           uint64_t *tsum, uint64_t *total, uint64_t *off, SiteRec *next, hipStream_t s);
+
 }  // namespace mcx

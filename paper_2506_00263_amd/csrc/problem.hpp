@@ -12,6 +12,14 @@ enum : int { EMODE_MG = 0, EMODE_CE = 1 };
 enum : int { MODE_FWD = 0, MODE_REPLAY_A = 1, MODE_REPLAY_B = 2 };
 enum : int { MAX_SPECIES = 4 };
 
+// A copy split off by a weight window: a history of the next generation
+// starts from it.  parent: the history that split it off (index in its
+// generation); seq: the copy's ordinal among that history's copies.
+struct SiteRec {
+    double pos[3], dir[3], e, w, t;
+    uint32_t gc, parent, seq, pad;
+};
+
 struct ProbDev {
     // geometry
     int32_t geometry, n_slabs, nx, ny;
@@ -89,6 +97,22 @@ struct ProbDev {
     // to weight w_surv (the closeout of a collision)
     int32_t implicit;
     double w_cut, w_surv;
+    // spatial weight windows (the closeout of a collision or crossing): a
+    // uniform grid of ww_n cells over the box, ww_inv = ww_n / (box_hi -
+    // box_lo), lower bound ww_lo per cell (0: none), upper ww_ratio * lo,
+    // survival ww_surv * lo, at most ww_max_split copies; ww_n[0] = 0: none
+    int32_t ww_n[3], ww_max_split;
+    double ww_inv[3];
+    const double *ww_lo;
+    double ww_ratio, ww_surv;
+    // generations of split copies: this generation's source sites (null in
+    // generation 0), the staging area for the copies it splits off (gcap
+    // records, gcount filled), and per history the copies it banked
+    const SiteRec *gsrc;
+    SiteRec *gout;
+    unsigned long long *gcount;
+    uint64_t gcap;
+    uint32_t *gn;
 };
 
 enum : int {
@@ -104,7 +128,7 @@ constexpr long long TREP_MAX_BINS = 1ll << 24;
 enum Counter : int {
     C_SOURCED = 0, C_FLIGHTS, C_COLLISIONS, C_SCATTERS, C_ABSORBS, C_CROSSINGS, C_LEAKS, C_REFLECTIONS,
     C_CUTOFFS, C_KILLED, C_PIECES, C_EVENTS, C_LANE_SLOTS, C_DISPATCHES, C_SPILLS, C_REFILLS, C_MAKE_WORK,
-    C_FISSIONS, C_ROULETTES, C_COMPLETED, C_QSUM, C_PASSA_U, C_CDF, C_NUM
+    C_FISSIONS, C_ROULETTES, C_COMPLETED, C_QSUM, C_PASSA_U, C_CDF, C_SPLITS, C_NUM
 };
 constexpr int C_WAVE = C_COMPLETED;   // entries counted per wavefront (32-bit)
 

@@ -11,8 +11,8 @@
 //
 // The paper (Sec. 4) runs this loop either as one monolithic "step" event
 // per flight or decomposed into separate events at the points where lanes
-// diverge.  Both forms are here: ev_step (fused) and ev_lookup, ev_move,
-// ev_surface, ev_collide (split).  Random numbers are keyed by (history,
+// diverge.  Both forms are here: ev_step (fused) and ev_move (the step),
+// ev_surface, ev_collide, ev_closeout (split).  Random numbers are keyed by (history,
 // flight, slot), never by event, so the two forms and every scheduler give
 // identical bits.
 //
@@ -52,7 +52,7 @@ __device__ __forceinline__ T *gptr(T *p)
     return (T *)gmem(p);
 }
 
-enum : int { EV_STEP = 0, EV_LOOKUP = 0, EV_MOVE = 1, EV_SURFACE = 2, EV_COLLIDE = 3, EV_DEAD = 7 };
+enum : int { EV_STEP = 0, EV_SURFACE = 1, EV_COLLIDE = 2, EV_CLOSEOUT = 3, EV_DEAD = 7 };
 enum : uint32_t {
     O_SOURCE = 1u << 0, O_FLIGHT = 1u << 1, O_COLL = 1u << 2, O_SCAT = 1u << 3, O_ABS = 1u << 4,
     O_CROSS = 1u << 5, O_LEAK = 1u << 6, O_REFL = 1u << 7, O_CUT = 1u << 8, O_KILL = 1u << 9,
@@ -79,6 +79,7 @@ struct Part {
     uint32_t gc;      // packed group | cell | inside | surface
     uint32_t prob;    // problem index in the batch
     uint32_t ncoll;   // collisions so far (digest)
+    uint32_t nsplit;  // copies split off so far (weight windows)
 };
 
 // gc: bits 0-7 group, 8-17 cell x / slab, 18-27 cell y, 28 inside pin,
@@ -101,6 +102,7 @@ struct Lane {
     uint32_t err;
     uint32_t rep;            // this wavefront's tally replica (wavefront id mod TREP)
     uint32_t cdf;            // transfer-CDF entries read by multigroup scatters
+    uint32_t splits;         // copies split off by weight windows
 };
 
 // Everything an event needs besides the particle.
@@ -630,6 +632,7 @@ __device__ __forceinline__ void finish(const ProbDev &P, const EvCtx &cx, Lane &
 {
     uint32_t flights = (fate == FATE_KILLED) ? p.step - 1 : p.step;
     uint64_t idx = P.gbase + (uint64_t)(p.hid - P.first);
+    if (MODE == MODE_FWD && P.gn) *gmem(P.gn + idx) = p.nsplit;   // copies this history split off
     if (MODE == MODE_FWD) {
         if (cx.digest) {
             auto *dg = gmem(cx.digest + idx);
@@ -711,12 +714,28 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
     p.prob = prob;
     p.step = 1;
     p.ncoll = 0;
+    p.nsplit = 0;
     p.hq = 0;
     p.sigt = 0.0;
     p.L = 0.0;
     p.G = 0.0;
     p.t = 0.0;
     p.wgt = 1.0;
+    if (P.gsrc) {
+        // a history of a later generation: the state its copy was split off
+        // with (no source draws are used)
+        const auto *r = gmem(P.gsrc + idx);
+        p.x = r->pos[0];
+        p.y = r->pos[1];
+        p.z = r->pos[2];
+        p.u = r->dir[0];
+        p.v = r->dir[1];
+        p.w = r->dir[2];
+        p.e = r->e;
+        p.wgt = r->w;
+        p.t = r->t;
+        p.gc = r->gc;
+    }
     if (MODE == MODE_REPLAY_B) p.G = *gmem(P.G + (P.gbase + (uint64_t)(hid - P.first)));
 }
 
@@ -730,20 +749,6 @@ __device__ __forceinline__ bool kill_check(const ProbDev &P, const EvCtx &cx, La
         return true;
     }
     return false;
-}
-
-template <int GEOM, int EMODE, int MODE, class TB>
-__device__ __forceinline__ int ev_lookup(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
-{
-    if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
-    int m = material<GEOM>(P, T, p.gc);
-    if (EMODE == EMODE_MG) {
-        p.sigt = T.sig_t()[m * P.n_grp + gc_group(p.gc)];
-    } else {
-        CEXS X;
-        p.sigt = ce_lookup(P, m, p.e, X);
-    }
-    return EV_MOVE;
 }
 
 enum : int { FLY_SURFACE = 0, FLY_COLLIDE = 1, FLY_TIME = 2 };
@@ -840,10 +845,85 @@ __device__ __forceinline__ bool cross(const ProbDev &P, const TB &T, Part &p, in
 
 // Collision at the current site with the flight's random numbers xi1..xi5.
 // Returns false if the history ends (absorption, energy cutoff, roulette).
+// Weight-window closeout (extended particles; after a collision that leaves
+// the particle alive, or a surface crossing that does not leak).  The cell of
+// the position on the window grid gives the window [lo, ratio lo] and the
+// survival weight surv lo.  Above the window the particle splits into
+// n = floor(w / (surv lo)) copies, clamped to [2, max_split], of weight w / n:
+// it continues as the first, the other n - 1 are staged for the next
+// generation with their parent and ordinal (the next generation orders them
+// by those, whatever wavefront staged them).  Below the window it plays
+// roulette with xi5: survival weight with probability w / (surv lo), else the
+// history ends.  Returns false if it ended.
+template <int MODE>
+__device__ __forceinline__ bool ww_closeout(const ProbDev &P, const EvCtx &cx, Lane &ln, Part &p, double xi5,
+                                            uint32_t &out)
+{
+    const double pos[3] = {p.x, p.y, p.z};
+    long c = 0;
+#pragma unroll
+    for (int a = 2; a >= 0; --a) {
+        const int n = P.ww_n[a];
+        const double tt = (pos[a] - P.box_lo[a]) * P.ww_inv[a];
+        int i = 0;
+        if (tt > 0.0) i = (tt < (double)n) ? (int)tt : n - 1;
+        c = c * n + i;
+    }
+    const double lo = gptr(P.ww_lo)[c];
+    if (!(lo > 0.0)) return true;
+    const double surv = P.ww_surv * lo;
+    const double w = p.wgt;
+    if (w > P.ww_ratio * lo) {
+        const double q = w / surv;
+        int n = (q < (double)P.ww_max_split) ? (int)q : P.ww_max_split;
+        if (n < 2) n = 2;
+        const double wn = w / (double)n;
+        p.wgt = wn;
+        if (MODE == MODE_FWD) {
+            const unsigned long long at = __hip_atomic_fetch_add((gu64 *)P.gcount, (unsigned long long)(n - 1),
+                                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int k = 1; k < n; ++k) {
+                const unsigned long long i = at + (unsigned long long)(k - 1);
+                if (i >= P.gcap) {
+                    ln.err |= ERR_CAPACITY;
+                    continue;
+                }
+                auto *r = gmem(P.gout + i);
+                r->pos[0] = p.x;
+                r->pos[1] = p.y;
+                r->pos[2] = p.z;
+                r->dir[0] = p.u;
+                r->dir[1] = p.v;
+                r->dir[2] = p.w;
+                r->e = p.e;
+                r->w = wn;
+                r->t = p.t;
+                r->gc = p.gc & ~(3u << 29);      // no surface pending
+                r->parent = p.hid;
+                r->seq = p.nsplit + (uint32_t)(k - 1);
+                r->pad = 0;
+            }
+            p.nsplit += (uint32_t)(n - 1);
+            ln.splits += (uint32_t)(n - 1);
+        }
+        return true;
+    }
+    if (w < lo) {
+        if ((xi5 * surv) < w) {
+            p.wgt = surv;
+            return true;
+        }
+        out |= O_ROUL;
+        finish<MODE>(P, cx, ln, p, FATE_ROULETTE);
+        return false;
+    }
+    return true;
+}
+
 // With implicit capture (extended state) a collision never absorbs: the
 // particle scatters with its weight times the scattering probability, and
 // the closeout then plays weight roulette below the cutoff (xi5).
-template <int EMODE, int MODE, int EXT, class TB>
+template <int EMODE, int MODE, int EXT, bool CLOSE, class TB>
 __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, int m,
                                         double sigt, const CEXS &X, double xi1, double xi2, double xi3, double xi4,
                                         double xi5, uint32_t &out)
@@ -913,7 +993,10 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
         }
         p.e = enew;
     }
-    // closeout: weight roulette below the cutoff
+    // closeout (split events: an event of its own): weight windows, or
+    // without them weight roulette below the cutoff
+    if (!CLOSE) return true;
+    if (EXT && P.ww_n[0] > 0) return ww_closeout<MODE>(P, cx, ln, p, xi5, out);
     if (implicit && p.wgt < P.w_cut) {
         if ((xi5 * P.w_surv) < p.wgt) {
             p.wgt = P.w_surv;
@@ -951,28 +1034,60 @@ __device__ __forceinline__ int ev_step(const ProbDev &P, const TB &T, const EvCt
         double xi2, xi3, xi4, xi5;
         uniform_pair(k, p.hid, p.step, 1, xi2, xi3, P.stream);
         uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
-        if (!collide<EMODE, MODE, EXT>(P, T, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, xi5, out)) return EV_DEAD;
+        if (!collide<EMODE, MODE, EXT, true>(P, T, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, xi5, out)) return EV_DEAD;
     } else {
         if (!cross<GEOM>(P, T, p, surf, out)) {
             finish<MODE>(P, cx, ln, p, FATE_LEAK);
             return EV_DEAD;
+        }
+        if (EXT && P.ww_n[0] > 0) {
+            double xi4, xi5;
+            uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
+            if (!ww_closeout<MODE>(P, cx, ln, p, xi5, out)) return EV_DEAD;
         }
     }
     p.step += 1;
     return EV_STEP;
 }
 
-// Decomposed events ------------------------------------------------------
+// Decomposed events: the paper's decomposed scheme (Sec. 4) without domain
+// crossing.  STEP looks up the total cross section, moves the particle to
+// its next collision site or surface and scores the track on the way;
+// SURFACE crosses; COLLIDE collides; CLOSEOUT (extended particles with
+// weight windows, or implicit capture after a collision) applies weights
+// and weight windows before the next flight.  The flight counter advances
+// when the particle goes back to STEP, so every event of a flight draws
+// from that flight's slots.
+
+template <int EXT>
+__device__ __forceinline__ bool closeout_after_collision(const ProbDev &P)
+{
+    return EXT && (P.ww_n[0] > 0 || P.implicit);
+}
+
+template <int EXT>
+__device__ __forceinline__ bool closeout_after_crossing(const ProbDev &P)
+{
+    return EXT && P.ww_n[0] > 0;
+}
 
 template <int GEOM, int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p, uint32_t &out)
 {
+    if (kill_check<MODE>(P, cx, ln, p, out)) return EV_DEAD;
     int m = material<GEOM>(P, T, p.gc);
+    double sigt;
+    if (EMODE == EMODE_MG) {
+        sigt = T.sig_t()[m * P.n_grp + gc_group(p.gc)];
+    } else {
+        CEXS X;
+        sigt = ce_lookup(P, m, p.e, X);
+    }
     Key k{P.key0, P.key1};
     double xi0, xi1;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
     int surf;
-    const int res = fly<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, p.sigt, xi0, m, surf);
+    const int res = fly<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, sigt, xi0, m, surf);
     out |= O_FLIGHT;
     if (EXT && res == FLY_TIME) {
         out |= O_CUT;
@@ -983,7 +1098,7 @@ __device__ __forceinline__ int ev_move(const ProbDev &P, const TB &T, const EvCt
     return (res == FLY_COLLIDE) ? EV_COLLIDE : EV_SURFACE;
 }
 
-template <int GEOM, int EMODE, int MODE, class TB>
+template <int GEOM, int EMODE, int MODE, int EXT, class TB>
 __device__ __forceinline__ int ev_surface(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
                                           uint32_t &out)
 {
@@ -991,8 +1106,9 @@ __device__ __forceinline__ int ev_surface(const ProbDev &P, const TB &T, const E
         finish<MODE>(P, cx, ln, p, FATE_LEAK);
         return EV_DEAD;
     }
+    if (closeout_after_crossing<EXT>(P)) return EV_CLOSEOUT;
     p.step += 1;
-    return EV_LOOKUP;
+    return EV_STEP;
 }
 
 template <int GEOM, int EMODE, int MODE, int EXT, class TB>
@@ -1001,15 +1117,45 @@ __device__ __forceinline__ int ev_collide(const ProbDev &P, const TB &T, const E
 {
     int m = material<GEOM>(P, T, p.gc);
     CEXS X;
-    if (EMODE == EMODE_CE) ce_lookup(P, m, p.e, X);
+    // the flight's total cross section, as its STEP found it
+    double sigt;
+    if (EMODE == EMODE_MG) sigt = T.sig_t()[m * P.n_grp + gc_group(p.gc)];
+    else sigt = ce_lookup(P, m, p.e, X);
     Key k{P.key0, P.key1};
     double xi0, xi1, xi2, xi3, xi4, xi5;
     uniform_pair(k, p.hid, p.step, 0, xi0, xi1, P.stream);
     uniform_pair(k, p.hid, p.step, 1, xi2, xi3, P.stream);
+    xi4 = 0.0;
+    xi5 = 0.0;
     uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
-    if (!collide<EMODE, MODE, EXT>(P, T, cx, ln, p, m, p.sigt, X, xi1, xi2, xi3, xi4, xi5, out)) return EV_DEAD;
+    if (!collide<EMODE, MODE, EXT, false>(P, T, cx, ln, p, m, sigt, X, xi1, xi2, xi3, xi4, xi5, out)) return EV_DEAD;
+    if (closeout_after_collision<EXT>(P)) return EV_CLOSEOUT;
     p.step += 1;
-    return EV_LOOKUP;
+    return EV_STEP;
+}
+
+// Closeout of a collision or crossing (slot 5 of the flight): weight
+// windows, or without them implicit capture's roulette below the cutoff.
+template <int GEOM, int EMODE, int MODE, int EXT, class TB>
+__device__ __forceinline__ int ev_closeout(const ProbDev &P, const TB &T, const EvCtx &cx, Lane &ln, Part &p,
+                                           uint32_t &out)
+{
+    Key k{P.key0, P.key1};
+    double xi4, xi5;
+    uniform_pair(k, p.hid, p.step, 2, xi4, xi5, P.stream);
+    if (EXT && P.ww_n[0] > 0) {
+        if (!ww_closeout<MODE>(P, cx, ln, p, xi5, out)) return EV_DEAD;
+    } else if (EXT && P.implicit && p.wgt < P.w_cut) {
+        if ((xi5 * P.w_surv) < p.wgt) {
+            p.wgt = P.w_surv;
+        } else {
+            out |= O_ROUL;
+            finish<MODE>(P, cx, ln, p, FATE_ROULETTE);
+            return EV_DEAD;
+        }
+    }
+    p.step += 1;
+    return EV_STEP;
 }
 
 template <int GEOM, int EMODE, int MODE, int SPLIT, int EXT, class TB>
@@ -1017,10 +1163,10 @@ __device__ __forceinline__ int run_event(int ev, const ProbDev &P, const TB &T, 
                                          uint32_t &out)
 {
     if (!SPLIT) return ev_step<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
-    if (ev == EV_LOOKUP) return ev_lookup<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
-    if (ev == EV_MOVE) return ev_move<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
-    if (ev == EV_SURFACE) return ev_surface<GEOM, EMODE, MODE>(P, T, cx, ln, p, out);
-    return ev_collide<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
+    if (ev == EV_STEP) return ev_move<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
+    if (ev == EV_SURFACE) return ev_surface<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
+    if (ev == EV_COLLIDE) return ev_collide<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
+    return ev_closeout<GEOM, EMODE, MODE, EXT>(P, T, cx, ln, p, out);
 }
 
 // ------------------------------------------------------- wavefront helpers
@@ -1110,6 +1256,7 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
     uint32_t err = ln.err;
     unsigned long long pieces = ln.pieces;
     unsigned long long cdf = ln.cdf;
+    unsigned long long spl = ln.splits;
     unsigned long long u = ln.u;
     for (int off = 32; off > 0; off >>= 1) {
         unsigned long long oq = __shfl_xor(q, off);
@@ -1117,6 +1264,7 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
         uint32_t oe = __shfl_xor(err, off);
         unsigned long long op = __shfl_xor(pieces, off);
         unsigned long long oc = __shfl_xor(cdf, off);
+        unsigned long long os = __shfl_xor(spl, off);
         unsigned long long nq = q + oq;
         if (nq < q) err |= ERR_OVERFLOW;
         q = nq;
@@ -1126,6 +1274,7 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
         err |= oe;
         pieces += op;
         cdf += oc;
+        spl += os;
     }
     if (__lane_id() == 0) {
         const unsigned int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -1147,6 +1296,7 @@ __device__ __forceinline__ void flush_wave(RunCtl *ctl, const WaveCount &wc, con
             if (wc.c[i]) atomicAdd(&S[i], (unsigned long long)wc.c[i]);
         if (pieces) atomicAdd(&S[C_PIECES], pieces);
         if (cdf) atomicAdd(&S[C_CDF], cdf);
+        if (spl) atomicAdd(&S[C_SPLITS], spl);
     }
 }
 

@@ -51,6 +51,8 @@ class ProblemDesc(C.Structure):
         ("n_tbins", C.c_int32), ("t_max", C.c_double), ("speed", C.c_void_p), ("speed_coef", C.c_double),
         ("sigma_f", C.c_void_p), ("nu", C.c_void_p), ("chi", C.c_void_p),
         ("implicit_capture", C.c_int32), ("w_cutoff", C.c_double), ("w_survival", C.c_double),
+        ("ww_n", C.c_int32 * 3), ("ww_lo", C.c_void_p), ("ww_ratio", C.c_double), ("ww_surv", C.c_double),
+        ("ww_max_split", C.c_int32),
     ]
 
 
@@ -76,7 +78,8 @@ class Counters(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in COUNTER_NAMES] + [
         ("kernel_ms", C.c_double), ("grid_blocks", C.c_int32), ("block_threads", C.c_int32),
         ("lds_bytes", C.c_int32), ("pad", C.c_int32), ("fissions", C.c_uint64), ("sites", C.c_uint64),
-        ("roulettes", C.c_uint64), ("cdf_scans", C.c_uint64)]
+        ("roulettes", C.c_uint64), ("cdf_scans", C.c_uint64), ("splits", C.c_uint64),
+        ("generations", C.c_uint64)]
 
 
 class EigenOpts(C.Structure):
@@ -209,6 +212,12 @@ def _desc(d: dict, keep: list) -> ProblemDesc:
     s.implicit_capture = int(d.get("implicit_capture", 0))
     s.w_cutoff = float(d.get("w_cutoff", 0.0))
     s.w_survival = float(d.get("w_survival", 0.0))
+    if int(d.get("ww_n", [0])[0]) > 0:
+        s.ww_n[:] = [int(v) for v in d["ww_n"]]
+        s.ww_lo = arr("ww_lo", np.float64)
+        s.ww_ratio = float(d["ww_ratio"])
+        s.ww_surv = float(d["ww_surv"])
+        s.ww_max_split = int(d["ww_max_split"])
     s.sigma_f = s.nu = s.chi = None
     if d.get("sigma_f") is not None:
         mg = int(d["n_mat"]) * int(d["n_grp"])
@@ -396,6 +405,7 @@ class Problem:
         out = {n: int(getattr(c, n)) for n in COUNTER_NAMES}
         out.update(kernel_ms=c.kernel_ms, grid_blocks=c.grid_blocks, block_threads=c.block_threads,
                    lds_bytes=c.lds_bytes, fissions=int(c.fissions), sites=int(c.sites),
-                   roulettes=int(c.roulettes), cdf_scans=int(c.cdf_scans))
+                   roulettes=int(c.roulettes), cdf_scans=int(c.cdf_scans), splits=int(c.splits),
+                   generations=int(c.generations))
         return out
 
