@@ -341,7 +341,9 @@ typedef struct {
     double *dtally;           /* mode 3: lengths in double                      */
     int64_t *tally;
     const double *w;
-    double G, L;              /* pass A accumulators (path order)              */
+    double G, L;              /* pass A accumulators (path order); in pass B of
+                                 a weighted run G is the running score F      */
+    double A;                 /* pass A, weighted runs: sum of |w[bin] * len|  */
     uint64_t nfl;
     int64_t hq;               /* this history's q sum                           */
     orc_counts *cnt;
@@ -358,6 +360,12 @@ typedef struct {
 static void orc_score_bin(const orc_problem *p, orc_acc *acc, int64_t bin, double len)
 {
     if (acc->mode == 1) {
+        acc->G = acc->G + (acc->w[bin] * len);
+        if (p->implicit_capture) acc->A = acc->A + fabs(acc->w[bin] * len);
+        return;
+    }
+    if (acc->mode == 2) {
+        /* weighted pass B: the score of the pieces flown so far */
         acc->G = acc->G + (acc->w[bin] * len);
         return;
     }
@@ -669,6 +677,7 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
     if (from) t = from->t;
     acc->G = 0.0;
     acc->L = 0.0;
+    acc->A = 0.0;
     acc->nfl = 0;
     int64_t step = 1;
     for (;;) {
@@ -710,12 +719,11 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
             acc->tk = orc_time_bin(t, acc->tw, p->n_tbins);
         }
         /* track-length tally along the flight */
-        if (acc->mode != 2) {
+        if (acc->mode != 2 || p->implicit_capture) {
             if (p->tally_kind == 0) orc_tally_mesh(p, acc, pos, dir, d, g);
             else orc_tally_energy(p, acc, e, d);
-        } else {
-            gr->SL[m * p->n_grp + g] += orc_qs(Gh * d, gr->scale);
         }
+        if (acc->mode == 2) gr->SL[m * p->n_grp + g] += orc_qs(Gh * d, gr->scale);
         acc->L = acc->L + d;
         acc->nfl += 1;
         /* move */
@@ -740,8 +748,15 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
             if (p->energy_mode == 0) {
                 double ss = p->sigma_s[m * p->n_grp + g];
                 if (p->implicit_capture) {
-                    /* implicit capture: no absorption, the weight carries it */
+                    /* implicit capture: no absorption, the weight carries it.
+                       Pass B: G_h for the collision density Sigma_t, and the
+                       score still to come, G_h - F, for the weight factor
+                       Sigma_s / Sigma_t that every later piece carries */
                     acc->wt = acc->wt * (ss / sigma_t);
+                    if (acc->mode == 2) {
+                        gr->SA[m * p->n_grp + g] += orc_qs(Gh, gr->scale);
+                        gr->SS[m * p->n_grp + g] += orc_qs(Gh - acc->G, gr->scale);
+                    }
                 } else if (!((c1 * sigma_t) < ss)) {
                     fate = ORC_FATE_ABSORB;
                     cnt->absorbs += 1;
@@ -761,7 +776,7 @@ static void orc_history(const orc_problem *p, uint32_t h, orc_acc *acc, orc_grad
                     break;
                 }
                 cnt->scatters += 1;
-                if (acc->mode == 2) gr->SS[m * p->n_grp + g] += orc_qs(Gh, gr->scale);
+                if (acc->mode == 2 && !p->implicit_capture) gr->SS[m * p->n_grp + g] += orc_qs(Gh, gr->scale);
                 const double *row = p->cdf + ((int64_t)m * p->n_grp + g) * p->n_grp;
                 int32_t gn = p->n_grp - 1;
                 for (int32_t k = 0; k < p->n_grp; ++k) {
@@ -931,7 +946,10 @@ int orc_replay_a(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w
     for (uint64_t h = h0; h < h1; ++h) {
         orc_history(p, (uint32_t)h, &acc, NULL, NULL, NULL, NULL);
         G[h - h0] = acc.G;
-        double bound = ceil(fabs(acc.G) * (acc.L + (double)acc.nfl));
+        /* every pass B sum of the history is at most this in magnitude (the
+           score still to come at a collision is at most A_h) */
+        double bound = p->implicit_capture ? ceil((fabs(acc.G) + acc.A) * (acc.L + (double)acc.nfl))
+                                           : ceil(fabs(acc.G) * (acc.L + (double)acc.nfl));
         if (!(bound < 0x1p63)) { bad = 1; continue; }
         uint64_t before = u;
         u = u + (uint64_t)bound;
@@ -941,7 +959,7 @@ int orc_replay_a(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w
     return bad;
 }
 
-int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *G, int32_t s,
+int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w, const double *G, int32_t s,
                  int64_t *SL, int64_t *SA, int64_t *SS)
 {
     orc_counts local;
@@ -949,7 +967,9 @@ int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *G
     orc_acc acc;
     memset(&acc, 0, sizeof acc);
     acc.mode = 2;
+    acc.w = w;
     acc.cnt = &local;
+    if (p->implicit_capture && !w) return 2;
     orc_grad gr;
     gr.G = G;
     gr.h0 = h0;

@@ -170,14 +170,19 @@ int orc_run(const orc_problem *p, uint64_t h0, uint64_t h1, int64_t *tally,
 int orc_run_gen(const orc_problem *p, int32_t gen, const orc_site *src, uint64_t h0, uint64_t h1, int64_t *tally,
                 orc_digest *digest, orc_counts *counts, orc_site *bank, uint64_t bank_cap, uint64_t *bank_n);
 
-/* score-function backward, pass A: G_h = sum over tally pieces of w[bin]*len,
-   with L_h (track length) and n_h (flights); U += ceil(|G_h| * (L_h + n_h)) */
+/* score-function backward, pass A: G_h = sum over tally pieces of w[bin]*len
+   (len times the weight in weighted runs), with L_h (track length) and n_h
+   (flights); U += ceil(|G_h| * (L_h + n_h)), or with implicit capture
+   U += ceil((|G_h| + A_h) * (L_h + n_h)), A_h = sum of |w[bin]*len| */
 int orc_replay_a(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w,
                  double *G, uint64_t *U);
 
-/* pass B at scale 2^s: SL[m*G+g] += q(G_h*len) per flight, SA per absorption,
-   SS per scatter, with q(x) = rint(x * 2^s) */
-int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *G, int32_t s,
+/* pass B at scale 2^s, q(x) = rint(x * 2^s): SL[m*G+g] += q(G_h*len) per
+   flight.  Analog runs: SA += q(G_h) per absorption, SS += q(G_h) per
+   scatter (w unused, may be NULL).  Implicit capture: at every collision
+   SA += q(G_h) and SS += q(G_h - F), F the score w[bin]*len of the pieces
+   flown so far (w required; returns 2 without it). */
+int orc_replay_b(const orc_problem *p, uint64_t h0, uint64_t h1, const double *w, const double *G, int32_t s,
                  int64_t *SL, int64_t *SA, int64_t *SS);
 
 /* k-eigenvalue power iteration (multigroup, fission data required).

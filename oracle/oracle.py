@@ -84,7 +84,8 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(LIB_PATH):
+            if not os.path.exists(LIB_PATH) or any(os.path.getmtime(f) > os.path.getmtime(LIB_PATH)
+                                                   for f in SOURCES):
                 build()
             L = C.CDLL(LIB_PATH)
             P = C.POINTER
@@ -117,7 +118,7 @@ def lib():
             L.orc_run.argtypes = [P(OrcProblem), C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, P(OrcCounts)]
             L.orc_replay_a.argtypes = [P(OrcProblem), C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p,
                                        P(C.c_uint64)]
-            L.orc_replay_b.argtypes = [P(OrcProblem), C.c_uint64, C.c_uint64, C.c_void_p, C.c_int32,
+            L.orc_replay_b.argtypes = [P(OrcProblem), C.c_uint64, C.c_uint64, C.c_void_p, C.c_void_p, C.c_int32,
                                        C.c_void_p, C.c_void_p, C.c_void_p]
             L.orc_eigen.argtypes = [P(OrcProblem), C.c_uint64, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                     C.c_void_p, P(OrcCounts), C.c_void_p, C.c_uint64, P(C.c_uint64)]
@@ -405,20 +406,31 @@ def grad_scale(U: int) -> int:
     return 62 - int(U).bit_length()
 
 
-def replay_b(d: dict, G: np.ndarray, s: int, h0: int = 0, h1: int | None = None, threads: int | None = None):
+def replay_b(d: dict, G: np.ndarray, s: int, h0: int = 0, h1: int | None = None, threads: int | None = None,
+             w: np.ndarray | None = None):
+    """Pass B: the fixed-point sums SL, SA, SS at scale 2^s.  Weighted
+    (implicit-capture) runs need the loss weights w again: SS is then the
+    score still to come at each collision."""
     P = Problem(d)
     L = lib()
     if h1 is None:
         h1 = d["n_histories"]
     mg = d["n_mat"] * d["n_grp"]
     G = np.ascontiguousarray(G, dtype=np.float64)
+    wp = None
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        assert w.size == P.n_bins
+        wp = _ptr(w)
+    elif d.get("implicit_capture", 0):
+        raise ValueError("pass B of a weighted run needs the loss weights")
     threads = default_threads() if threads is None else threads
     parts = _ranges(h0, h1, threads)
     acc = [[np.zeros(mg, np.int64) for _ in range(3)] for _ in parts]
 
     def work(k):
         a, b = parts[k]
-        L.orc_replay_b(C.byref(P.s), a, b, _ptr(G[a - h0:]), s, *[_ptr(x) for x in acc[k]])
+        L.orc_replay_b(C.byref(P.s), a, b, wp, _ptr(G[a - h0:]), s, *[_ptr(x) for x in acc[k]])
 
     _parallel(work, len(parts))
     SL = np.sum([a[0] for a in acc], axis=0, dtype=np.int64)
@@ -428,30 +440,46 @@ def replay_b(d: dict, G: np.ndarray, s: int, h0: int = 0, h1: int | None = None,
 
 
 def grads_from_sums(d: dict, SL, SA, SS, s: int, n: int):
-    """grad Sigma_t = (-SL + SA/Sigma_a) 2^-s / N;
-    grad Sigma_s = (SS/Sigma_s - SA/Sigma_a) 2^-s / N, in float64."""
-    st = np.asarray(d["sigma_t"], np.float64)
-    ss = np.asarray(d["sigma_s"], np.float64)
+    """Analog runs: grad Sigma_t = (-SL + SA/Sigma_a) 2^-s / N and
+    grad Sigma_s = (SS/Sigma_s - SA/Sigma_a) 2^-s / N.  Implicit capture (SA
+    over collisions, SS the score still to come at them):
+    grad Sigma_t = (-SL + (SA/Sigma_t - SS/Sigma_t)) 2^-s / N and
+    grad Sigma_s = (SS/Sigma_s) 2^-s / N.  In float64."""
+    st = np.asarray(d["sigma_t"], np.float64).ravel()
+    ss = np.asarray(d["sigma_s"], np.float64).ravel()
     sa = st - ss
     sc = 2.0 ** (-s)
     gt = np.empty_like(st)
     gs = np.empty_like(st)
+    weighted = bool(d.get("implicit_capture", 0))
     for p in range(st.size):
-        gt[p] = ((-float(SL[p])) + (float(SA[p]) / sa[p])) * sc / n
-        gs[p] = ((float(SS[p]) / ss[p]) - (float(SA[p]) / sa[p])) * sc / n
+        if weighted:
+            gt[p] = ((-float(SL[p])) + ((float(SA[p]) / st[p]) - (float(SS[p]) / st[p]))) * sc / n
+            gs[p] = (float(SS[p]) / ss[p]) * sc / n
+        else:
+            gt[p] = ((-float(SL[p])) + (float(SA[p]) / sa[p])) * sc / n
+            gs[p] = ((float(SS[p]) / ss[p]) - (float(SA[p]) / sa[p])) * sc / n
     return gt, gs
 
 
 def backward(d: dict, w: np.ndarray, threads: int | None = None):
     """Score-function vector-Jacobian product for the normalised tally
-    T = raw * 2^-S / N: returns (grad Sigma_t, grad Sigma_s), each [M*G]."""
-    if d.get("implicit_capture", 0):
-        raise ValueError("the score-function backward needs analog histories (no implicit capture)")
+    T = raw * 2^-S / N: returns (grad Sigma_t, grad Sigma_s), each [M*G].
+
+    With implicit capture the tally carries weights that are products of
+    Sigma_s / Sigma_t over earlier collisions: the estimator adds their
+    derivative along the path (the score still to come after a collision,
+    times d log(Sigma_s / Sigma_t)) to the score of the path's density, in
+    which a collision is Sigma_t exp(-Sigma_t l) and the roulette's survival
+    probability is held at its value (a roulette with a fixed probability
+    is unbiased for every Sigma and plays the same game here)."""
+    if int(d.get("energy_mode", 0)) != 0:
+        raise ValueError("the score-function backward needs a multigroup problem")
     if int(d.get("ww_n", [0])[0]) > 0:
         raise ValueError("the score-function backward takes no weight windows")
     G, U = replay_a(d, w, threads=threads)
     s = grad_scale(U)
-    SL, SA, SS = replay_b(d, G, s, threads=threads)
+    SL, SA, SS = replay_b(d, G, s, threads=threads, w=w)
     gt, gs = grads_from_sums(d, SL, SA, SS, s, d["n_histories"])
     return dict(grad_sigma_t=gt, grad_sigma_s=gs, G=G, U=U, s=s, SL=SL, SA=SA, SS=SS)
 
