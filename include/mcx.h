@@ -399,8 +399,14 @@ mcx_status mcx_tallies(mcx_problem_t p, int32_t problem, int64_t *out, int64_t n
  * and scatters per (material, group), in int64 fixed point at an adaptive
  * power-of-two scale).  problem = -1 covers all problems of a batch:
  * dL_dT is then the concatenation of every problem's bins and the gradients
- * the concatenation of every problem's n_mat*n_grp entries.  Multigroup, analog
- * (no implicit capture) problems only.
+ * the concatenation of every problem's n_mat*n_grp entries.  With implicit
+ * capture the tally's weights are products of Sigma_s / Sigma_t over earlier
+ * collisions: pass B also walks the tally for the running score F and adds,
+ * at every collision, G_h and the score still to come, G_h - F, so that
+ * grad Sigma_t = -SL + (SC - SR) / Sigma_t and grad Sigma_s = SR / Sigma_s
+ * (times 2^-s / N); the roulette's survival probability is held at its value
+ * (a fixed-probability roulette is unbiased for every Sigma).  Multigroup
+ * problems without weight windows only (MCX_E_INVALID_ARG otherwise).
  * opts selects the scheduler and tuning for the replays (accumulate, range
  * and digest fields are ignored). */
 mcx_status mcx_backward(mcx_problem_t p, int32_t problem, const double *dL_dT, double *grad_sigma_t,

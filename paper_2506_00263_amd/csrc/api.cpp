@@ -1427,9 +1427,6 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
     if (h->emode != MCX_MG) return fail(h, MCX_E_INVALID_ARG, "the backward needs multigroup problems");
     for (int k = 0; k < h->n; ++k)
         if (h->hp[k].ww) return fail(h, MCX_E_INVALID_ARG, "the backward takes no weight windows");
-    for (int k = 0; k < h->n; ++k)
-        if (h->hp[k].d.implicit_capture)
-            return fail(h, MCX_E_INVALID_ARG, "the backward needs analog histories (no implicit capture)");
     if (problem < -1 || problem >= h->n) return fail(h, MCX_E_INVALID_ARG, "bad problem index");
     if (!h->have_forward) return fail(h, MCX_E_STATE, "mcx_backward needs a successful forward run first");
     mcx_run_opts o = *opts;
@@ -1491,7 +1488,11 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
     h->counters.launches += launches_a;
     h->counters.rounds += rounds_a;
     HIP_TRY(h, hipMemcpy(acc.data(), h->d_gacc, h->gacc_words * 8, hipMemcpyDeviceToHost));
-    // gradients: grad Sigma_t = (-SL + SA/Sigma_a) 2^-s / N, grad Sigma_s = (SS/Sigma_s - SA/Sigma_a) 2^-s / N
+    // gradients, analog: grad Sigma_t = (-SL + SA/Sigma_a) 2^-s / N and
+    // grad Sigma_s = (SS/Sigma_s - SA/Sigma_a) 2^-s / N; implicit capture (SA
+    // over collisions, SS the score still to come at them):
+    // grad Sigma_t = (-SL + (SA/Sigma_t - SS/Sigma_t)) 2^-s / N and
+    // grad Sigma_s = (SS/Sigma_s) 2^-s / N
     std::vector<double> gt, gs;
     for (int k = 0; k < h->n; ++k) {
         if (problem >= 0 && k != problem) continue;
@@ -1502,10 +1503,17 @@ extern "C" mcx_status mcx_backward(mcx_problem_t h, int32_t problem, const doubl
         const long long *SS = SL + 2 * mg;
         double sc = std::ldexp(1.0, -scale[k]);
         double n = (double)h->last_count[k];
+        const bool weighted = hp.d.implicit_capture != 0;
         for (size_t i = 0; i < mg; ++i) {
-            double sa = hp.sig_t[i] - hp.sig_s[i];
-            gt.push_back(((-(double)SL[i]) + ((double)SA[i] / sa)) * sc / n);
-            gs.push_back((((double)SS[i] / hp.sig_s[i]) - ((double)SA[i] / sa)) * sc / n);
+            const double st = hp.sig_t[i], ss = hp.sig_s[i];
+            if (weighted) {
+                gt.push_back(((-(double)SL[i]) + (((double)SA[i] / st) - ((double)SS[i] / st))) * sc / n);
+                gs.push_back(((double)SS[i] / ss) * sc / n);
+            } else {
+                double sa = st - ss;
+                gt.push_back(((-(double)SL[i]) + ((double)SA[i] / sa)) * sc / n);
+                gs.push_back((((double)SS[i] / ss) - ((double)SA[i] / sa)) * sc / n);
+            }
         }
     }
     size_t nb = gt.size() * 8;
@@ -1529,7 +1537,7 @@ extern "C" mcx_status mcx_workspace_size(mcx_problem_t h, const mcx_run_opts *op
     // forward, and the backward's two replays where the handle has them
     bool replays = h->emode == MCX_MG;
     for (int k = 0; k < h->n; ++k)
-        if (h->hp[k].d.implicit_capture) replays = false;
+        if (h->hp[k].ww) replays = false;
     size_t need = 0;
     for (int mode : {MODE_FWD, MODE_REPLAY_A, MODE_REPLAY_B}) {
         if (mode != MODE_FWD && !replays) continue;

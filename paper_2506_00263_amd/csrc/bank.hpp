@@ -14,13 +14,17 @@ template <int EMODE, int MODE, int SPLIT, int EXT>
 struct Layout {
     static constexpr bool CE = EMODE == EMODE_CE;
     static constexpr bool GG = MODE != MODE_FWD;
-    static constexpr bool LL = MODE == MODE_REPLAY_A;
     static constexpr bool TM = EXT != 0;                // particle time and weight
+    // pass A: track length; weighted pass B: the running score (the slot is
+    // carried by every extended pass B)
+    static constexpr bool LL = MODE == MODE_REPLAY_A || (MODE == MODE_REPLAY_B && TM);
+    static constexpr bool AA = MODE == MODE_REPLAY_A && TM;   // weighted pass A: absolute score
     static constexpr bool DIGEST = MODE == MODE_FWD;   // present only when digests are requested
     static constexpr int D_E = 6;
     static constexpr int D_G = D_E + (CE ? 1 : 0);
     static constexpr int D_L = D_G + (GG ? 1 : 0);
-    static constexpr int D_T = D_L + (LL ? 1 : 0);
+    static constexpr int D_A = D_L + (LL ? 1 : 0);
+    static constexpr int D_T = D_A + (AA ? 1 : 0);
     static constexpr int D_W = D_T + (TM ? 1 : 0);
     static constexpr int D_HQ = D_W + (TM ? 1 : 0);
     static constexpr int ND_CORE = D_HQ;                // without the digest field
@@ -78,6 +82,7 @@ __device__ __forceinline__ void put(const R &s, long i, const Part &p, bool dig)
     if (LAY::CE) *dptr(s, i, LAY::D_E) = p.e;
     if (LAY::GG) *dptr(s, i, LAY::D_G) = p.G;
     if (LAY::LL) *dptr(s, i, LAY::D_L) = p.L;
+    if (LAY::AA) *dptr(s, i, LAY::D_A) = p.A;
     if (LAY::TM) {
         *dptr(s, i, LAY::D_T) = p.t;
         *dptr(s, i, LAY::D_W) = p.wgt;
@@ -106,6 +111,7 @@ __device__ __forceinline__ void get(const R &s, long i, Part &p, bool dig)
     p.sigt = 0.0;
     p.G = LAY::GG ? *dptr(s, i, LAY::D_G) : 0.0;
     p.L = LAY::LL ? *dptr(s, i, LAY::D_L) : 0.0;
+    p.A = LAY::AA ? *dptr(s, i, LAY::D_A) : 0.0;
     p.t = LAY::TM ? *dptr(s, i, LAY::D_T) : 0.0;
     p.wgt = LAY::TM ? *dptr(s, i, LAY::D_W) : 1.0;
     p.hid = *uptr(s, i, 0);

@@ -70,7 +70,9 @@ struct Part {
     double x, y, z, u, v, w;
     double e;         // energy (continuous energy)
     double sigt;      // total cross section of the current flight (split events)
-    double G, L;      // backward accumulators
+    double G, L, A;   // backward: pass A score, track length and (weighted
+                      // runs) absolute score; pass B G_h and (weighted runs)
+                      // the running score in L
     double t;         // particle time (time-binned tallies)
     double wgt;       // statistical weight (non-analog runs; 1 otherwise)
     long long hq;     // this history's tally sum (digest)
@@ -432,12 +434,14 @@ __device__ __forceinline__ void add_lds(unsigned long long *p, unsigned long lon
 // device serialises atomics per address), or the global tally, or for a
 // large energy-bin tally this wavefront's replica (particles of a round or
 // wavefront have similar energies and hit the same few bins, so the adds are
-// spread over replicas); the fixed-point scale; pass A's dL/dT.
+// spread over replicas); the fixed-point scale; the replays' dL/dT (pass B
+// reads it only in weighted runs), and whether pass A also sums |w len|.
 struct Sink {
     unsigned long long *lt;
     unsigned long long *g;
     double tscale;
     const double *w;
+    bool wabs;
 };
 
 template <int MODE>
@@ -448,11 +452,13 @@ __device__ __forceinline__ Sink sink_of(const ProbDev &P, const Lane &ln, unsign
     k.g = nullptr;
     k.tscale = 0.0;
     k.w = nullptr;
+    k.wabs = false;
     if (MODE == MODE_FWD) {
         k.g = P.trep ? P.trep + (size_t)ln.rep * (size_t)P.n_bins : P.tally;
         k.tscale = P.tscale;
-    } else if (MODE == MODE_REPLAY_A) {
+    } else {
         k.w = gptr(P.w);
+        k.wabs = MODE == MODE_REPLAY_A && P.implicit;
     }
     return k;
 }
@@ -473,6 +479,10 @@ __device__ __forceinline__ void score(const Sink &k, Lane &ln, Part &p, long bin
         }
     } else if (MODE == MODE_REPLAY_A) {
         p.G = p.G + (k.w[bin] * len);
+        if (k.wabs) p.A = p.A + fabs(k.w[bin] * len);
+    } else {
+        // weighted pass B: the score of the pieces flown so far
+        p.L = p.L + (k.w[bin] * len);
     }
 }
 
@@ -605,7 +615,8 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
     int g = gc_group(p.gc);
     if (MODE == MODE_REPLAY_B) {
         pass_b_add<MODE>(P, cx, 0, m * P.n_grp + g, (long long)to_fixed(p.G * d, P.gscale));
-        return;
+        // weighted runs walk the tally as well, for the running score
+        if (!(EXT && P.implicit)) return;
     }
     const Sink sk = sink_of<MODE>(P, ln, cx.ltally);
     if (P.tally_kind == 0) {
@@ -644,7 +655,10 @@ __device__ __forceinline__ void finish(const ProbDev &P, const EvCtx &cx, Lane &
         }
     } else if (MODE == MODE_REPLAY_A) {
         *gmem(P.G + idx) = p.G;
-        double bound = ceil(fabs(p.G) * (p.L + (double)flights));
+        // every pass B sum of the history is at most this in magnitude (in a
+        // weighted run the score still to come at a collision is at most A)
+        double bound = P.implicit ? ceil((fabs(p.G) + p.A) * (p.L + (double)flights))
+                                  : ceil(fabs(p.G) * (p.L + (double)flights));
         if (!(bound < 0x1p63)) {
             ln.err |= ERR_BOUND;
         } else if (cx.single) {
@@ -719,6 +733,7 @@ __device__ __forceinline__ void source(const ProbDev &P, const TB &T, Part &p, u
     p.sigt = 0.0;
     p.L = 0.0;
     p.G = 0.0;
+    p.A = 0.0;
     p.t = 0.0;
     p.wgt = 1.0;
     if (P.gsrc) {
@@ -937,6 +952,13 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
         double ss = T.sig_s()[mg];
         if (implicit) {
             p.wgt = p.wgt * (ss / sigt);
+            // pass B: G_h for the collision density, and the score still to
+            // come, G_h - F, for the factor Sigma_s / Sigma_t in every later
+            // piece's weight
+            if (MODE == MODE_REPLAY_B) {
+                pass_b_add<MODE>(P, cx, 1, mg, (long long)to_fixed(p.G, P.gscale));
+                pass_b_add<MODE>(P, cx, 2, mg, (long long)to_fixed(p.G - p.L, P.gscale));
+            }
         } else if (!((xi1 * sigt) < ss)) {
             out |= O_ABS;
             if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 1, mg, (long long)to_fixed(p.G, P.gscale));
@@ -955,7 +977,7 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
             return false;
         }
         out |= O_SCAT;
-        if (MODE == MODE_REPLAY_B) pass_b_add<MODE>(P, cx, 2, mg, (long long)to_fixed(p.G, P.gscale));
+        if (MODE == MODE_REPLAY_B && !implicit) pass_b_add<MODE>(P, cx, 2, mg, (long long)to_fixed(p.G, P.gscale));
         const double *row = T.cdf() + (long)mg * P.n_grp;
         int gn = P.n_grp - 1;
         for (int k = 0; k < P.n_grp; ++k) {

@@ -5,7 +5,9 @@ The weight changes which histories end where (roulette) and what every
 piece scores (length times weight), so tallies, invariant counters and
 per-history digests must match bit for bit on every scheduler and event
 decomposition, through every tally path, with time bins, in mixed batches
-and through the global link arena.
+and through the global link arena.  The score-function backward of weighted
+runs (the running score and the score still to come at every collision)
+must give the oracle's gradients bit for bit as well.
 """
 import numpy as np
 import pytest
@@ -120,13 +122,52 @@ def test_mixed_batch(mcx, oracle):
             assert c[key] == sum(r["counts"][key] for r in refs), (sched, decomp, key)
 
 
-def test_weights_rejected_where_analog_is_required(mcx):
-    d = inputs.with_implicit_capture(inputs.lattice_mg(n_histories=500))
+@pytest.mark.parametrize("sched,decomp", SCHEDS)
+def test_weighted_backward_matches_oracle(mcx, oracle, sched, decomp):
+    # implicit capture: pass B walks the tally for the running score and adds
+    # G_h and G_h - F at every collision
+    d = inputs.with_implicit_capture(inputs.lattice_mg(n_histories=5000), 0.25, 0.5)
+    w = np.random.default_rng(17).normal(size=inputs.n_bins(d))
+    ref = oracle.backward(d, w)
+    P = mcx.Problem(d)
+    P.run(sched=sched, decomp=decomp)
+    gt, gs = P.backward(w, sched=sched, decomp=decomp)
+    assert np.array_equal(gt, ref["grad_sigma_t"]), (gt[:4], ref["grad_sigma_t"][:4])
+    assert np.array_equal(gs, ref["grad_sigma_s"])
+
+
+def test_weighted_backward_time_bins_spills_shared(mcx, oracle):
+    d = inputs.with_implicit_capture(inputs.with_time_bins(inputs.cfg1_box(6000), 5, 30.0), 0.2, 0.6)
+    w = np.random.default_rng(18).uniform(-1.0, 1.0, inputs.n_bins(d))
+    ref = oracle.backward(d, w)
     P = mcx.Problem(d)
     P.run(sched="async")
-    with pytest.raises(mcx.McxError) as e:
-        P.backward(np.zeros(inputs.n_bins(d)), sched="async")
-    assert e.value.status == 1
+    for kw in ({"sched": "async", "force_spill": 3, "stash_links": 6},
+               {"sched": "async", "decomp": "split", "async_shared_stash": 1},
+               {"sched": "stack", "decomp": "split", "stack_capacity": 64 * 1024 * 8, "stack_threshold": 2048}):
+        gt, gs = P.backward(w, **kw)
+        assert np.array_equal(gt, ref["grad_sigma_t"]) and np.array_equal(gs, ref["grad_sigma_s"]), kw
+
+
+def test_weighted_backward_mixed_batch(mcx, oracle):
+    probs = inputs.cfg5_batch(n_problems=12, hist_scale=0.02)
+    mixed = [inputs.with_implicit_capture(d, 0.2, 0.5) if k % 2 else d for k, d in enumerate(probs)]
+    P = mcx.Problem(mixed)
+    P.run(sched="async")
+    ws = [np.random.default_rng(40 + k).normal(size=inputs.n_bins(d)) for k, d in enumerate(mixed)]
+    for sched in ("async", "stack"):
+        gt, gs = P.backward(np.concatenate(ws), problem=-1, sched=sched)
+        off = 0
+        for d, w in zip(mixed, ws):
+            ref = oracle.backward(d, w)
+            mg = d["n_mat"] * d["n_grp"]
+            assert np.array_equal(gt[off:off + mg], ref["grad_sigma_t"]), sched
+            assert np.array_equal(gs[off:off + mg], ref["grad_sigma_s"]), sched
+            off += mg
+
+
+def test_weights_rejected_where_analog_is_required(mcx):
+    d = inputs.with_implicit_capture(inputs.lattice_mg(n_histories=500))
     with pytest.raises(mcx.McxError):
         mcx.Problem(inputs.with_fission(d)).run_eigen(100, 2, 1)
     for wc, ws in ((-0.1, 0.5), (0.6, 0.5), (0.1, 0.0), (0.1, float("inf"))):
