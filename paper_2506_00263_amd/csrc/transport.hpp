@@ -228,11 +228,11 @@ __device__ __forceinline__ int edge_index_guess(const double *__restrict__ e, in
     return edge_index_from(e, n, x, dir, g);
 }
 
+// (one division whatever the sign of u: lanes moving either way share it)
 __device__ __forceinline__ double plane_dist(double lo, double hi, double x, double u)
 {
-    double d = inf();
-    if (u > 0.0) d = (hi - x) / u;
-    else if (u < 0.0) d = (lo - x) / u;
+    const double q = ((u > 0.0) ? (hi - x) : (lo - x)) / u;
+    double d = (u > 0.0 || u < 0.0) ? q : inf();
     if (d < 0.0) d = 0.0;
     return d;
 }
@@ -278,16 +278,20 @@ __device__ __forceinline__ double surface_distance(const ProbDev &P, const TB &T
         double k = (ddx * p.u) + (ddy * p.v);
         double c = ((ddx * ddx) + (ddy * ddy)) - P.r2;
         double disc = (k * k) - (a * c);
-        if (gc_in(p.gc)) {
-            if (a > 0.0) {
-                if (disc < 0.0) disc = 0.0;
-                dc = (root(disc) - k) / a;
-            }
-        } else {
-            dx = plane_dist(T.xpl()[c0], T.xpl()[c0 + 1], p.x, p.u);
-            dy = plane_dist(T.ypl()[c1], T.ypl()[c1 + 1], p.y, p.v);
-            if (a > 0.0 && k < 0.0 && disc >= 0.0) dc = c / (root(disc) - k);
-        }
+        // inside the pin the cylinder is left at (sqrt(disc) - k) / a; outside
+        // it is met (if at all) at c / (sqrt(disc) - k) and the cell planes
+        // bound the flight too.  Both sides are evaluated with the same root
+        // and one division, operands chosen per lane, so a wavefront with
+        // lanes on both sides runs each once
+        const bool in = gc_in(p.gc) != 0;
+        const double px = plane_dist(T.xpl()[c0], T.xpl()[c0 + 1], p.x, p.u);
+        const double py = plane_dist(T.ypl()[c1], T.ypl()[c1 + 1], p.y, p.v);
+        dx = in ? inf() : px;
+        dy = in ? inf() : py;
+        const double r = root((disc < 0.0) ? 0.0 : disc);
+        const bool hit = in ? (a > 0.0) : (a > 0.0 && k < 0.0 && disc >= 0.0);
+        const double q = (in ? (r - k) : c) / (in ? a : (r - k));
+        dc = hit ? q : inf();
         if (dc < 0.0) dc = 0.0;
     }
     int s = 0;
@@ -467,7 +471,14 @@ template <int MODE>
 __device__ __forceinline__ void score(const Sink &k, Lane &ln, Part &p, long bin, double len)
 {
     if (MODE == MODE_FWD) {
-        long long q = (long long)to_fixed(len, k.tscale);
+        // rint(len 2^S) as an integer: for 0 <= v < 2^52 the sum v + 2^52,
+        // rounded to nearest even, is 2^52 + rint(v) exactly, whose bit
+        // pattern less that of 2^52 is the integer (no float-to-int64
+        // conversion sequence)
+        const double v = len * k.tscale;
+        long long q;
+        if (v >= 0.0 && v < 0x1p52) q = (long long)(__double_as_longlong(v + 0x1p52) - 0x4330000000000000ll);
+        else q = (long long)to_fixed(len, k.tscale);
         if (q != 0) {
             if (k.lt) add_lds(k.lt + bin, (unsigned long long)q);
             else add_global(k.g + bin, (unsigned long long)q);
@@ -541,11 +552,18 @@ __device__ __forceinline__ void score_piece(const ProbDev &P, const Sink &sk, La
     }
 }
 
+// index of the edge bounding cell i + (one cell along u) on its far side,
+// clamped into [0, n]: the edge the crossing after next will be measured to
+__device__ __forceinline__ int edge_after(int i, double u, int n)
+{
+    const int j = (u > 0.0) ? i + 2 : i - 1;
+    return (j < 0) ? 0 : (j > n ? n : j);
+}
+
 __device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, double x0, double u)
 {
-    double t = inf();
-    if (u > 0.0) t = (e[i + 1] - x0) / u;
-    else if (u < 0.0) t = (e[i] - x0) / u;
+    const double q = (e[(u > 0.0) ? i + 1 : i] - x0) / u;
+    double t = (u > 0.0 || u < 0.0) ? q : inf();
     if (t < 0.0) t = 0.0;
     return t;
 }
@@ -565,32 +583,50 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, const S
     double t0 = axis_t(mx, i0, p.x, p.u);
     double t1 = axis_t(my, i1, p.y, p.v);
     double t2 = axis_t(mz, i2, p.z, p.w);
+    // the edge each axis's next-but-one crossing will need, read one crossing
+    // ahead (index clamped into the table; the value is used only once the
+    // index is inside the mesh), so no crossing waits for its LDS read
+    double q0 = mx[edge_after(i0, p.u, n0)];
+    double q1 = my[edge_after(i1, p.v, n1)];
+    double q2 = mz[edge_after(i2, p.w, n2)];
     double tprev = 0.0;
+    // the bin of cell (i0, i1, i2) in group g; a crossing moves it by the
+    // axis stride 1, n0 or n0 n1
+    long bin = (((long)g * n2 + i2) * n1 + i1) * n0 + i0;
+    const long sy = n0, sz = (long)n0 * n1;
     for (;;) {
         int a = 0;
         double tm = t0;
         if (t1 < tm) { tm = t1; a = 1; }
         if (t2 < tm) { tm = t2; a = 2; }
         double tend = (tm < d) ? tm : d;
-        long bin = (((long)g * n2 + i2) * n1 + i1) * n0 + i0;
         score_piece<MODE, EXT>(P, sk, ln, p, ts, bin, tprev, tend);
         if (tm >= d) break;
-        if (a == 0) {
-            i0 += (p.u > 0.0) ? 1 : -1;
-            if (i0 < 0 || i0 >= n0) break;
-            t0 = (mx[i0 + ((p.u > 0.0) ? 1 : 0)] - p.x) / p.u;
-            if (t0 < 0.0) t0 = 0.0;
-        } else if (a == 1) {
-            i1 += (p.v > 0.0) ? 1 : -1;
-            if (i1 < 0 || i1 >= n1) break;
-            t1 = (my[i1 + ((p.v > 0.0) ? 1 : 0)] - p.y) / p.v;
-            if (t1 < 0.0) t1 = 0.0;
-        } else {
-            i2 += (p.w > 0.0) ? 1 : -1;
-            if (i2 < 0 || i2 >= n2) break;
-            t2 = (mz[i2 + ((p.w > 0.0) ? 1 : 0)] - p.z) / p.w;
-            if (t2 < 0.0) t2 = 0.0;
-        }
+        // advance along the crossed axis: its edges, position, direction and
+        // index are selected, so every lane makes one edge read and one
+        // division whichever axis it crosses (a branch per axis would make a
+        // wavefront whose lanes cross different axes pay for all three)
+        const double ua = (a == 0) ? p.u : (a == 1) ? p.v : p.w;
+        const double xa = (a == 0) ? p.x : (a == 1) ? p.y : p.z;
+        const double *ea = (a == 0) ? mx : (a == 1) ? my : mz;
+        const int na = (a == 0) ? n0 : (a == 1) ? n1 : n2;
+        int ia = ((a == 0) ? i0 : (a == 1) ? i1 : i2) + ((ua > 0.0) ? 1 : -1);
+        if (ia < 0 || ia >= na) break;
+        // edge ea[ia + (ua > 0)], read one crossing ago
+        double ta = (((a == 0) ? q0 : (a == 1) ? q1 : q2) - xa) / ua;
+        if (ta < 0.0) ta = 0.0;
+        const double qn = ea[edge_after(ia, ua, na)];
+        q0 = (a == 0) ? qn : q0;
+        q1 = (a == 1) ? qn : q1;
+        q2 = (a == 2) ? qn : q2;
+        const long sa = (a == 0) ? 1l : (a == 1) ? sy : sz;
+        bin += (ua > 0.0) ? sa : -sa;
+        i0 = (a == 0) ? ia : i0;
+        i1 = (a == 1) ? ia : i1;
+        i2 = (a == 2) ? ia : i2;
+        t0 = (a == 0) ? ta : t0;
+        t1 = (a == 1) ? ta : t1;
+        t2 = (a == 2) ? ta : t2;
         tprev = tend;
     }
 }
@@ -634,6 +670,25 @@ __device__ __forceinline__ void score_flight(const ProbDev &P, const TB &T, cons
         score_piece<MODE, EXT>(P, sk, ln, p, ts, k, 0.0, d);
     }
     if (MODE == MODE_REPLAY_A) p.L = p.L + d;
+}
+
+// First k in [0, n) with xi < row[k], else n - 1 (the outgoing group of a
+// scatter).  Entries are read four at a time as independent loads, so the
+// scan waits for one LDS round trip per four entries rather than per entry.
+__device__ __forceinline__ int cdf_first_above(const double *row, int n, double xi)
+{
+    for (int k = 0; k < n; k += 4) {
+        const int last = n - 1;
+        const double r0 = row[k];
+        const double r1 = row[(k + 1 < n) ? k + 1 : last];
+        const double r2 = row[(k + 2 < n) ? k + 2 : last];
+        const double r3 = row[(k + 3 < n) ? k + 3 : last];
+        if (xi < r0) return k;
+        if (k + 1 < n && xi < r1) return k + 1;
+        if (k + 2 < n && xi < r2) return k + 2;
+        if (k + 3 < n && xi < r3) return k + 3;
+    }
+    return n - 1;
 }
 
 // ---------------------------------------------------------------- events
@@ -978,14 +1033,7 @@ __device__ __forceinline__ bool collide(const ProbDev &P, const TB &T, const EvC
         }
         out |= O_SCAT;
         if (MODE == MODE_REPLAY_B && !implicit) pass_b_add<MODE>(P, cx, 2, mg, (long long)to_fixed(p.G, P.gscale));
-        const double *row = T.cdf() + (long)mg * P.n_grp;
-        int gn = P.n_grp - 1;
-        for (int k = 0; k < P.n_grp; ++k) {
-            if (xi2 < row[k]) {
-                gn = k;
-                break;
-            }
-        }
+        const int gn = cdf_first_above(T.cdf() + (long)mg * P.n_grp, P.n_grp, xi2);
         ln.cdf += (uint32_t)gn + 1u;
         p.gc = (p.gc & ~0xffu) | (uint32_t)gn;
         isotropic(xi3, xi4, p);
