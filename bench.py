@@ -124,6 +124,53 @@ def _wall(P, reps, **kw):
     return float(np.median(ts[1:]))
 
 
+def _kernel_ms(P, reps, **kw) -> float:
+    ks = []
+    for _ in range(reps):
+        P.run(time_kernels=True, **kw)
+        ks.append(P.counters()["kernel_ms"])
+    return float(np.median(ks))
+
+
+def latency_block(P, n_hist: int) -> dict:
+    """Where the asynchronous kernel's time goes on the lattice (default
+    knobs): its kernel time against the number of histories (the slope over
+    the two largest runs is the marginal cost of a history, the intercept the
+    fixed cost of a run's start and end), the latency of one wavefront
+    running a single history (a fit of kernel time against that history's
+    flights over 20 seeds), and the headline run's longest history, whose
+    flights times that latency bound the run's end from below."""
+    import torch
+    from paper_2506_00263_amd import inputs, mcx
+    by_n = []
+    for n in (250_000, 500_000, 1_000_000, 2_000_000):
+        Q = mcx.Problem(inputs.cfg2_lattice(n))
+        Q.run(sched="async")
+        by_n.append((n, _kernel_ms(Q, 5, sched="async")))
+        del Q
+    (n1, t1), (n2, t2) = by_n[-2], by_n[-1]
+    slope = (t2 - t1) / (n2 - n1)
+    lone = []
+    for seed in range(1, 21):
+        Q = mcx.Problem(dict(inputs.cfg2_lattice(1), seed=seed))
+        dg = torch.zeros(24, dtype=torch.uint8, device="cuda")
+        Q.run(sched="async", digest=dg)
+        fl = int(dg.cpu().numpy().view(mcx.DIGEST_DTYPE)["flights"][0])
+        lone.append((fl, _kernel_ms(Q, 3, sched="async")))
+        del Q
+    fl = np.array([x[0] for x in lone], dtype=np.float64)
+    tk = np.array([x[1] for x in lone])
+    per_flight, lone_fixed = np.linalg.lstsq(np.vstack([fl, np.ones_like(fl)]).T, tk, rcond=None)[0]
+    dg = torch.zeros(24 * n_hist, dtype=torch.uint8, device="cuda")
+    P.run(sched="async", digest=dg)
+    longest = int(dg.cpu().numpy().view(mcx.DIGEST_DTYPE)["flights"].max())
+    return {"scheduler": "async", "decomposition": "fused",
+            "kernel_ms_by_histories": {str(n): t for n, t in by_n},
+            "marginal_ns_per_history": 1e6 * slope, "fixed_ms": t2 - slope * n2,
+            "lone_us_per_flight": 1e3 * float(per_flight), "lone_fixed_us": 1e3 * float(lone_fixed),
+            "longest_history_flights": longest, "tail_floor_ms": longest * float(per_flight)}
+
+
 SWEEP_PARTS = ("box", "lattice", "pincell_ce", "pincell_time", "tally_path", "eigen", "async_waves", "weights",
                "backward", "batch")
 
@@ -324,6 +371,8 @@ def main():
     ap.add_argument("--histories", type=int, default=0, help="histories (0: 1e6)")
     ap.add_argument("--no-extras", action="store_true", help="time only the headline configuration")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--latency", action="store_true",
+                    help="lattice: also report where the asynchronous kernel's time goes (with --no-extras too)")
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the benchmark line, print one JSON object with the measurement sweep: "
                          "box histories 1e4..1e7, lattice histories 1e5..1e7, the continuous-energy pin cell over bins, lookups and "
@@ -412,6 +461,8 @@ def main():
         # input population of each remapping round of the last timed run
         out["stack_rounds"] = [int(v) for v in P.stack_rounds()]
 
+    if args.latency and args.no_extras and args.workload == "lattice":
+        out["latency"] = latency_block(P, N_HIST)
     if not args.no_extras:
         from paper_2506_00263_amd import autotune
         sched = {}
@@ -542,6 +593,8 @@ def main():
             eres[f"{s}_{dc}"] = {"ms": 1e3 * t, "hist_per_s": nh / t}
         out["eigen"] = {"per_cycle": N_HIST, "cycles": 24, "inactive": 6,
                         "k_active_mean": float(np.mean(eref[0][6:])), **eres}
+        if args.workload == "lattice":
+            out["latency"] = latency_block(P, N_HIST)
 
     if not args.no_cpu:
         # the oracle as it stands, on the host cores: the whole workload,
