@@ -552,14 +552,6 @@ __device__ __forceinline__ void score_piece(const ProbDev &P, const Sink &sk, La
     }
 }
 
-// index of the edge bounding cell i + (one cell along u) on its far side,
-// clamped into [0, n]: the edge the crossing after next will be measured to
-__device__ __forceinline__ int edge_after(int i, double u, int n)
-{
-    const int j = (u > 0.0) ? i + 2 : i - 1;
-    return (j < 0) ? 0 : (j > n ? n : j);
-}
-
 __device__ __forceinline__ double axis_t(const double *__restrict__ e, int i, double x0, double u)
 {
     const double q = (e[(u > 0.0) ? i + 1 : i] - x0) / u;
@@ -583,12 +575,6 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, const S
     double t0 = axis_t(mx, i0, p.x, p.u);
     double t1 = axis_t(my, i1, p.y, p.v);
     double t2 = axis_t(mz, i2, p.z, p.w);
-    // the edge each axis's next-but-one crossing will need, read one crossing
-    // ahead (index clamped into the table; the value is used only once the
-    // index is inside the mesh), so no crossing waits for its LDS read
-    double q0 = mx[edge_after(i0, p.u, n0)];
-    double q1 = my[edge_after(i1, p.v, n1)];
-    double q2 = mz[edge_after(i2, p.w, n2)];
     double tprev = 0.0;
     // the bin of cell (i0, i1, i2) in group g; a crossing moves it by the
     // axis stride 1, n0 or n0 n1
@@ -612,13 +598,8 @@ __device__ __forceinline__ void walk_mesh(const ProbDev &P, const TB &T, const S
         const int na = (a == 0) ? n0 : (a == 1) ? n1 : n2;
         int ia = ((a == 0) ? i0 : (a == 1) ? i1 : i2) + ((ua > 0.0) ? 1 : -1);
         if (ia < 0 || ia >= na) break;
-        // edge ea[ia + (ua > 0)], read one crossing ago
-        double ta = (((a == 0) ? q0 : (a == 1) ? q1 : q2) - xa) / ua;
+        double ta = (ea[ia + ((ua > 0.0) ? 1 : 0)] - xa) / ua;
         if (ta < 0.0) ta = 0.0;
-        const double qn = ea[edge_after(ia, ua, na)];
-        q0 = (a == 0) ? qn : q0;
-        q1 = (a == 1) ? qn : q1;
-        q2 = (a == 2) ? qn : q2;
         const long sa = (a == 0) ? 1l : (a == 1) ? sy : sz;
         bin += (ua > 0.0) ? sa : -sa;
         i0 = (a == 0) ? ia : i0;
