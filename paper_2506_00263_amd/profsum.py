@@ -32,7 +32,9 @@ from collections import defaultdict
 
 from . import build
 
-KERNELS = {"naive": "naive_kernel", "stack": "stack_round", "async": "async_kernel"}
+# the kernels a scheduler launches for its work (the asynchronous scheme runs
+# the block-shared stash kernel for decomposed events of large runs)
+KERNELS = {"naive": ("naive_kernel",), "stack": ("stack_round",), "async": ("async_kernel", "async_shared_kernel")}
 PASSES = {
     "fetch": ["FETCH_SIZE"],
     "write": ["WRITE_SIZE", "TCC_HIT_sum", "TCC_MISS_sum"],
@@ -66,7 +68,7 @@ def counters(d: str, pass_name: str, sched: str):
         name = r["Kernel_Name"]
         by_dispatch[(r["Dispatch_Id"], name)][r["Counter_Name"]] = float(r["Counter_Value"])
     for (did, name), cs in by_dispatch.items():
-        short = next((v for v in KERNELS.values() if v in name), None)
+        short = next((v for vs in KERNELS.values() for v in vs if v in name), None)
         if short is None:
             if "copyBuffer" in name and cs.get("FETCH_SIZE", cs.get("WRITE_SIZE", 0.0)) * 1024 > COPY_BYTES / 4:
                 copy = cs
@@ -82,24 +84,24 @@ def counters(d: str, pass_name: str, sched: str):
     return out, copy
 
 
-def kernel_stats(d: str, sched: str):
+def kernel_stats(d: str, sched: str, kern: str):
     rows = _csv(os.path.join(d, f"trace_{sched}", "**", "*kernel_stats.csv"))
     for r in rows:
-        if KERNELS[sched] in r["Name"]:
+        if kern in r["Name"]:
             return {"calls": int(r["Calls"]), "total_ns": float(r["TotalDurationNs"]),
                     "avg_ns": float(r["AverageNs"]), "min_ns": float(r["MinNs"]), "max_ns": float(r["MaxNs"])}
     return None
 
 
-def launch_durations(d: str, sched: str):
-    """Durations (ns) of the scheduler kernel's dispatches in start order."""
+def launch_durations(d: str, sched: str, kern: str):
+    """Durations (ns) of kernel `kern`'s dispatches in start order."""
     rows = _csv(os.path.join(d, f"trace_{sched}", "**", "*kernel_trace.csv"))
     ds = [(int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
-          for r in rows if KERNELS[sched] in r["Kernel_Name"]]
+          for r in rows if kern in r["Kernel_Name"]]
     return [dur for _, dur in sorted(ds)]
 
 
-def round_table(d: str, sched: str):
+def round_table(d: str, sched: str, kern: str):
     """Per-round rows (round, input particles, duration us) of the last run
     of a stack trace, or None."""
     try:
@@ -109,7 +111,7 @@ def round_table(d: str, sched: str):
         return None
     rounds = bench.get("stack_rounds")
     n = bench.get("counters", {}).get("launches")
-    durs = launch_durations(d, sched)
+    durs = launch_durations(d, sched, kern)
     if not rounds or not n or len(durs) < n:
         return None
     last = durs[-n:]
@@ -119,14 +121,14 @@ def round_table(d: str, sched: str):
 def summarise(d: str, out_dir: str, workload: str, decomp: str = "fused", bench_args: str = "") -> dict:
     src = build.source_hash()
     traffic = {}
-    for sched, kern in KERNELS.items():
-        st = kernel_stats(d, sched)
+    for sched, kern in ((s, k) for s, ks in KERNELS.items() for k in ks):
         f, fcopy = counters(d, "fetch", sched)
         w, wcopy = counters(d, "write", sched)
-        s1, _ = counters(d, "sq1", sched)
-        s2, _ = counters(d, "sq2", sched)
         if kern not in f or kern not in w:
             continue
+        st = kernel_stats(d, sched, kern)
+        s1, _ = counters(d, "sq1", sched)
+        s2, _ = counters(d, "sq2", sched)
         rf = COPY_BYTES / (fcopy["FETCH_SIZE"] * 1024) if fcopy.get("FETCH_SIZE") else None
         rw = COPY_BYTES / (wcopy["WRITE_SIZE"] * 1024) if wcopy.get("WRITE_SIZE") else None
         rd = f[kern]["FETCH_SIZE"] * 1024 * rf if rf else None
@@ -182,7 +184,7 @@ def summarise(d: str, out_dir: str, workload: str, decomp: str = "fused", bench_
             for c in PASSES["sq2"]:
                 lines.append(f"| {c} | {b[c]:.4g} |")
         lines.append("")
-        rt = round_table(d, sched) if sched == "stack" else None
+        rt = round_table(d, sched, kern) if sched == "stack" else None
         if rt:
             lines.append("Remapping rounds of the last run (input particles from bench.py's `stack_rounds`, "
                          "duration from the kernel trace; rounds past the last one are queued launches that "

@@ -28,7 +28,7 @@ def _counter_rows(kernel, values, copy_values):
 
 
 def _fake_run(d, sched="async"):
-    kern = profsum.KERNELS[sched]
+    kern = profsum.KERNELS[sched][0]
     hdr = ["Kernel_Name", "Dispatch_Id", "Counter_Name", "Counter_Value"]
     # the copy reads half and writes all of 1 GiB in KiB: scales x2 and x1
     _write(os.path.join(d, f"fetch_{sched}", "run_counter_collection.csv"), hdr,
