@@ -270,6 +270,11 @@ typedef struct {
                                  MCX_E_INVALID_ARG before anything runs.  NULL:
                                  the handle's own workspace, grown on demand. */
     size_t ws_bytes;
+    int32_t async_bulk_events;/* async, fused events: a full link's particles
+                                 run up to this many events in place, until
+                                 more than 4 of them have ended, before the
+                                 link is repacked and refilled (0 = library
+                                 default, 64; 1 = one event per pass)         */
 } mcx_run_opts;
 
 /* Tally paths (results are the same integers on every path):

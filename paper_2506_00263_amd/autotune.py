@@ -36,6 +36,8 @@ def candidates(sched: str, decomp: str, histories: int = 0) -> list:
                 for links in sorted({events + 1, events + 2, events + 3}):
                     out.append(dict(async_block_waves=wpb, waves_per_cu=wpc, stash_links=links))
         out += [dict(async_drain_events=k) for k in (1, 4, 16, 64)]
+        if decomp == "fused":
+            out += [dict(async_bulk_events=k) for k in (1, 8)]
         for shared in (1, 2):
             for wpb in (4, 2):
                 for links in (0, events + wpb + 1, events + 2 * wpb + 2):

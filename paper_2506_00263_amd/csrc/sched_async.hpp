@@ -52,10 +52,23 @@ struct AsyncArgs {
     int tl_bytes;                // packed tables copied to LDS (single problem)
     int wpb;                     // wavefronts per block (each with its own stash)
     int drain_events;            // events per pass on a drained wavefront's partial link
+    int bulk_events;             // fused: events per pass on a full link
 };
 
 constexpr uint32_t NIL = 0xFFFFFFFFu;
 constexpr int DONATE_BELOW = 32;   // a drained stash with fewer particles is donated
+
+// Whether a link's particles run another event in place (wave-uniform).  A
+// drained wavefront's partial link goes on while any particle lives; a full
+// link (fused events) while at most ASYNC_BULK_ENDED of its particles have
+// ended, so few slots idle before it is repacked and refilled.  Every
+// history draws from its own keyed streams and the tallies are integer
+// sums, so how many events run in place never changes a result.
+__device__ __forceinline__ bool goes_on(bool drained, bool act, bool live)
+{
+    if (drained) return __ballot(live) != 0;
+    return __popcll(__ballot(act && !live)) <= ASYNC_BULK_ENDED;
+}
 constexpr unsigned long long Q_EMPTY = ~0ull;
 constexpr unsigned long long Q_CLAIMED = 0xFFFFFFFEFFFFFFFEull;
 __device__ __forceinline__ uint32_t q_head(unsigned long long q) { return (uint32_t)(q >> 32); }
@@ -527,7 +540,9 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
         // partial link has no full link to be packed with: its particles
         // run up to drain_events events in place (their histories draw from
         // their own keyed streams, so results do not change), which saves
-        // the unpack and pack of every event on the longest histories.
+        // the unpack and pack of every event on the longest histories.  A
+        // full link of fused events runs up to bulk_events events in place
+        // while few of its particles have ended (see bulk_goes_on).
         idle = Wait{};                              // the wait budget is per idle spell
         int ev = W.S.ev(l);
         int c = W.S.cnt(l);
@@ -536,7 +551,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
         if (act) get<LAY>(W.link(l), lane, p, dig);
         W.S.freem |= 1u << l;
         int ne = EV_DEAD;
-        const int K = drained ? A.drain_events : 1;
+        const int K = drained ? A.drain_events : (SPLIT ? 1 : A.bulk_events);
         int cur = ev;
         bool live = act;
         for (int i = 0;;) {
@@ -546,7 +561,7 @@ async_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
             wc.outcomes(live, out);
             if (++i >= K) break;
             live = live && ne != EV_DEAD;
-            if (__ballot(live) == 0) break;
+            if (!goes_on(drained, act, live)) break;
             cur = ne;
         }
         W.template deposit<LAY, E>(act, ne, p, dig, wc, ln.err);
@@ -937,9 +952,10 @@ async_shared_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
         int ne = EV_STEP;
         if (!fresh) {
             // run the event on the particles; a drained wavefront's closed
-            // partial link runs up to drain_events events in place
+            // partial link runs up to drain_events events in place, a full
+            // link of fused events up to bulk_events
             ne = EV_DEAD;
-            const int K = drained ? A.drain_events : 1;
+            const int K = drained ? A.drain_events : (SPLIT ? 1 : A.bulk_events);
             int cur = ev;
             bool live = act;
             for (int i = 0;;) {
@@ -949,7 +965,7 @@ async_shared_kernel(AsyncArgs A, const ProbDev *__restrict__ probs)
                 wc.outcomes(live, out);
                 if (++i >= K) break;
                 live = live && ne != EV_DEAD;
-                if (__ballot(live) == 0) break;
+                if (!goes_on(drained, act, live)) break;
                 cur = ne;
             }
         }
@@ -1128,6 +1144,7 @@ static hipError_t async_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.tl_bytes = tl_bytes;
     A.wpb = wpb;
     A.drain_events = a.async_drain_events > 0 ? a.async_drain_events : ASYNC_DRAIN_EVENTS;
+    A.bulk_events = a.async_bulk_events > 0 ? a.async_bulk_events : ASYNC_BULK_EVENTS;
     int ib = (std::max(n_arena, Q) + 255) / 256;
     hipLaunchKernelGGL(arena_init, dim3(ib), dim3(256), 0, a.stream, A, (unsigned int)waves);
     st.grid_blocks = (int)blocks;
