@@ -275,6 +275,14 @@ typedef struct {
                                  more than 4 of them have ended, before the
                                  link is repacked and refilled (0 = library
                                  default, 64; 1 = one event per pass)         */
+    int32_t stack_bulk_events;/* stack, fused events: a popped chunk's
+                                 particles go on past their events per pop,
+                                 up to this many events in place, while at
+                                 least 60 of its 64 lanes hold live particles
+                                 (0 = library default: 64 for continuous
+                                 energy, 1 = off for multigroup problems,
+                                 whose short histories make the rounds wait
+                                 for the chunks that go on)                   */
 } mcx_run_opts;
 
 /* Tally paths (results are the same integers on every path):

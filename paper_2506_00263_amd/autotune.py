@@ -46,6 +46,8 @@ def candidates(sched: str, decomp: str, histories: int = 0) -> list:
     if sched == "stack":
         out += [dict(stack_min_events=m, stack_tail_events=t) for m in (1, 2, 4, 6, 8) for t in (16, 64, 256)]
         out += [dict(waves_per_cu=w) for w in (4, 8)]
+        if decomp == "fused":
+            out += [dict(stack_bulk_events=1)]
         if histories >= 4096:
             out += [dict(stack_threshold=max(256, histories // f)) for f in (2, 8, 32)]
         return out

@@ -797,6 +797,8 @@ static mcx_status check_opts(mcx_problem_t h, const mcx_run_opts &o)
         return fail(h, MCX_E_INVALID_ARG, "async_drain_events must be in [0, 1024]");
     if (o.async_bulk_events < 0 || o.async_bulk_events > 1024)
         return fail(h, MCX_E_INVALID_ARG, "async_bulk_events must be in [0, 1024]");
+    if (o.stack_bulk_events < 0 || o.stack_bulk_events > 1024)
+        return fail(h, MCX_E_INVALID_ARG, "stack_bulk_events must be in [0, 1024]");
     if (o.workspace && ((uintptr_t)o.workspace % 256) != 0)
         return fail(h, MCX_E_INVALID_ARG, "workspace must be 256-byte aligned");
     if (o.workspace && o.ws_bytes == 0) return fail(h, MCX_E_INVALID_ARG, "workspace given with ws_bytes 0");
@@ -876,6 +878,7 @@ static LaunchArgs launch_args(mcx_problem_t h, const mcx_run_opts &o, int mode, 
     a.async_block_waves = o.async_block_waves;
     a.async_drain_events = o.async_drain_events;
     a.async_bulk_events = o.async_bulk_events;
+    a.stack_bulk_events = o.stack_bulk_events;
     a.async_shared = o.async_shared_stash;
     a.ws_query = nullptr;
     a.poll[0] = h->poll[0];

@@ -81,6 +81,7 @@ struct LaunchArgs {
     int async_block_waves;                 // async: wavefronts per block, 1, 2 or 4 (0 = ASYNC_BLOCK_WAVES)
     int async_drain_events;                // async: events per pass on a drained wavefront's partial link (0 = default)
     int async_bulk_events;                 // async fused: events per pass on a full link (0 = default)
+    int stack_bulk_events;                 // stack fused: events per pop while few particles end (0 = default)
     int async_shared;                      // async: 1 = the block's wavefronts share one stash (0, 2: one each)
     size_t *ws_query;                      // non-null: only report the workspace bytes the launch
                                            // needs (nothing is allocated or launched)
@@ -96,14 +97,18 @@ struct LaunchArgs {
 // and changed the rest by a few percent either way.
 constexpr int ASYNC_BLOCK_WAVES = 4;
 constexpr int ASYNC_DRAIN_EVENTS = 8;
-// Fused async events on a full link: its particles run up to
-// ASYNC_BULK_EVENTS events in place, until more than ASYNC_BULK_ENDED of
-// them have ended, before the link is repacked and refilled.  Measured on
-// MI355X at 1e6 histories: the continuous-energy pin cell (670 flights per
-// history, about one lane in ten ends within ten events) 3.5 % faster, the
-// lattice (11 flights per history: a pass rarely goes on) unchanged.
+// Fused events on a full link (async) or a full popped chunk (stack): its
+// particles run up to ASYNC_BULK_EVENTS / STACK_BULK_EVENTS events in place,
+// until more than BULK_ENDED of them have ended, before they are repacked
+// and refilled.  Measured on MI355X at 1e6 histories: the continuous-energy
+// pin cell (670 flights per history, about one lane in ten ends within ten
+// events) 3.5 % faster with async and 15 % with the stack scheme; the
+// multigroup lattice (11 flights per history) unchanged with async and 3 %
+// slower with the stack scheme, whose rounds wait for the chunks that go
+// on, so there the stack default is off for multigroup problems.
 constexpr int ASYNC_BULK_EVENTS = 64;
-constexpr int ASYNC_BULK_ENDED = 4;
+constexpr int STACK_BULK_EVENTS = 64;
+constexpr int BULK_ENDED = 4;
 // Budget of one bounded wait in the asynchronous scheduler (a queue claimed
 // by others, no empty arena link, links in flight): far beyond any transient
 // contention (a queue is held for well under a microsecond), short enough

@@ -60,14 +60,14 @@ constexpr int DONATE_BELOW = 32;   // a drained stash with fewer particles is do
 
 // Whether a link's particles run another event in place (wave-uniform).  A
 // drained wavefront's partial link goes on while any particle lives; a full
-// link (fused events) while at most ASYNC_BULK_ENDED of its particles have
+// link (fused events) while at most BULK_ENDED of its particles have
 // ended, so few slots idle before it is repacked and refilled.  Every
 // history draws from its own keyed streams and the tallies are integer
 // sums, so how many events run in place never changes a result.
 __device__ __forceinline__ bool goes_on(bool drained, bool act, bool live)
 {
     if (drained) return __ballot(live) != 0;
-    return __popcll(__ballot(act && !live)) <= ASYNC_BULK_ENDED;
+    return __popcll(__ballot(act && !live)) <= BULK_ENDED;
 }
 constexpr unsigned long long Q_EMPTY = ~0ull;
 constexpr unsigned long long Q_CLAIMED = 0xFFFFFFFEFFFFFFFEull;

@@ -58,6 +58,7 @@ struct StackArgs {
     int lacc_words;
     int tail_events;            // most events a popped particle runs in place in the tail
     int min_events;             // events a popped particle runs at least
+    int bulk_events;            // fused: most events a popped chunk runs while few of its particles end
     int tl_bytes;               // packed tables copied to LDS (single problem)
     unsigned long long static_share;   // > 0: round 0 sources wavefront w's ids [w s, (w+1) s)
 };
@@ -202,8 +203,12 @@ stack_round(StackArgs A, int round, const ProbDev *__restrict__ probs)
     // min_events (1: remap after every event).  Tail: when the round's input
     // chunks no longer give every wavefront one, remapping cannot fill the
     // device and each round costs a launch plus one event's latency, so K
-    // grows as the population shrinks (up to tail_events).  Every history
-    // draws from its own keyed streams, so results do not change.
+    // grows as the population shrinks (up to tail_events).  Fused events go
+    // on past K, up to bulk_events, while at least 64 - BULK_ENDED of the
+    // chunk's lanes hold live particles: a full chunk has nothing to gain
+    // from being pushed and popped again (a partly filled one would hold the
+    // round for its few particles).  Every history draws from its own keyed
+    // streams, so results do not change.
     int K = A.min_events;
     int cs_log2 = 6;                 // particles per popped chunk: 64, fewer in the tail
     {
@@ -254,8 +259,10 @@ stack_round(StackArgs A, int round, const ProbDev *__restrict__ probs)
                 if (live) ne = run_event_in<GEOM, EMODE, MODE, SPLIT, EXT, BATCH>(cur, probs, tl, cx, ln, p, out);
                 wc.dispatch(live);
                 wc.outcomes(live, out);
-                if (++i >= K) break;
+                ++i;
                 live = live && ne != EV_DEAD;
+                if (i >= K && (SPLIT || i >= A.bulk_events || __popcll(__ballot(live)) < 64 - BULK_ENDED))
+                    break;
                 if (__ballot(live) == 0) break;
                 cur = ne;
             }
@@ -389,6 +396,7 @@ static hipError_t stack_t(const LaunchArgs &a, Workspace &ws, LaunchStats &st, L
     A.lacc_words = a.lacc_words;
     A.tail_events = a.stack_tail_events > 0 ? a.stack_tail_events : STACK_TAIL_EVENTS;
     A.min_events = a.stack_min_events > 0 ? a.stack_min_events : 1;
+    A.bulk_events = a.stack_bulk_events > 0 ? a.stack_bulk_events : (a.emode == EMODE_CE ? STACK_BULK_EVENTS : 1);
     A.tl_bytes = BATCH ? 0 : a.tl_bytes;
     // every history fits and the threshold would not stop the source: round 0
     // sources them all, each wavefront its own share (a multiple of 64)

@@ -66,7 +66,7 @@ class RunOpts(C.Structure):
         ("stack_tail_events", C.c_int32), ("stack_min_events", C.c_int32), ("tally_path", C.c_int32),
         ("async_block_waves", C.c_int32), ("async_drain_events", C.c_int32),
         ("async_shared_stash", C.c_int32), ("workspace", C.c_void_p), ("ws_bytes", C.c_size_t),
-        ("async_bulk_events", C.c_int32),
+        ("async_bulk_events", C.c_int32), ("stack_bulk_events", C.c_int32),
     ]
 
 
@@ -235,7 +235,8 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
              stack_threshold=0, stash_links=0, arena_links=0, waves_per_cu=0, block_size=0, stream=None,
              digest=None, time_kernels=False, force_spill=0, consolidate=0, stack_tail_events=0,
              stack_min_events=0, tally_path="auto", async_block_waves=0,
-             async_drain_events=0, workspace=None, async_shared_stash=0, async_bulk_events=0) -> RunOpts:
+             async_drain_events=0, workspace=None, async_shared_stash=0, async_bulk_events=0,
+             stack_bulk_events=0) -> RunOpts:
     o = RunOpts()
     o.sched = SCHED[sched] if isinstance(sched, str) else int(sched)
     o.decomp = DECOMP[decomp] if isinstance(decomp, str) else int(decomp)
@@ -259,6 +260,7 @@ def run_opts(sched="async", decomp="fused", lookup="binary", accumulate=False, f
     o.async_block_waves = int(async_block_waves)
     o.async_drain_events = int(async_drain_events)
     o.async_bulk_events = int(async_bulk_events)
+    o.stack_bulk_events = int(stack_bulk_events)
     # async stash shared by a block's wavefronts: True/1 on, False/2 off, 0 default
     o.async_shared_stash = {True: 1, False: 2}.get(async_shared_stash, async_shared_stash) \
         if isinstance(async_shared_stash, bool) else int(async_shared_stash)

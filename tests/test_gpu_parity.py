@@ -482,6 +482,59 @@ def test_async_bulk_events(mcx, oracle, cfg1, cfg2, k):
         B.run(sched="async", async_bulk_events=1025)
 
 
+@pytest.mark.parametrize("k", [1, 2, 64])
+def test_stack_bulk_events(mcx, oracle, cfg1, cfg2, k):
+    # a full popped chunk of fused events goes on past its events per pop
+    # while at least 60 of its lanes hold live particles: same integers, digests and
+    # counters (with several events per pop, a small threshold, backward
+    # passes, implicit capture with time bins, continuous energy, a batch,
+    # eigenvalue cycles)
+    for d, ref in (cfg1, cfg2):
+        P = mcx.Problem(d)
+        dg = _digest(mcx, d["n_histories"])
+        P.run(sched="stack", stack_bulk_events=k, digest=dg)
+        assert np.array_equal(P.tallies(), ref["tally"])
+        _check_counts(P.counters(), ref["counts"])
+        assert np.array_equal(_digest_np(dg, mcx), ref["digest"])
+        P.run(sched="stack", stack_bulk_events=k, stack_min_events=3, stack_threshold=512)
+        assert np.array_equal(P.tallies(), ref["tally"]), "min events, threshold"
+        _check_counts(P.counters(), ref["counts"])
+    d = inputs.lattice_mg(n_histories=3000)
+    w = np.random.default_rng(5).normal(size=inputs.n_bins(d))
+    refb = oracle.backward(d, w)
+    R = mcx.Problem(d)
+    R.run(sched="stack", stack_bulk_events=k)
+    gt, gs = R.backward(w, sched="stack", stack_bulk_events=k)
+    assert np.array_equal(gt, refb["grad_sigma_t"]) and np.array_equal(gs, refb["grad_sigma_s"])
+    dw = inputs.with_time_bins(inputs.with_implicit_capture(inputs.cfg2_lattice(4000)), 8, 60.0)
+    refw = oracle.run(dw)
+    W = mcx.Problem(dw)
+    W.run(sched="stack", stack_bulk_events=k)
+    assert np.array_equal(W.tallies(), refw["tally"])
+    _check_counts(W.counters(), refw["counts"])
+    dc = inputs.pincell_ce(n_ebins=100, n_histories=1500)
+    refc = oracle.run(dc)
+    C = mcx.Problem(dc)
+    C.run(sched="stack", stack_bulk_events=k)
+    assert np.array_equal(C.tallies(), refc["tally"])
+    _check_counts(C.counters(), refc["counts"])
+    probs = inputs.cfg5_batch(n_problems=10, hist_scale=0.02)
+    B = mcx.Problem(probs)
+    B.run(sched="stack", stack_bulk_events=k)
+    for j, pd in enumerate(probs):
+        assert np.array_equal(B.tallies(j), oracle.run(pd)["tally"]), j
+    dk = inputs.with_fission(inputs.cfg2_lattice(1))
+    refk = oracle.eigen(dk, 5000, 4, 1)
+    K = mcx.Problem(dk)
+    got = K.run_eigen(5000, 4, 1, sched="stack", stack_bulk_events=k)
+    assert np.array_equal(K.tallies(), refk["tally"])
+    assert np.array_equal(got["k"], refk["k"])
+    with pytest.raises(mcx.McxError):
+        B.run(sched="stack", stack_bulk_events=-1)
+    with pytest.raises(mcx.McxError):
+        B.run(sched="stack", stack_bulk_events=1025)
+
+
 def test_async_default_shape(mcx, cfg2):
     # default launch shape: four wavefronts per block, or two with the
     # smallest stash when that keeps more resident (split events on the
